@@ -1,0 +1,165 @@
+/*
+ * plprof -- profile log-likelihoods of Box-Cox transformed Gaussian
+ * geostatistical models with anisotropic Matern correlation, on one
+ * MI355X (gfx950) GPU.
+ *
+ * C ABI.  All entry points return 0 (PL_OK) on success, -i when argument i
+ * (1-based) is invalid (LAPACK convention), or a positive PL_E_* code for a
+ * runtime failure.  Every device-side call is asynchronous on the HIP stream
+ * passed in `stream` (a hipStream_t; NULL means the default stream); results
+ * are valid once the caller has synchronised that stream.
+ *
+ * Ownership: the caller allocates and owns every device buffer, including the
+ * workspace sized by the matching *_workspace_size call.  The library keeps
+ * no device state between calls.  Host arrays (omega, lambda, options) are
+ * read during the call only.
+ *
+ * Notation and definitions (Xu & Brown, "Profile likelihoods for parameters
+ * in trans-Gaussian geostatistical models"):
+ *   omega = (phi_X range, kappa shape, nu^2 nugget, phi_R ratio, phi_A angle),
+ *   phi_Y = phi_X / phi_R, Section 2.1 and the parameter tables of Sections 6-7;
+ *   rho(x) = 2^(1-kappa)/Gamma(kappa) (sqrt(8 kappa) d)^kappa K_kappa(sqrt(8 kappa) d),
+ *   d(x) = || diag(1/phi_X, 1/phi_Y) Rot(phi_A) x ||, Section 2.1 (the printed
+ *   constant 2^(kappa-1) is read as 2^(1-kappa), the value with rho(0) = 1);
+ *   V = R(omega) + nu^2 I, equation (1);
+ *   Box-Cox y' = (y^lambda - 1)/lambda, log y at lambda = 0, Section 2;
+ *   profile log-likelihood l_p(omega, lambda), equation "profile" (returned as
+ *   l_p itself, not -2 l_p), with the statistics of Table "tab:tocpu".
+ */
+#ifndef PLPROF_H
+#define PLPROF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* precision modes */
+#define PL_FP64  0      /* every step in FP64                                  */
+#define PL_MIXED 1      /* FP32 trailing updates / solves on MFMA, FP64 diagonal
+                           tiles, log-determinant, p x p stage and residual,
+                           one FP64 iterative-refinement step                   */
+
+/* runtime error codes (positive returns) */
+#define PL_OK            0
+#define PL_E_HIP         1   /* a HIP runtime call failed                       */
+#define PL_E_WORKSPACE   2   /* workspace too small for even one omega          */
+#define PL_E_UNSUPPORTED 3   /* size outside the compiled limits                */
+
+/* per-record info codes */
+#define PL_INFO_RANK     (-1)        /* X^T V^-1 X not positive definite        */
+#define PL_INFO_BAD_Y    (-2)        /* some y_i <= 0 or not finite             */
+#define PL_INFO_FALLBACK (1 << 30)   /* mixed form: point redone in FP64        */
+
+/* compiled limits */
+#define PL_MAX_P      32     /* covariates                                      */
+#define PL_MAX_M      64     /* Box-Cox values per call                         */
+#define PL_MIN_SHAPE  0.05
+#define PL_MAX_SHAPE  100.0
+
+/* One record per (omega_k, lambda_m), stored at index k*M + m (80 bytes). */
+typedef struct pl_result {
+  double loglik;        /* l_p(omega, lambda), equation "profile"               */
+  double logdet_v;      /* log|V| (detVar)                                      */
+  double logdet_xvx;    /* log|X^T V^-1 X| (detReml)                             */
+  double ssq_y;         /* y'^T V^-1 y'                                         */
+  double ssq_betahat;   /* (X b)^T V^-1 (X b) (ssqBetahat)                        */
+  double ssq_resid;     /* (y' - X b)^T V^-1 (y' - X b) (ssqResidual)            */
+  double sigma2_hat;    /* ssq_resid / n                                        */
+  double jacobian;      /* sum_i log y_i                                         */
+  double loglik_reml;   /* restricted profile log-likelihood, Appendix "remlpro" */
+  int32_t info;         /* 0; j > 0: first non-positive pivot of V (column j,
+                           1-based), loglik = -inf; PL_INFO_RANK; PL_INFO_BAD_Y
+                           (loglik = NaN); PL_INFO_FALLBACK may be or-ed in      */
+  int32_t pad;
+} pl_result;
+
+typedef struct pl_opts {
+  int32_t precision;    /* PL_FP64 (default) or PL_MIXED                         */
+  int32_t refine;       /* PL_MIXED: refinement steps, default 1                 */
+  int64_t chunk;        /* max omega per device pass; 0 = as many as fit          */
+  int32_t reserved[4];
+} pl_opts;
+
+/* Library version string. */
+const char* pl_version(void);
+
+/* Human-readable text for a return code. */
+const char* pl_error_string(int code);
+
+/*
+ * Workspace for pl_profile_loglik.  `bytes` receives the size that holds all
+ * K points in one device pass; any workspace of at least the one-point size
+ * (K = 1) is accepted, and the call then runs in chunks.
+ * Errors: -1 n < 2, -2 p < 1 or p >= n or p > PL_MAX_P, -3 K < 1,
+ * -4 M < 1 or M > PL_MAX_M, -6 bytes NULL.
+ */
+int pl_workspace_size(int64_t n, int64_t p, int64_t K, int64_t M,
+                      const pl_opts* opts, size_t* bytes);
+
+/*
+ * Matern correlation-plus-nugget matrices V_k = R(omega_k) + nu_k^2 I
+ * (Section 2.1, equation (1); Step 1 of Section 3.3).
+ *   locs   device, n x 2 row-major (x_i, y_i)
+ *   omega  host, K x 5 row-major natural parameters
+ *   V      device, K matrices, each n x n column-major with leading dimension
+ *          ld >= n; matrix k starts at V + k*ld*n.  The lower triangle and the
+ *          diagonal are written; the strict upper triangle is not touched.
+ *   work   device workspace of pl_matern_workspace_size(K) bytes.
+ * Errors: -1 locs NULL, -2 n < 1, -3 omega NULL or a parameter out of domain
+ * (range <= 0, shape outside [PL_MIN_SHAPE, PL_MAX_SHAPE], nugget < 0,
+ * ratio <= 0, any value not finite), -4 K < 1, -5 V NULL, -6 ld < n,
+ * -7/-8 workspace NULL or too small.
+ */
+int pl_matern_workspace_size(int64_t K, size_t* bytes);
+int pl_matern_cov(const double* locs, int64_t n, const double* omega, int64_t K,
+                  double* V, int64_t ld, void* work, size_t work_bytes, void* stream);
+
+/*
+ * In-place batched Cholesky V_k = L_k L_k^T (Step 2 of Section 3.3; the paper
+ * factors L D L^T, whose determinant is the same) with
+ * logdet[k] = log|V_k| = 2 sum_i log L_k,ii.
+ *   V      device, K matrices, n x n column-major, leading dimension ld,
+ *          matrix k at V + k*ld*n; the lower triangle is read and overwritten
+ *          by L, the strict upper triangle is not referenced.
+ *   logdet device, K doubles.  info device, K int32: 0, or j > 0 when the
+ *          leading minor of order j is not positive definite (that matrix is
+ *          left partly factored and logdet[k] is not meaningful).
+ *   work   device workspace of pl_chol_workspace_size(K) bytes.
+ * Errors: -1 V NULL, -2 n < 1, -3 K < 1, -4 ld < n, -5 logdet NULL,
+ * -6 info NULL, -7/-8 workspace NULL or too small.
+ */
+int pl_chol_workspace_size(int64_t K, size_t* bytes);
+int pl_chol_batched(double* V, int64_t n, int64_t K, int64_t ld, double* logdet,
+                    int32_t* info, void* work, size_t work_bytes, void* stream);
+
+/*
+ * Profile log-likelihood at every (omega_k, lambda_m) (Section 3.3, Steps 1-8;
+ * equations "betahat", (4) and "profile"; Appendix "remlpro").
+ *   locs     device, n x 2 row-major        y  device, n (must be > 0)
+ *   X        device, n x p column-major (column j at X + j*n)
+ *   omega    host, K x 5                      lambda host, M
+ *   out      device, K*M pl_result records, record k*M + m
+ *   beta_hat device, K*M*p doubles (GLS estimate for record k*M+m at
+ *            beta_hat + (k*M+m)*p), or NULL
+ *   opts     NULL for defaults
+ *   work     device workspace, see pl_workspace_size
+ * Errors: -1 locs, -2 y, -3 X NULL; -4 n < 2; -5 p < 1, p >= n or p > PL_MAX_P;
+ * -6 omega NULL or out of domain (as pl_matern_cov); -7 K < 1;
+ * -8 lambda NULL or not finite; -9 M < 1 or M > PL_MAX_M; -10 out NULL;
+ * -12 bad option; -13/-14 workspace NULL or too small.
+ * y <= 0 is detected on the device: every record then carries PL_INFO_BAD_Y.
+ */
+int pl_profile_loglik(const double* locs, const double* y, const double* X,
+                      int64_t n, int64_t p, const double* omega, int64_t K,
+                      const double* lambda, int64_t M, pl_result* out,
+                      double* beta_hat, const pl_opts* opts, void* work,
+                      size_t work_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PLPROF_H */

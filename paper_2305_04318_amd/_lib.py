@@ -1,0 +1,78 @@
+"""ctypes binding of the plprof C ABI (include/plprof.h).  Argument
+marshalling only; every step runs in the HIP library."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libplprof.so")
+
+PL_FP64, PL_MIXED = 0, 1
+PL_INFO_RANK, PL_INFO_BAD_Y, PL_INFO_FALLBACK = -1, -2, 1 << 30
+PL_MAX_P, PL_MAX_M = 32, 64
+
+# every symbol the header declares
+EXPORTS = ("pl_version", "pl_error_string", "pl_workspace_size", "pl_matern_workspace_size",
+           "pl_matern_cov", "pl_chol_workspace_size", "pl_chol_batched", "pl_profile_loglik")
+
+
+class PlResult(ctypes.Structure):
+    _fields_ = [("loglik", ctypes.c_double), ("logdet_v", ctypes.c_double),
+                ("logdet_xvx", ctypes.c_double), ("ssq_y", ctypes.c_double),
+                ("ssq_betahat", ctypes.c_double), ("ssq_resid", ctypes.c_double),
+                ("sigma2_hat", ctypes.c_double), ("jacobian", ctypes.c_double),
+                ("loglik_reml", ctypes.c_double), ("info", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+
+class PlOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("refine", ctypes.c_int32),
+                ("chunk", ctypes.c_int64), ("reserved", ctypes.c_int32 * 4)]
+
+
+class PlError(RuntimeError):
+    pass
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_SZ = ctypes.c_size_t
+
+
+def load(path: str = None):
+    """Load the shared library; raises if it has not been built."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise PlError(f"plprof HIP library not found at {p}; run __graft_entry__.build()")
+    lib = ctypes.CDLL(p)
+    lib.pl_version.restype = ctypes.c_char_p
+    lib.pl_version.argtypes = []
+    lib.pl_error_string.restype = ctypes.c_char_p
+    lib.pl_error_string.argtypes = [ctypes.c_int]
+    lib.pl_workspace_size.restype = ctypes.c_int
+    lib.pl_workspace_size.argtypes = [_I64, _I64, _I64, _I64, ctypes.POINTER(PlOpts),
+                                      ctypes.POINTER(_SZ)]
+    lib.pl_matern_workspace_size.restype = ctypes.c_int
+    lib.pl_matern_workspace_size.argtypes = [_I64, ctypes.POINTER(_SZ)]
+    lib.pl_matern_cov.restype = ctypes.c_int
+    lib.pl_matern_cov.argtypes = [_P, _I64, _P, _I64, _P, _I64, _P, _SZ, _P]
+    lib.pl_chol_workspace_size.restype = ctypes.c_int
+    lib.pl_chol_workspace_size.argtypes = [_I64, ctypes.POINTER(_SZ)]
+    lib.pl_chol_batched.restype = ctypes.c_int
+    lib.pl_chol_batched.argtypes = [_P, _I64, _I64, _I64, _P, _P, _P, _SZ, _P]
+    lib.pl_profile_loglik.restype = ctypes.c_int
+    lib.pl_profile_loglik.argtypes = [_P, _P, _P, _I64, _I64, _P, _I64, _P, _I64, _P, _P,
+                                      ctypes.POINTER(PlOpts), _P, _SZ, _P]
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def check(rc: int, what: str):
+    if rc != 0:
+        msg = load().pl_error_string(rc).decode()
+        raise PlError(f"{what} returned {rc} ({msg})")

@@ -1,0 +1,146 @@
+"""Python entry points with the C ABI's names.  PyTorch provides device
+memory and the stream; all arithmetic happens in the HIP library."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import PlOpts, check, load
+
+RESULT_FIELDS = ("loglik", "logdet_v", "logdet_xvx", "ssq_y", "ssq_betahat",
+                 "ssq_resid", "sigma2_hat", "jacobian", "loglik_reml")
+_PREC = {"fp64": _lib.PL_FP64, "mixed": _lib.PL_MIXED}
+
+
+def _stream_ptr(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_f64(t, device, shape=None):
+    t = torch.as_tensor(t, dtype=torch.float64, device=device)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
+    return t.contiguous()
+
+
+def _host_f64(a, ncol=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if ncol is not None:
+        a = a.reshape(-1, ncol)
+    return a
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _opts(precision="fp64", chunk=0, refine=1):
+    o = PlOpts()
+    o.precision = _PREC[precision]
+    o.refine = refine
+    o.chunk = int(chunk or 0)
+    return o
+
+
+def version() -> str:
+    return load().pl_version().decode()
+
+
+def workspace_size(n, p, K, M, precision="fp64", chunk=0) -> int:
+    lib = load()
+    out = ctypes.c_size_t(0)
+    o = _opts(precision, chunk)
+    check(lib.pl_workspace_size(n, p, K, M, ctypes.byref(o), ctypes.byref(out)), "pl_workspace_size")
+    return int(out.value)
+
+
+def matern_cov(locs, omega, device="cuda", ld=None, stream=None):
+    """V_k = R(omega_k) + nu_k^2 I, lower triangle, as a (K, n, ld) tensor whose
+    row k*... is column-major per matrix (V[k].T[:n, :n] is the matrix)."""
+    lib = load()
+    locs_d = _dev_f64(locs, device)
+    n = locs_d.shape[0]
+    om = _host_f64(omega, 5)
+    K = om.shape[0]
+    ld = ld or n
+    V = torch.zeros((K, n, ld), dtype=torch.float64, device=device)
+    wb = ctypes.c_size_t(0)
+    check(lib.pl_matern_workspace_size(K, ctypes.byref(wb)), "pl_matern_workspace_size")
+    work = torch.empty(max(1, wb.value), dtype=torch.uint8, device=device)
+    rc = lib.pl_matern_cov(_ptr(locs_d), n, om.ctypes.data_as(ctypes.c_void_p), K, _ptr(V), ld,
+                           _ptr(work), wb.value, _stream_ptr(stream))
+    check(rc, "pl_matern_cov")
+    return V
+
+
+def chol_batched(V, n=None, stream=None):
+    """In-place Cholesky of V (K, n, ld) column-major matrices; returns (logdet, info)."""
+    lib = load()
+    K, n_, ld = V.shape
+    n = n or n_
+    logdet = torch.empty(K, dtype=torch.float64, device=V.device)
+    info = torch.empty(K, dtype=torch.int32, device=V.device)
+    wb = ctypes.c_size_t(0)
+    check(lib.pl_chol_workspace_size(K, ctypes.byref(wb)), "pl_chol_workspace_size")
+    work = torch.empty(max(1, wb.value), dtype=torch.uint8, device=V.device)
+    rc = lib.pl_chol_batched(_ptr(V), n, K, ld, _ptr(logdet), _ptr(info), _ptr(work), wb.value,
+                             _stream_ptr(stream))
+    check(rc, "pl_chol_batched")
+    return logdet, info
+
+
+def unpack_records(rec: torch.Tensor) -> dict:
+    """(K, M, 10) float64 record tensor -> dict of (K, M) tensors."""
+    out = {f: rec[..., i] for i, f in enumerate(RESULT_FIELDS)}
+    out["info"] = rec.view(torch.int32)[..., 18]
+    return out
+
+
+class Inputs:
+    """Device-resident copy of one dataset (locs, y, X in column-major)."""
+
+    def __init__(self, locs, y, X, device="cuda"):
+        self.locs = _dev_f64(locs, device)
+        self.n = self.locs.shape[0]
+        self.y = _dev_f64(y, device, (self.n,))
+        Xt = torch.as_tensor(X, dtype=torch.float64)
+        if Xt.dim() == 1:
+            Xt = Xt[:, None]
+        self.p = Xt.shape[1]
+        # column-major n x p: columns contiguous
+        self.Xc = Xt.to(device).t().contiguous()
+        self.device = device
+
+
+def profile_loglik(locs, y, X, omega, lam, precision="fp64", chunk=0, return_beta=False,
+                   out=None, beta=None, work=None, stream=None, device="cuda", inputs=None):
+    """Records for every (omega_k, lambda_m): dict of (K, M) tensors on the
+    device, plus "beta" (K, M, p) when return_beta."""
+    lib = load()
+    inp = inputs if inputs is not None else Inputs(locs, y, X, device)
+    om = _host_f64(omega, 5)
+    lm = _host_f64(lam).reshape(-1)
+    K, M = om.shape[0], lm.shape[0]
+    dev = inp.device
+    if out is None:
+        out = torch.empty((K, M, 10), dtype=torch.float64, device=dev)
+    if return_beta and beta is None:
+        beta = torch.empty((K, M, inp.p), dtype=torch.float64, device=dev)
+    o = _opts(precision, chunk)
+    if work is None:
+        work = torch.empty(workspace_size(inp.n, inp.p, K, M, precision, chunk),
+                           dtype=torch.uint8, device=dev)
+    rc = lib.pl_profile_loglik(_ptr(inp.locs), _ptr(inp.y), _ptr(inp.Xc), inp.n, inp.p,
+                               om.ctypes.data_as(ctypes.c_void_p), K,
+                               lm.ctypes.data_as(ctypes.c_void_p), M, _ptr(out),
+                               _ptr(beta) if return_beta else None, ctypes.byref(o),
+                               _ptr(work), work.numel(), _stream_ptr(stream))
+    check(rc, "pl_profile_loglik")
+    res = unpack_records(out)
+    if return_beta:
+        res["beta"] = beta
+    return res

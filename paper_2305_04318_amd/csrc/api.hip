@@ -1,0 +1,291 @@
+// C-ABI entry points: argument checks, per-omega constants, workspace
+// carving and the kernel sequence of Step 3 (Section 3.3).
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+
+using namespace plk;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Carve {
+  char* base;
+  size_t off = 0;
+  template <class P>
+  P* take(size_t bytes) {
+    P* p = reinterpret_cast<P*>(base + off);
+    off += align_up(bytes);
+    return p;
+  }
+};
+
+bool omega_ok(const double* om) {
+  for (int i = 0; i < 5; ++i)
+    if (!std::isfinite(om[i])) return false;
+  return om[0] > 0.0 && om[1] >= PL_MIN_SHAPE && om[1] <= PL_MAX_SHAPE && om[2] >= 0.0 &&
+         om[3] > 0.0;
+}
+
+// Constants for one omega = (phi_X, kappa, nu^2, phi_R, phi_A); phi_Y = phi_X / phi_R.
+MaternParams make_params(const double* om) {
+  MaternParams P{};
+  const double phix = om[0], kappa = om[1], nug = om[2], ratio = om[3], ang = om[4];
+  P.inv_phix = 1.0 / phix;
+  P.inv_phiy = ratio / phix;
+  P.cosA = cos(ang);
+  P.sinA = sin(ang);
+  P.sqrt8k = sqrt(8.0 * kappa);
+  P.nugget = nug;
+  P.kappa = kappa;
+  P.log_norm = (1.0 - kappa) * M_LN2 - lgamma(kappa);
+  // x_hi: beyond it rho < exp(-745) (below the smallest double).  From the
+  // large-argument form log rho ~ log_norm + 0.5 log(pi/2) + (kappa-1/2) log x - x,
+  // solved by fixed-point iteration, then widened for the neglected terms.
+  const double C = P.log_norm + 0.5 * log(M_PI / 2.0) + 760.0;
+  double x = std::max(C, 10.0);
+  for (int i = 0; i < 60; ++i) x = std::max(10.0, C + (kappa - 0.5) * log(x));
+  P.x_hi = 1.1 * x + 50.0;
+  P.u_a = log(X_LO);
+  P.inv_w = NP / (log(P.x_hi) - P.u_a);
+  return P;
+}
+
+Lay packed_layout(int64_t n, int64_t q) {
+  Lay lay{};
+  lay.kind = 0;
+  lay.n = (int)n;
+  lay.Nv = (int)((n + T - 1) / T);
+  lay.q = (int)q;
+  lay.TB = (int)((q + 15) / 16 * 16);
+  lay.mstride = packed_stride(lay.Nv, lay.TB);
+  return lay;
+}
+
+size_t per_omega_bytes(const Lay& lay) {
+  return align_up(lay.mstride * sizeof(double)) + align_up((size_t)T * T * sizeof(double)) +
+         2 * ALIGN;
+}
+
+size_t fixed_bytes(int64_t n, int64_t K, int64_t M, const Lay& lay) {
+  size_t b = 0;
+  b += align_up(K * sizeof(MaternParams));
+  b += 2 * align_up((size_t)K * NP * NC * sizeof(double));
+  b += align_up(M * sizeof(double));
+  b += align_up((size_t)n * lay.TB * sizeof(double));
+  b += align_up(sizeof(double)) + align_up(sizeof(int32_t));
+  return b;
+}
+
+// Host buffer kept alive until the stream has consumed the copy from it.
+void copy_h2d_async(void* dst, const void* src, size_t bytes, hipStream_t s, hipError_t* err) {
+  char* hold = new char[bytes];
+  memcpy(hold, src, bytes);
+  hipError_t e = hipMemcpyAsync(dst, hold, bytes, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) {
+    delete[] hold;
+    *err = e;
+    return;
+  }
+  e = hipLaunchHostFunc(s, [](void* p) { delete[] static_cast<char*>(p); }, hold);
+  if (e != hipSuccess) *err = e;
+}
+
+#define PL_CHECK(call)                        \
+  do {                                        \
+    hipError_t _e = (call);                   \
+    if (_e != hipSuccess) return PL_E_HIP;    \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char* pl_version(void) { return "plprof 0.1 (gfx950)"; }
+
+const char* pl_error_string(int code) {
+  if (code == PL_OK) return "ok";
+  if (code < 0) return "invalid argument";
+  switch (code) {
+    case PL_E_HIP: return "HIP runtime error";
+    case PL_E_WORKSPACE: return "workspace too small";
+    case PL_E_UNSUPPORTED: return "unsupported size";
+    default: return "unknown error";
+  }
+}
+
+int pl_matern_workspace_size(int64_t K, size_t* bytes) {
+  if (K < 1) return -1;
+  if (!bytes) return -2;
+  *bytes = align_up(K * sizeof(MaternParams)) + 2 * align_up((size_t)K * NP * NC * sizeof(double));
+  return PL_OK;
+}
+
+int pl_matern_cov(const double* locs, int64_t n, const double* omega, int64_t K, double* V,
+                  int64_t ld, void* work, size_t work_bytes, void* stream) {
+  if (!locs) return -1;
+  if (n < 1 || n > (1 << 30)) return -2;
+  if (!omega) return -3;
+  if (K < 1 || K > (1 << 24)) return -4;
+  for (int64_t k = 0; k < K; ++k)
+    if (!omega_ok(omega + 5 * k)) return -3;
+  if (!V) return -5;
+  if (ld < n) return -6;
+  if (!work) return -7;
+  size_t need = 0;
+  pl_matern_workspace_size(K, &need);
+  if (work_bytes < need) return -8;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<MaternParams> hp(K);
+  for (int64_t k = 0; k < K; ++k) hp[k] = make_params(omega + 5 * k);
+  Carve cv{(char*)work};
+  MaternParams* mp = cv.take<MaternParams>(K * sizeof(MaternParams));
+  double* nodes = cv.take<double>((size_t)K * NP * NC * sizeof(double));
+  double* tables = cv.take<double>((size_t)K * NP * NC * sizeof(double));
+  hipError_t err = hipSuccess;
+  copy_h2d_async(mp, hp.data(), K * sizeof(MaternParams), s, &err);
+  if (err != hipSuccess) return PL_E_HIP;
+  PL_CHECK(launch_cheb_tables(mp, nodes, tables, (int)K, s));
+  PL_CHECK(launch_matern_colmajor(V, ld, (int)n, locs, mp, tables, (int)K, s));
+  return PL_OK;
+}
+
+int pl_chol_workspace_size(int64_t K, size_t* bytes) {
+  if (K < 1) return -1;
+  if (!bytes) return -2;
+  *bytes = align_up((size_t)K * T * T * sizeof(double));
+  return PL_OK;
+}
+
+int pl_chol_batched(double* V, int64_t n, int64_t K, int64_t ld, double* logdet, int32_t* info,
+                    void* work, size_t work_bytes, void* stream) {
+  if (!V) return -1;
+  if (n < 1 || n > (1 << 30)) return -2;
+  if (K < 1 || K > (1 << 24)) return -3;
+  if (ld < n) return -4;
+  if (!logdet) return -5;
+  if (!info) return -6;
+  if (!work) return -7;
+  size_t need = 0;
+  pl_chol_workspace_size(K, &need);
+  if (work_bytes < need) return -8;
+  hipStream_t s = (hipStream_t)stream;
+  Lay lay{};
+  lay.kind = 1;
+  lay.n = (int)n;
+  lay.Nv = (int)((n + T - 1) / T);
+  lay.ld = ld;
+  lay.mstride = ld * n;
+  double* W = (double*)work;
+  PL_CHECK(launch_fill(logdet, 0.0, K, s));
+  PL_CHECK(launch_fill_i32(info, 0, K, s));
+  for (int J = 0; J < lay.Nv; ++J) {
+    if (J > 0) PL_CHECK(launch_gemm_col(lay, V, info, J, lay.Nv - J, (int)K, s));
+    PL_CHECK(launch_potrf(lay, V, W, logdet, info, J, (int)K, s));
+    if (lay.Nv - J - 1 > 0) PL_CHECK(launch_trsm(lay, V, W, info, J, lay.Nv - J - 1, (int)K, s));
+  }
+  return PL_OK;
+}
+
+int pl_workspace_size(int64_t n, int64_t p, int64_t K, int64_t M, const pl_opts* opts,
+                      size_t* bytes) {
+  if (n < 2 || n > (1 << 30)) return -1;
+  if (p < 1 || p >= n || p > PL_MAX_P) return -2;
+  if (K < 1 || K > (1 << 24)) return -3;
+  if (M < 1 || M > PL_MAX_M) return -4;
+  if (!bytes) return -6;
+  if (opts && opts->precision != PL_FP64 && opts->precision != PL_MIXED) return -5;
+  const Lay lay = packed_layout(n, M + p);
+  int64_t kc = K;
+  if (opts && opts->chunk > 0) kc = std::min<int64_t>(kc, opts->chunk);
+  *bytes = fixed_bytes(n, K, M, lay) + (size_t)kc * per_omega_bytes(lay);
+  return PL_OK;
+}
+
+int pl_profile_loglik(const double* locs, const double* y, const double* X, int64_t n, int64_t p,
+                      const double* omega, int64_t K, const double* lambda, int64_t M,
+                      pl_result* out, double* beta_hat, const pl_opts* opts, void* work,
+                      size_t work_bytes, void* stream) {
+  if (!locs) return -1;
+  if (!y) return -2;
+  if (!X) return -3;
+  if (n < 2 || n > (1 << 30)) return -4;
+  if (p < 1 || p >= n || p > PL_MAX_P) return -5;
+  if (!omega) return -6;
+  if (K < 1 || K > (1 << 24)) return -7;
+  for (int64_t k = 0; k < K; ++k)
+    if (!omega_ok(omega + 5 * k)) return -6;
+  if (!lambda) return -8;
+  for (int64_t m = 0; m < M && m < PL_MAX_M; ++m)
+    if (!std::isfinite(lambda[m])) return -8;
+  if (M < 1 || M > PL_MAX_M) return -9;
+  if (!out) return -10;
+  int precision = PL_FP64;
+  int64_t chunk = 0;
+  if (opts) {
+    precision = opts->precision;
+    chunk = opts->chunk;
+    if (precision != PL_FP64 && precision != PL_MIXED) return -12;
+    if (chunk < 0) return -12;
+  }
+  if (precision != PL_FP64) return PL_E_UNSUPPORTED;
+  if (!work) return -13;
+  hipStream_t s = (hipStream_t)stream;
+
+  const Lay lay = packed_layout(n, M + p);
+  const size_t fixed = fixed_bytes(n, K, M, lay);
+  const size_t per = per_omega_bytes(lay);
+  if (work_bytes < fixed + per) return -14;
+  int64_t kc = (int64_t)((work_bytes - fixed) / per);
+  kc = std::min<int64_t>(kc, K);
+  if (chunk > 0) kc = std::min<int64_t>(kc, chunk);
+
+  Carve cv{(char*)work};
+  MaternParams* mp = cv.take<MaternParams>(K * sizeof(MaternParams));
+  double* nodes = cv.take<double>((size_t)K * NP * NC * sizeof(double));
+  double* tables = cv.take<double>((size_t)K * NP * NC * sizeof(double));
+  double* lam_d = cv.take<double>(M * sizeof(double));
+  double* rhs = cv.take<double>((size_t)n * lay.TB * sizeof(double));
+  double* jac = cv.take<double>(sizeof(double));
+  int32_t* flags = cv.take<int32_t>(sizeof(int32_t));
+  double* mats = cv.take<double>((size_t)kc * lay.mstride * sizeof(double));
+  double* W = cv.take<double>((size_t)kc * T * T * sizeof(double));
+  double* logdet = cv.take<double>((size_t)kc * sizeof(double));
+  int32_t* info = cv.take<int32_t>((size_t)kc * sizeof(int32_t));
+
+  std::vector<MaternParams> hp(K);
+  for (int64_t k = 0; k < K; ++k) hp[k] = make_params(omega + 5 * k);
+  hipError_t err = hipSuccess;
+  copy_h2d_async(mp, hp.data(), K * sizeof(MaternParams), s, &err);
+  copy_h2d_async(lam_d, lambda, M * sizeof(double), s, &err);
+  if (err != hipSuccess) return PL_E_HIP;
+
+  PL_CHECK(launch_cheb_tables(mp, nodes, tables, (int)K, s));
+  PL_CHECK(launch_boxcox_rhs(y, X, lam_d, (int)n, (int)p, (int)M, rhs, jac, flags, s));
+
+  for (int64_t c0 = 0; c0 < K; c0 += kc) {
+    const int kk = (int)std::min<int64_t>(kc, K - c0);
+    PL_CHECK(launch_border_init(lay, mats, rhs, kk, s));
+    PL_CHECK(launch_matern_packed(lay, mats, locs, mp + c0, tables + c0 * NP * NC, kk, s));
+    PL_CHECK(launch_fill(logdet, 0.0, kk, s));
+    PL_CHECK(launch_fill_i32(info, 0, kk, s));
+    for (int J = 0; J <= lay.Nv; ++J) {
+      if (J > 0) PL_CHECK(launch_gemm_col(lay, mats, info, J, lay.Nv - J + 1, kk, s));
+      if (J < lay.Nv) {
+        PL_CHECK(launch_potrf(lay, mats, W, logdet, info, J, kk, s));
+        PL_CHECK(launch_trsm(lay, mats, W, info, J, lay.Nv - J, kk, s));
+      }
+    }
+    PL_CHECK(launch_finalize(lay, mats, logdet, info, jac, flags, lam_d, (int)n, (int)p, (int)M,
+                             kk, out + c0 * M, beta_hat ? beta_hat + c0 * M * p : nullptr, s));
+  }
+  return PL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// Internal declarations shared by the plprof HIP sources (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/plprof.h"
+
+namespace plk {
+
+// Tile edge of the blocked factorisation and of the covariance builder.
+constexpr int T = 128;
+// Chebyshev table for h(u) = log rho(e^u) + e^u, u = log x: NP pieces of NC
+// coefficients each, over [log X_LO, log x_hi(omega)].
+constexpr int NP = 48;
+constexpr int NC = 16;
+constexpr double X_LO = 1.0e-3;     // below: direct quadrature per element
+constexpr double X_ZERO = 1.0e-200; // below: rho = 1 to double precision
+
+// Per-omega constants, computed on the host once per call.
+struct MaternParams {
+  double inv_phix, inv_phiy;   // 1/phi_X, 1/phi_Y
+  double cosA, sinA;           // rotation by phi_A
+  double sqrt8k;               // sqrt(8 kappa)
+  double nugget;               // nu^2
+  double kappa;
+  double log_norm;             // log(2^(1-kappa) / Gamma(kappa))
+  double u_a;                  // log X_LO
+  double inv_w;                // NP / (log x_hi - log X_LO)
+  double x_hi;                 // rho(x) underflows beyond
+  double pad;
+};
+
+// Addressing of the per-omega matrices.
+//  kind 0: packed lower tiles, each T x T column-major, tile (I,J) of the V
+//          part at (I(I+1)/2 + J) T^2; below them a bordered tile row of
+//          height TB holding the right-hand sides as rows (tile (Nv,J) is
+//          TB x T, the final tile (Nv,Nv) TB x TB).  A row panel I (tiles
+//          (I,0..I-1)) is then one contiguous column-major block.
+//  kind 1: plain column-major n x n with leading dimension ld.
+struct Lay {
+  int kind;
+  int Nv;        // tile rows covering the n rows of V
+  int n;         // order of V
+  int q;         // bordered rows (right-hand sides), 0 for kind 1
+  int TB;        // height of the bordered tile row (q rounded up to 16)
+  int pad;
+  int64_t ld;      // kind 1 leading dimension
+  int64_t mstride; // elements per matrix
+
+  __host__ __device__ int64_t tile_off(int I, int J) const {
+    if (kind == 1) return (int64_t)J * T * ld + (int64_t)I * T;
+    if (I < Nv) return ((int64_t)I * (I + 1) / 2 + J) * (int64_t)(T * T);
+    return (int64_t)Nv * (Nv + 1) / 2 * (T * T) + (int64_t)J * TB * T;
+  }
+  __host__ __device__ int64_t tile_ld(int I) const {
+    if (kind == 1) return ld;
+    return I < Nv ? T : TB;
+  }
+  __host__ __device__ int rows(int I) const {
+    if (I < Nv) { int r = n - I * T; return r < T ? r : T; }
+    return q;
+  }
+};
+
+__host__ inline int64_t packed_stride(int Nv, int TB) {
+  return (int64_t)Nv * (Nv + 1) / 2 * (T * T) + (int64_t)Nv * TB * T + (int64_t)TB * TB;
+}
+
+// Workgroup index remapped so that consecutive logical indices share an XCD
+// (hardware dispatches consecutive workgroups round-robin over the 8 XCDs,
+// each with its own L2).  Bijective for any grid size.
+__device__ inline int xcd_remap(int wg, int G) {
+  const int nx = 8;
+  int per = G / nx, rem = G % nx;
+  int x = wg % nx, i = wg / nx;
+  return x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
+}
+
+// ---- launch wrappers (defined in the .hip files) --------------------------
+hipError_t launch_cheb_tables(const MaternParams* mp, double* nodes, double* tables,
+                              int K, hipStream_t s);
+hipError_t launch_matern_packed(const Lay& lay, double* mats, const double* locs,
+                                const MaternParams* mp, const double* tables, int K,
+                                hipStream_t s);
+hipError_t launch_matern_colmajor(double* V, int64_t ld, int n, const double* locs,
+                                  const MaternParams* mp, const double* tables, int K,
+                                  hipStream_t s);
+hipError_t launch_potrf(const Lay& lay, double* mats, double* W, double* logdet,
+                        int32_t* info, int J, int K, hipStream_t s);
+hipError_t launch_trsm(const Lay& lay, double* mats, const double* W, const int32_t* info,
+                       int J, int nI, int K, hipStream_t s);
+hipError_t launch_gemm_col(const Lay& lay, double* mats, const int32_t* info, int J, int nI,
+                           int K, hipStream_t s);
+hipError_t launch_fill(double* p, double v, int64_t count, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s);
+hipError_t launch_boxcox_rhs(const double* y, const double* X, const double* lam, int n,
+                             int p, int M, double* rhs, double* jac, int32_t* flags,
+                             hipStream_t s);
+hipError_t launch_border_init(const Lay& lay, double* mats, const double* rhs, int K,
+                              hipStream_t s);
+hipError_t launch_finalize(const Lay& lay, const double* mats, const double* logdet,
+                           const int32_t* info, const double* jac, const int32_t* flags,
+                           const double* lam, int n, int p, int M, int K,
+                           pl_result* out, double* beta, hipStream_t s);
+
+}  // namespace plk

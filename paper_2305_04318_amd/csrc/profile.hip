@@ -1,0 +1,246 @@
+// Box-Cox right-hand sides and Jacobian (Section 2; equation (2)'s third
+// term), and the p x p stage of Step 3 (Steps 5-8 of Section 3.3) that turns
+// the cross products into beta-hat, sigma-hat^2 and the profile
+// log-likelihood (equations "betahat", (4), "profile", Appendix "remlpro").
+#include <math.h>
+
+#include "common.h"
+
+namespace plk {
+
+__global__ void k_fill(double* p, double v, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+hipError_t launch_fill(double* p, double v, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, v, count);
+  return hipGetLastError();
+}
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, v, count);
+  return hipGetLastError();
+}
+
+// rhs is n rows of TB values: [y'(lambda_1) .. y'(lambda_M) | X_1 .. X_p | 0 ..]
+// (y' = expm1(lambda log y)/lambda, log y at lambda = 0).
+__global__ void k_boxcox_rhs(const double* __restrict__ y, const double* __restrict__ X,
+                             const double* __restrict__ lam, int n, int p, int M, int TB,
+                             double* __restrict__ rhs) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * TB) return;
+  const int i = (int)(idx / TB), a = (int)(idx % TB);
+  double v = 0.0;
+  if (a < M) {
+    const double ly = log(y[i]);
+    const double l = lam[a];
+    v = (l == 0.0) ? ly : expm1(l * ly) / l;
+  } else if (a < M + p) {
+    v = X[(int64_t)(a - M) * n + i];
+  }
+  rhs[idx] = v;
+}
+
+// J = sum log y_i in one workgroup (fixed summation order) and the y > 0 flag.
+__global__ __launch_bounds__(1024) void k_jacobian(const double* __restrict__ y, int n,
+                                                   double* __restrict__ jac,
+                                                   int32_t* __restrict__ flags) {
+  __shared__ double red[1024];
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  double s = 0.0;
+  int lbad = 0;
+  for (int i = threadIdx.x; i < n; i += 1024) {
+    const double v = y[i];
+    if (!(v > 0.0) || !isfinite(v)) lbad = 1;
+    else s += log(v);
+  }
+  red[threadIdx.x] = s;
+  if (lbad) atomicOr(&bad, 1);
+  __syncthreads();
+  for (int off = 512; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    jac[0] = red[0];
+    flags[0] = bad;
+  }
+}
+
+hipError_t launch_boxcox_rhs(const double* y, const double* X, const double* lam, int n, int p,
+                             int M, double* rhs, double* jac, int32_t* flags, hipStream_t s) {
+  const int TB = ((M + p) + 15) / 16 * 16;
+  const int64_t total = (int64_t)n * TB;
+  hipLaunchKernelGGL(k_boxcox_rhs, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, y, X,
+                     lam, n, p, M, TB, rhs);
+  hipLaunchKernelGGL(k_jacobian, dim3(1), dim3(1024), 0, s, y, n, jac, flags);
+  return hipGetLastError();
+}
+
+// Copy the right-hand sides into each omega's bordered tile row (column i of
+// the bordered panel is rhs row i) and clear the final TB x TB tile.
+__global__ void k_border_init(Lay lay, double* __restrict__ mats, const double* __restrict__ rhs,
+                              int K) {
+  const int64_t per = (int64_t)lay.n * lay.TB + (int64_t)lay.TB * lay.TB;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= per * K) return;
+  const int k = (int)(idx / per);
+  const int64_t e = idx % per;
+  double* base = mats + (int64_t)k * lay.mstride;
+  if (e < (int64_t)lay.n * lay.TB) {
+    base[lay.tile_off(lay.Nv, 0) + e] = rhs[e];
+  } else {
+    base[lay.tile_off(lay.Nv, lay.Nv) + (e - (int64_t)lay.n * lay.TB)] = 0.0;
+  }
+}
+
+hipError_t launch_border_init(const Lay& lay, double* mats, const double* rhs, int K,
+                              hipStream_t s) {
+  const int64_t per = (int64_t)lay.n * lay.TB + (int64_t)lay.TB * lay.TB;
+  const int64_t total = per * K;
+  hipLaunchKernelGGL(k_border_init, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, lay,
+                     mats, rhs, K);
+  return hipGetLastError();
+}
+
+// ---- p x p stage ----------------------------------------------------------
+// One wave per omega.  The final tile holds S = -(y',X)^T V^-1 (y',X) (the
+// Schur complement of V in the bordered matrix), so ssqYX = -S:
+//   A = X^T V^-1 X = Q Q^T           (Step 5; log|X^T V^-1 X| = 2 sum log Q_ii)
+//   c_m = Q^-1 X^T V^-1 y'_m          (Step 6)
+//   ssqBetahat_m = c_m^T c_m          (Step 7)
+//   ssqResidual_m = ssqY_m - ssqBetahat_m (Step 8); beta-hat = Q^-T c_m.
+__global__ __launch_bounds__(64) void k_finalize(Lay lay, const double* __restrict__ mats,
+                                                 const double* __restrict__ logdet,
+                                                 const int32_t* __restrict__ info,
+                                                 const double* __restrict__ jac,
+                                                 const int32_t* __restrict__ flags,
+                                                 const double* __restrict__ lam, int n, int p,
+                                                 int M, pl_result* __restrict__ out,
+                                                 double* __restrict__ beta) {
+  __shared__ double Q[PL_MAX_P * PL_MAX_P];
+  __shared__ double cm[PL_MAX_M * PL_MAX_P];
+  __shared__ int rank_bad;
+  __shared__ double ldx;
+  const int k = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int TB = lay.TB;
+  const double* S = mats + (int64_t)k * lay.mstride + lay.tile_off(lay.Nv, lay.Nv);
+  const double J = jac[0];
+  const int inf = info[k];
+  const bool bady = flags[0] != 0;
+  const double LOG2PI = 1.8378770664093454836;
+  const double ldv = logdet[k];
+
+  if (!bady && inf == 0) {
+    // A (lower) into LDS: ssq(a,b) = -S[b*TB + a] for a >= b
+    for (int idx = tid; idx < p * p; idx += 64) {
+      const int i = idx / p, j = idx % p;
+      const int a = M + (i > j ? i : j), b = M + (i > j ? j : i);
+      Q[i * PL_MAX_P + j] = -S[(int64_t)b * TB + a];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      // Cholesky of the p x p matrix (row-major, lower used)
+      int bad = 0;
+      double sl = 0.0;
+      for (int j = 0; j < p && !bad; ++j) {
+        double d = Q[j * PL_MAX_P + j];
+        for (int m = 0; m < j; ++m) d -= Q[j * PL_MAX_P + m] * Q[j * PL_MAX_P + m];
+        if (!(d > 0.0)) { bad = 1; break; }
+        const double l = sqrt(d);
+        Q[j * PL_MAX_P + j] = l;
+        sl += log(l);
+        for (int i = j + 1; i < p; ++i) {
+          double v = Q[i * PL_MAX_P + j];
+          for (int m = 0; m < j; ++m) v -= Q[i * PL_MAX_P + m] * Q[j * PL_MAX_P + m];
+          Q[i * PL_MAX_P + j] = v / l;
+        }
+      }
+      rank_bad = bad;
+      ldx = 2.0 * sl;
+    }
+    __syncthreads();
+  } else {
+    if (tid == 0) { rank_bad = 0; ldx = NAN; }
+    __syncthreads();
+  }
+
+  for (int m = tid; m < M; m += 64) {
+    pl_result rec;
+    rec.jacobian = J;
+    rec.pad = 0;
+    rec.logdet_v = ldv;
+    rec.logdet_xvx = ldx;
+    const double lm = lam[m];
+    if (bady) {
+      rec.loglik = NAN; rec.loglik_reml = NAN; rec.info = PL_INFO_BAD_Y;
+      rec.logdet_v = NAN; rec.logdet_xvx = NAN;
+      rec.ssq_y = rec.ssq_betahat = rec.ssq_resid = rec.sigma2_hat = NAN;
+    } else if (inf != 0) {
+      rec.loglik = -INFINITY; rec.loglik_reml = -INFINITY; rec.info = inf;
+      rec.logdet_v = NAN;
+      rec.ssq_y = rec.ssq_betahat = rec.ssq_resid = rec.sigma2_hat = NAN;
+    } else if (rank_bad) {
+      rec.loglik = NAN; rec.loglik_reml = NAN; rec.info = PL_INFO_RANK;
+      rec.ssq_y = -S[(int64_t)m * TB + m];
+      rec.ssq_betahat = rec.ssq_resid = rec.sigma2_hat = NAN;
+    } else {
+      double* c = cm + m * PL_MAX_P;
+      // c = Q^-1 B_m, B_m[i] = ssq(M+i, m) = -S[m*TB + M+i]
+      double ssb = 0.0;
+      for (int i = 0; i < p; ++i) {
+        double v = -S[(int64_t)m * TB + M + i];
+        for (int j = 0; j < i; ++j) v -= Q[i * PL_MAX_P + j] * c[j];
+        v /= Q[i * PL_MAX_P + i];
+        c[i] = v;
+        ssb += v * v;
+      }
+      const double ssy = -S[(int64_t)m * TB + m];
+      const double ssr = ssy - ssb;
+      const double s2 = ssr / n;
+      rec.ssq_y = ssy;
+      rec.ssq_betahat = ssb;
+      rec.ssq_resid = ssr;
+      rec.sigma2_hat = s2;
+      rec.info = 0;
+      rec.loglik = -0.5 * (n * log(s2) + ldv + n * LOG2PI + n) + (lm - 1.0) * J;
+      rec.loglik_reml = -0.5 * ((n - p) * log(ssr / (n - p)) + ldv + ldx + n * LOG2PI + n - p) +
+                        (lm - 1.0) * J;
+      if (beta) {
+        // beta-hat = Q^-T c (back substitution), written in place of c
+        double* bo = beta + ((int64_t)k * M + m) * p;
+        for (int i = p - 1; i >= 0; --i) {
+          double v = c[i];
+          for (int j = i + 1; j < p; ++j) v -= Q[j * PL_MAX_P + i] * c[j];
+          v /= Q[i * PL_MAX_P + i];
+          c[i] = v;
+        }
+        for (int i = 0; i < p; ++i) bo[i] = c[i];
+      }
+    }
+    if (beta && rec.info != 0) {
+      double* bo = beta + ((int64_t)k * M + m) * p;
+      for (int i = 0; i < p; ++i) bo[i] = NAN;
+    }
+    out[(int64_t)k * M + m] = rec;
+  }
+}
+
+hipError_t launch_finalize(const Lay& lay, const double* mats, const double* logdet,
+                           const int32_t* info, const double* jac, const int32_t* flags,
+                           const double* lam, int n, int p, int M, int K, pl_result* out,
+                           double* beta, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(K), dim3(64), 0, s, lay, mats, logdet, info, jac, flags, lam,
+                     n, p, M, out, beta);
+  return hipGetLastError();
+}
+
+}  // namespace plk
