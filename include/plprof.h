@@ -158,6 +158,35 @@ int pl_profile_loglik(const double* locs, const double* y, const double* X,
                       double* beta_hat, const pl_opts* opts, void* work,
                       size_t work_bytes, void* stream);
 
+/*
+ * Optional timing of the library's own kernels with HIP events recorded on
+ * the caller's stream around every launch (benchmarks and tracing; off by
+ * default, no cost when off).  Kernel classes:
+ *   PL_KC_TABLES  per-omega Chebyshev tables of the Matern correlation
+ *   PL_KC_MATERN  covariance tiles
+ *   PL_KC_GEMM    left-looking block-column update (the dominant kernel)
+ *   PL_KC_POTRF   diagonal-tile factorisation and inverse
+ *   PL_KC_TRSM    panel solve
+ *   PL_KC_OTHER   Box-Cox right-hand sides, bordering, p x p stage, fills
+ * pl_profiling_enable(1) clears the counters and starts recording;
+ * pl_profiling_enable(0) stops.  pl_profiling_read waits for the recorded
+ * events, then writes per class (arrays of length nclass <= PL_KC_COUNT):
+ * total milliseconds, the algorithmic floating-point operations of those
+ * launches (for PL_KC_GEMM: the lower-triangle update flops the method
+ * needs, 2 r c k per off-diagonal tile and r (r+1) k per diagonal tile),
+ * and the launch count.  Errors: -1 bad nclass, -2..-4 NULL array;
+ * PL_E_HIP if an event failed.
+ */
+#define PL_KC_TABLES 0
+#define PL_KC_MATERN 1
+#define PL_KC_GEMM   2
+#define PL_KC_POTRF  3
+#define PL_KC_TRSM   4
+#define PL_KC_OTHER  5
+#define PL_KC_COUNT  6
+int pl_profiling_enable(int on);
+int pl_profiling_read(double* ms, double* alg_flops, int64_t* launches, int nclass);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,7 +12,9 @@ PL_MAX_P, PL_MAX_M = 32, 64
 
 # every symbol the header declares
 EXPORTS = ("pl_version", "pl_error_string", "pl_workspace_size", "pl_matern_workspace_size",
-           "pl_matern_cov", "pl_chol_workspace_size", "pl_chol_batched", "pl_profile_loglik")
+           "pl_matern_cov", "pl_chol_workspace_size", "pl_chol_batched", "pl_profile_loglik",
+           "pl_profiling_enable", "pl_profiling_read")
+KERNEL_CLASSES = ("tables", "matern", "gemm", "potrf", "trsm", "other")
 
 
 class PlResult(ctypes.Structure):
@@ -67,6 +69,11 @@ def load(path: str = None):
     lib.pl_profile_loglik.restype = ctypes.c_int
     lib.pl_profile_loglik.argtypes = [_P, _P, _P, _I64, _I64, _P, _I64, _P, _I64, _P, _P,
                                       ctypes.POINTER(PlOpts), _P, _SZ, _P]
+    lib.pl_profiling_enable.restype = ctypes.c_int
+    lib.pl_profiling_enable.argtypes = [ctypes.c_int]
+    lib.pl_profiling_read.restype = ctypes.c_int
+    lib.pl_profiling_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
     if path is None:
         _lib = lib
     return lib

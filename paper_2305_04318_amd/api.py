@@ -144,3 +144,20 @@ def profile_loglik(locs, y, X, omega, lam, precision="fp64", chunk=0, return_bet
     if return_beta:
         res["beta"] = beta
     return res
+
+
+def profiling_enable(on: bool = True):
+    """Start (clearing counters) or stop HIP-event timing of the library's kernels."""
+    check(load().pl_profiling_enable(1 if on else 0), "pl_profiling_enable")
+
+
+def profiling_read() -> dict:
+    """Per kernel class: total ms, algorithmic flops and launch count of the
+    launches recorded since profiling_enable(True)."""
+    n = len(_lib.KERNEL_CLASSES)
+    ms = (ctypes.c_double * n)()
+    fl = (ctypes.c_double * n)()
+    ln = (ctypes.c_int64 * n)()
+    check(load().pl_profiling_read(ms, fl, ln, n), "pl_profiling_read")
+    return {c: {"ms": ms[i], "flops": fl[i], "launches": ln[i]}
+            for i, c in enumerate(_lib.KERNEL_CLASSES)}

@@ -103,6 +103,57 @@ void copy_h2d_async(void* dst, const void* src, size_t bytes, hipStream_t s, hip
     if (_e != hipSuccess) return PL_E_HIP;    \
   } while (0)
 
+// ---- optional per-kernel-class timing with HIP events -----------------------
+struct ProfRec {
+  int cls;
+  double flops;
+  hipEvent_t a, b;
+};
+struct Prof {
+  bool on = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+Prof g_prof;
+
+// Runs `launch`, bracketed by events on stream s when profiling is on.
+template <class F>
+hipError_t timed(int cls, double flops, hipStream_t s, F&& launch) {
+  if (!g_prof.on) return launch();
+  hipEvent_t a = g_prof.get(), b = g_prof.get();
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, s);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, s);
+  if (e != hipSuccess) return e;
+  g_prof.recs.push_back({cls, flops, a, b});
+  return hipSuccess;
+}
+
+// Algorithmic flops of one left-looking column update (lower triangle only).
+double gemm_col_flops(const Lay& lay, int J, int nI) {
+  const double kk = std::min<double>((double)J * T, lay.n);
+  const double cj = lay.rows(J);
+  double f = 0.0;
+  for (int I = J; I < J + nI; ++I) {
+    const double ri = lay.rows(I);
+    f += (I == J) ? ri * (ri + 1.0) * kk : 2.0 * ri * cj * kk;
+  }
+  return f;
+}
+
 }  // namespace
 
 extern "C" {
@@ -151,8 +202,9 @@ int pl_matern_cov(const double* locs, int64_t n, const double* omega, int64_t K,
   hipError_t err = hipSuccess;
   copy_h2d_async(mp, hp.data(), K * sizeof(MaternParams), s, &err);
   if (err != hipSuccess) return PL_E_HIP;
-  PL_CHECK(launch_cheb_tables(mp, nodes, tables, (int)K, s));
-  PL_CHECK(launch_matern_colmajor(V, ld, (int)n, locs, mp, tables, (int)K, s));
+  PL_CHECK(timed(PL_KC_TABLES, 0.0, s, [&] { return launch_cheb_tables(mp, nodes, tables, (int)K, s); }));
+  PL_CHECK(timed(PL_KC_MATERN, 0.0, s,
+                 [&] { return launch_matern_colmajor(V, ld, (int)n, locs, mp, tables, (int)K, s); }));
   return PL_OK;
 }
 
@@ -186,9 +238,14 @@ int pl_chol_batched(double* V, int64_t n, int64_t K, int64_t ld, double* logdet,
   PL_CHECK(launch_fill(logdet, 0.0, K, s));
   PL_CHECK(launch_fill_i32(info, 0, K, s));
   for (int J = 0; J < lay.Nv; ++J) {
-    if (J > 0) PL_CHECK(launch_gemm_col(lay, V, info, J, lay.Nv - J, (int)K, s));
-    PL_CHECK(launch_potrf(lay, V, W, logdet, info, J, (int)K, s));
-    if (lay.Nv - J - 1 > 0) PL_CHECK(launch_trsm(lay, V, W, info, J, lay.Nv - J - 1, (int)K, s));
+    if (J > 0)
+      PL_CHECK(timed(PL_KC_GEMM, K * gemm_col_flops(lay, J, lay.Nv - J), s,
+                     [&] { return launch_gemm_col(lay, V, info, J, lay.Nv - J, (int)K, s); }));
+    PL_CHECK(timed(PL_KC_POTRF, 0.0, s,
+                   [&] { return launch_potrf(lay, V, W, logdet, info, J, (int)K, s); }));
+    if (lay.Nv - J - 1 > 0)
+      PL_CHECK(timed(PL_KC_TRSM, 0.0, s,
+                     [&] { return launch_trsm(lay, V, W, info, J, lay.Nv - J - 1, (int)K, s); }));
   }
   return PL_OK;
 }
@@ -266,24 +323,72 @@ int pl_profile_loglik(const double* locs, const double* y, const double* X, int6
   copy_h2d_async(lam_d, lambda, M * sizeof(double), s, &err);
   if (err != hipSuccess) return PL_E_HIP;
 
-  PL_CHECK(launch_cheb_tables(mp, nodes, tables, (int)K, s));
-  PL_CHECK(launch_boxcox_rhs(y, X, lam_d, (int)n, (int)p, (int)M, rhs, jac, flags, s));
+  PL_CHECK(timed(PL_KC_TABLES, 0.0, s, [&] { return launch_cheb_tables(mp, nodes, tables, (int)K, s); }));
+  PL_CHECK(timed(PL_KC_OTHER, 0.0, s, [&] {
+    return launch_boxcox_rhs(y, X, lam_d, (int)n, (int)p, (int)M, rhs, jac, flags, s);
+  }));
 
   for (int64_t c0 = 0; c0 < K; c0 += kc) {
     const int kk = (int)std::min<int64_t>(kc, K - c0);
-    PL_CHECK(launch_border_init(lay, mats, rhs, kk, s));
-    PL_CHECK(launch_matern_packed(lay, mats, locs, mp + c0, tables + c0 * NP * NC, kk, s));
-    PL_CHECK(launch_fill(logdet, 0.0, kk, s));
-    PL_CHECK(launch_fill_i32(info, 0, kk, s));
+    PL_CHECK(timed(PL_KC_OTHER, 0.0, s, [&] {
+      hipError_t e = launch_border_init(lay, mats, rhs, kk, s);
+      if (e == hipSuccess) e = launch_fill(logdet, 0.0, kk, s);
+      if (e == hipSuccess) e = launch_fill_i32(info, 0, kk, s);
+      return e;
+    }));
+    PL_CHECK(timed(PL_KC_MATERN, 0.0, s, [&] {
+      return launch_matern_packed(lay, mats, locs, mp + c0, tables + c0 * NP * NC, kk, s);
+    }));
     for (int J = 0; J <= lay.Nv; ++J) {
-      if (J > 0) PL_CHECK(launch_gemm_col(lay, mats, info, J, lay.Nv - J + 1, kk, s));
+      if (J > 0) {
+        const int nI = lay.Nv - J + 1;
+        PL_CHECK(timed(PL_KC_GEMM, kk * gemm_col_flops(lay, J, nI), s,
+                       [&] { return launch_gemm_col(lay, mats, info, J, nI, kk, s); }));
+      }
       if (J < lay.Nv) {
-        PL_CHECK(launch_potrf(lay, mats, W, logdet, info, J, kk, s));
-        PL_CHECK(launch_trsm(lay, mats, W, info, J, lay.Nv - J, kk, s));
+        PL_CHECK(timed(PL_KC_POTRF, 0.0, s,
+                       [&] { return launch_potrf(lay, mats, W, logdet, info, J, kk, s); }));
+        PL_CHECK(timed(PL_KC_TRSM, 0.0, s,
+                       [&] { return launch_trsm(lay, mats, W, info, J, lay.Nv - J, kk, s); }));
       }
     }
-    PL_CHECK(launch_finalize(lay, mats, logdet, info, jac, flags, lam_d, (int)n, (int)p, (int)M,
-                             kk, out + c0 * M, beta_hat ? beta_hat + c0 * M * p : nullptr, s));
+    PL_CHECK(timed(PL_KC_OTHER, 0.0, s, [&] {
+      return launch_finalize(lay, mats, logdet, info, jac, flags, lam_d, (int)n, (int)p, (int)M,
+                             kk, out + c0 * M, beta_hat ? beta_hat + c0 * M * p : nullptr, s);
+    }));
+  }
+  return PL_OK;
+}
+
+int pl_profiling_enable(int on) {
+  for (auto& r : g_prof.recs) {
+    g_prof.pool.push_back(r.a);
+    g_prof.pool.push_back(r.b);
+  }
+  g_prof.recs.clear();
+  g_prof.on = on != 0;
+  return PL_OK;
+}
+
+int pl_profiling_read(double* ms, double* alg_flops, int64_t* launches, int nclass) {
+  if (nclass < 1 || nclass > PL_KC_COUNT) return -1;
+  if (!ms) return -2;
+  if (!alg_flops) return -3;
+  if (!launches) return -4;
+  for (int c = 0; c < nclass; ++c) {
+    ms[c] = 0.0;
+    alg_flops[c] = 0.0;
+    launches[c] = 0;
+  }
+  for (auto& r : g_prof.recs) {
+    if (hipEventSynchronize(r.b) != hipSuccess) return PL_E_HIP;
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return PL_E_HIP;
+    if (r.cls < nclass) {
+      ms[r.cls] += t;
+      alg_flops[r.cls] += r.flops;
+      launches[r.cls] += 1;
+    }
   }
   return PL_OK;
 }

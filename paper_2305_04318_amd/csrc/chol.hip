@@ -10,8 +10,12 @@
 // under V, so the same steps produce Z = L^{-1}[Y'|X] (Step 3) and, in the
 // final tile, minus the cross products (y,X)^T V^{-1} (y,X) (Step 4).
 //
-// MFMA v_mfma_f64_16x16x4f64 operand layout (64 lanes): A[i][k] in lane
-// i + 16k, B[k][j] in lane j + 16k, D[i][j] in lane j + 16(i/4), item i%4.
+// MFMA v_mfma_f64_16x16x4f64 operand layout (64 lanes, checked on gfx950):
+// A[i][k] in lane i + 16k, B[k][j] in lane j + 16k, D[i][j] in lane
+// j + 16 (i % 4), item i / 4.  The kernels pass the B-panel fragment as the
+// first operand, so a lane's accumulator item e holds C[16i + (lane & 15)]
+// [16j + (lane >> 4) + 4e] of C = A B^T: sixteen lanes cover 16 consecutive
+// rows of one column, a contiguous 128-byte run in column-major storage.
 #include <math.h>
 
 #include "common.h"
@@ -54,7 +58,7 @@ __device__ __forceinline__ void mfma_nt64(d4 (&acc)[4][4], const double* __restr
       if (i < ni) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          if (j < nj) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+          if (j < nj) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j], a[i], acc[i][j], 0, 0, 0);
         }
       }
     }
@@ -65,17 +69,17 @@ __device__ __forceinline__ void mfma_nt64(d4 (&acc)[4][4], const double* __restr
 template <bool SUB>
 __device__ __forceinline__ void store64(double* C, int64_t ldc, const d4 (&acc)[4][4], int arows,
                                         int brows, int lane) {
-  const int lc = lane & 15, lg = lane >> 4;
+  const int lr = lane & 15, lg = lane >> 4;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
+    const int r = 16 * i + lr;
+    if (r >= arows) continue;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int c = 16 * j + lc;
-      if (c >= brows) continue;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int r = 16 * i + 4 * lg + e;
-        if (r < arows) {
+        const int c = 16 * j + lg + 4 * e;
+        if (c < brows) {
           double* p = C + (int64_t)c * ldc + r;
           if (SUB) *p -= acc[i][j][e];
           else *p = acc[i][j][e];
