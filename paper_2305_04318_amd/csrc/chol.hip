@@ -245,13 +245,15 @@ __global__ __launch_bounds__(256) void k_potrf(Lay lay, double* __restrict__ mat
         double cr[8], cc8[8];
 #pragma unroll
         for (int rr = 0; rr < 8; ++rr) cr[rr] = bc0[buf][8 * bi + rr] * invd;
+        // columns c <= j of the owner block get a zero multiplier instead of a
+        // per-element branch, so the 64 FMAs run unconditionally
 #pragma unroll
-        for (int c8 = 0; c8 < 8; ++c8) cc8[c8] = bc0[buf][8 * bj + c8];
+        for (int c8 = 0; c8 < 8; ++c8)
+          cc8[c8] = (bj > jb || c8 > jj) ? bc0[buf][8 * bj + c8] : 0.0;
 #pragma unroll
         for (int rr = 0; rr < 8; ++rr)
 #pragma unroll
-          for (int c8 = 0; c8 < 8; ++c8)
-            if (bj > jb || c8 > jj) a[rr][c8] -= cr[rr] * cc8[c8];
+          for (int c8 = 0; c8 < 8; ++c8) a[rr][c8] = fma(-cr[rr], cc8[c8], a[rr][c8]);
         if (bj == jb) {
           const double sc = 1.0 / sqrt(d);
 #pragma unroll
@@ -311,21 +313,23 @@ __global__ __launch_bounds__(256) void k_potrf(Lay lay, double* __restrict__ mat
       const double wmm = dinv[m];
       if (low && bi >= mb && bj <= mb) {
         double lr[8], wv[8];
+        // rows r <= m and columns c >= m get zero multipliers (no branches)
 #pragma unroll
-        for (int rr = 0; rr < 8; ++rr) lr[rr] = bc0[buf][8 * bi + rr];
+        for (int rr = 0; rr < 8; ++rr) lr[rr] = (bi > mb || rr > mm) ? bc0[buf][8 * bi + rr] : 0.0;
 #pragma unroll
-        for (int c8 = 0; c8 < 8; ++c8) wv[c8] = bc1[buf][8 * bj + c8];
+        for (int c8 = 0; c8 < 8; ++c8) wv[c8] = (bj < mb || c8 < mm) ? bc1[buf][8 * bj + c8] : 0.0;
 #pragma unroll
-        for (int rr = 0; rr < 8; ++rr) {
-          if (bi > mb || rr > mm) {
+        for (int rr = 0; rr < 8; ++rr)
 #pragma unroll
-            for (int c8 = 0; c8 < 8; ++c8) {
-              if (bj < mb || c8 < mm) a[rr][c8] -= lr[rr] * wv[c8];
-              else if (c8 == mm) a[rr][c8] = -lr[rr] * wmm;
-            }
+          for (int c8 = 0; c8 < 8; ++c8) a[rr][c8] = fma(-lr[rr], wv[c8], a[rr][c8]);
+        if (bj == mb) {
+          // column m becomes W_rm = -L_rm / L_mm (r > m), W_mm = 1 / L_mm
+#pragma unroll
+          for (int rr = 0; rr < 8; ++rr) {
+            if (bi > mb || rr > mm) a[rr][mm] = -lr[rr] * wmm;
           }
+          if (bi == mb) a[mm][mm] = wmm;
         }
-        if (bi == mb && bj == mb) a[mm][mm] = wmm;
       }
     }
   }
