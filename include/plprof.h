@@ -78,10 +78,16 @@ typedef struct pl_result {
 
 typedef struct pl_opts {
   int32_t precision;    /* PL_FP64 (default) or PL_MIXED                         */
-  int32_t refine;       /* PL_MIXED: refinement steps, default 1                 */
+  int32_t refine;       /* PL_MIXED: 1 (default) = one FP64 refinement of the
+                           cross products (see pl_profile_loglik); 0 = none      */
   int64_t chunk;        /* max omega per device pass; 0 = as many as fit          */
-  int32_t reserved[4];
+  int32_t flags;        /* PL_OPT_* bits                                         */
+  int32_t reserved[3];
 } pl_opts;
+
+/* pl_opts.flags */
+#define PL_OPT_NO_FALLBACK 1  /* PL_MIXED: do not synchronise to redo FP32
+                                 breakdowns in FP64 (they keep info > 0)        */
 
 /* Library version string. */
 const char* pl_version(void);
@@ -149,8 +155,19 @@ int pl_chol_batched(double* V, int64_t n, int64_t K, int64_t ld, double* logdet,
  * Errors: -1 locs, -2 y, -3 X NULL; -4 n < 2; -5 p < 1, p >= n or p > PL_MAX_P;
  * -6 omega NULL or out of domain (as pl_matern_cov); -7 K < 1;
  * -8 lambda NULL or not finite; -9 M < 1 or M > PL_MAX_M; -10 out NULL;
- * -12 bad option; -13/-14 workspace NULL or too small.
+ * -12 bad option; -13/-14 workspace NULL or too small; PL_E_UNSUPPORTED for
+ * PL_MIXED with M + p > 32.
  * y <= 0 is detected on the device: every record then carries PL_INFO_BAD_Y.
+ *
+ * PL_MIXED: V is factored in FP32 (FP32 MFMA off-diagonal updates and panel
+ * solves) with each diagonal tile updated from the FP64 V in FP64 and factored
+ * in FP64, so log|V| is accumulated in FP64; x0 = V^-1 [Y'|X] comes from FP32
+ * substitution; the cross products are then evaluated in FP64 as
+ * 2 B^T x0 - x0^T V x0 (B = [Y'|X]), whose error is second order in the error
+ * of x0 -- one FP64 refinement step applied to the quadratic forms; the p x p
+ * stage is FP64.  Points whose FP32 factorisation breaks down are recomputed
+ * with the FP64 form (info |= PL_INFO_FALLBACK); that check synchronises the
+ * stream once at the end of the call unless PL_OPT_NO_FALLBACK is set.
  */
 int pl_profile_loglik(const double* locs, const double* y, const double* X,
                       int64_t n, int64_t p, const double* omega, int64_t K,

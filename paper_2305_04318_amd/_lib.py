@@ -28,7 +28,11 @@ class PlResult(ctypes.Structure):
 
 class PlOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("refine", ctypes.c_int32),
-                ("chunk", ctypes.c_int64), ("reserved", ctypes.c_int32 * 4)]
+                ("chunk", ctypes.c_int64), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
+
+
+PL_OPT_NO_FALLBACK = 1
 
 
 class PlError(RuntimeError):

@@ -38,11 +38,12 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _opts(precision="fp64", chunk=0, refine=1):
+def _opts(precision="fp64", chunk=0, refine=1, fallback=True):
     o = PlOpts()
     o.precision = _PREC[precision]
-    o.refine = refine
+    o.refine = int(refine)
     o.chunk = int(chunk or 0)
+    o.flags = 0 if fallback else _lib.PL_OPT_NO_FALLBACK
     return o
 
 
@@ -117,7 +118,8 @@ class Inputs:
 
 
 def profile_loglik(locs, y, X, omega, lam, precision="fp64", chunk=0, return_beta=False,
-                   out=None, beta=None, work=None, stream=None, device="cuda", inputs=None):
+                   out=None, beta=None, work=None, stream=None, device="cuda", inputs=None,
+                   refine=1, fallback=True):
     """Records for every (omega_k, lambda_m): dict of (K, M) tensors on the
     device, plus "beta" (K, M, p) when return_beta."""
     lib = load()
@@ -130,7 +132,7 @@ def profile_loglik(locs, y, X, omega, lam, precision="fp64", chunk=0, return_bet
         out = torch.empty((K, M, 10), dtype=torch.float64, device=dev)
     if return_beta and beta is None:
         beta = torch.empty((K, M, inp.p), dtype=torch.float64, device=dev)
-    o = _opts(precision, chunk)
+    o = _opts(precision, chunk, refine, fallback)
     if work is None:
         work = torch.empty(workspace_size(inp.n, inp.p, K, M, precision, chunk),
                            dtype=torch.uint8, device=dev)

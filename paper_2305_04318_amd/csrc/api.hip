@@ -73,6 +73,18 @@ size_t per_omega_bytes(const Lay& lay) {
          2 * ALIGN;
 }
 
+// mixed form: FP32 packed factor (with the bordered row), FP64 copy of V,
+// the FP32 inverses of every diagonal tile, an FP64 scratch tile, x0 and the
+// per-tile-row cross-product slots
+int64_t v_stride64(const Lay& lay) { return (int64_t)lay.Nv * (lay.Nv + 1) / 2 * T * T; }
+
+size_t per_omega_bytes_mixed(const Lay& lay) {
+  return align_up(lay.mstride * sizeof(float)) + align_up(v_stride64(lay) * sizeof(double)) +
+         align_up((size_t)lay.Nv * T * T * sizeof(float)) + align_up((size_t)T * T * sizeof(double)) +
+         align_up((size_t)lay.n * lay.TB * sizeof(double)) +
+         align_up((size_t)lay.Nv * lay.TB * lay.TB * sizeof(double)) + 2 * ALIGN;
+}
+
 size_t fixed_bytes(int64_t n, int64_t K, int64_t M, const Lay& lay) {
   size_t b = 0;
   b += align_up(K * sizeof(MaternParams));
@@ -80,6 +92,7 @@ size_t fixed_bytes(int64_t n, int64_t K, int64_t M, const Lay& lay) {
   b += align_up(M * sizeof(double));
   b += align_up((size_t)n * lay.TB * sizeof(double));
   b += align_up(sizeof(double)) + align_up(sizeof(int32_t));
+  b += align_up(K * sizeof(int32_t));  // per-omega info of the whole call
   return b;
 }
 
@@ -258,10 +271,13 @@ int pl_workspace_size(int64_t n, int64_t p, int64_t K, int64_t M, const pl_opts*
   if (M < 1 || M > PL_MAX_M) return -4;
   if (!bytes) return -6;
   if (opts && opts->precision != PL_FP64 && opts->precision != PL_MIXED) return -5;
+  const bool mixed = opts && opts->precision == PL_MIXED;
+  if (mixed && M + p > 32) return PL_E_UNSUPPORTED;
   const Lay lay = packed_layout(n, M + p);
   int64_t kc = K;
   if (opts && opts->chunk > 0) kc = std::min<int64_t>(kc, opts->chunk);
-  *bytes = fixed_bytes(n, K, M, lay) + (size_t)kc * per_omega_bytes(lay);
+  *bytes = fixed_bytes(n, K, M, lay) + (size_t)kc * (mixed ? per_omega_bytes_mixed(lay)
+                                                           : per_omega_bytes(lay));
   return PL_OK;
 }
 
@@ -283,21 +299,24 @@ int pl_profile_loglik(const double* locs, const double* y, const double* X, int6
     if (!std::isfinite(lambda[m])) return -8;
   if (M < 1 || M > PL_MAX_M) return -9;
   if (!out) return -10;
-  int precision = PL_FP64;
+  int precision = PL_FP64, refine = 1, flags = 0;
   int64_t chunk = 0;
   if (opts) {
     precision = opts->precision;
     chunk = opts->chunk;
+    refine = opts->refine;
+    flags = opts->flags;
     if (precision != PL_FP64 && precision != PL_MIXED) return -12;
-    if (chunk < 0) return -12;
+    if (chunk < 0 || refine < 0 || refine > 1) return -12;
   }
-  if (precision != PL_FP64) return PL_E_UNSUPPORTED;
+  const bool mixed = precision == PL_MIXED;
+  if (mixed && M + p > 32) return PL_E_UNSUPPORTED;
   if (!work) return -13;
   hipStream_t s = (hipStream_t)stream;
 
   const Lay lay = packed_layout(n, M + p);
   const size_t fixed = fixed_bytes(n, K, M, lay);
-  const size_t per = per_omega_bytes(lay);
+  const size_t per = mixed ? per_omega_bytes_mixed(lay) : per_omega_bytes(lay);
   if (work_bytes < fixed + per) return -14;
   int64_t kc = (int64_t)((work_bytes - fixed) / per);
   kc = std::min<int64_t>(kc, K);
@@ -310,9 +329,28 @@ int pl_profile_loglik(const double* locs, const double* y, const double* X, int6
   double* lam_d = cv.take<double>(M * sizeof(double));
   double* rhs = cv.take<double>((size_t)n * lay.TB * sizeof(double));
   double* jac = cv.take<double>(sizeof(double));
-  int32_t* flags = cv.take<int32_t>(sizeof(int32_t));
-  double* mats = cv.take<double>((size_t)kc * lay.mstride * sizeof(double));
-  double* W = cv.take<double>((size_t)kc * T * T * sizeof(double));
+  int32_t* yflags = cv.take<int32_t>(sizeof(int32_t));
+  int32_t* info_all = cv.take<int32_t>(K * sizeof(int32_t));
+  // per-chunk buffers
+  double* mats = nullptr;
+  double* W = nullptr;
+  float* m32 = nullptr;
+  double* m64 = nullptr;
+  float* W32 = nullptr;
+  double* dscr = nullptr;
+  double* x0 = nullptr;
+  double* slots = nullptr;
+  if (!mixed) {
+    mats = cv.take<double>((size_t)kc * lay.mstride * sizeof(double));
+    W = cv.take<double>((size_t)kc * T * T * sizeof(double));
+  } else {
+    m32 = cv.take<float>((size_t)kc * lay.mstride * sizeof(float));
+    m64 = cv.take<double>((size_t)kc * v_stride64(lay) * sizeof(double));
+    W32 = cv.take<float>((size_t)kc * lay.Nv * T * T * sizeof(float));
+    dscr = cv.take<double>((size_t)kc * T * T * sizeof(double));
+    x0 = cv.take<double>((size_t)kc * n * lay.TB * sizeof(double));
+    slots = cv.take<double>((size_t)kc * lay.Nv * lay.TB * lay.TB * sizeof(double));
+  }
   double* logdet = cv.take<double>((size_t)kc * sizeof(double));
   int32_t* info = cv.take<int32_t>((size_t)kc * sizeof(int32_t));
 
@@ -325,37 +363,85 @@ int pl_profile_loglik(const double* locs, const double* y, const double* X, int6
 
   PL_CHECK(timed(PL_KC_TABLES, 0.0, s, [&] { return launch_cheb_tables(mp, nodes, tables, (int)K, s); }));
   PL_CHECK(timed(PL_KC_OTHER, 0.0, s, [&] {
-    return launch_boxcox_rhs(y, X, lam_d, (int)n, (int)p, (int)M, rhs, jac, flags, s);
+    return launch_boxcox_rhs(y, X, lam_d, (int)n, (int)p, (int)M, rhs, jac, yflags, s);
   }));
 
   for (int64_t c0 = 0; c0 < K; c0 += kc) {
     const int kk = (int)std::min<int64_t>(kc, K - c0);
     PL_CHECK(timed(PL_KC_OTHER, 0.0, s, [&] {
-      hipError_t e = launch_border_init(lay, mats, rhs, kk, s);
+      hipError_t e = mixed ? launch_border_init_f32(lay, m32, rhs, kk, s)
+                           : launch_border_init(lay, mats, rhs, kk, s);
       if (e == hipSuccess) e = launch_fill(logdet, 0.0, kk, s);
       if (e == hipSuccess) e = launch_fill_i32(info, 0, kk, s);
       return e;
     }));
     PL_CHECK(timed(PL_KC_MATERN, 0.0, s, [&] {
-      return launch_matern_packed(lay, mats, locs, mp + c0, tables + c0 * NP * NC, kk, s);
+      return mixed ? launch_matern_mixed(lay, m64, v_stride64(lay), m32, locs, mp + c0,
+                                         tables + c0 * NP * NC, kk, s)
+                   : launch_matern_packed(lay, mats, locs, mp + c0, tables + c0 * NP * NC, kk, s);
     }));
-    for (int J = 0; J <= lay.Nv; ++J) {
-      if (J > 0) {
-        const int nI = lay.Nv - J + 1;
-        PL_CHECK(timed(PL_KC_GEMM, kk * gemm_col_flops(lay, J, nI), s,
-                       [&] { return launch_gemm_col(lay, mats, info, J, nI, kk, s); }));
+    if (!mixed) {
+      for (int J = 0; J <= lay.Nv; ++J) {
+        if (J > 0) {
+          const int nI = lay.Nv - J + 1;
+          PL_CHECK(timed(PL_KC_GEMM, kk * gemm_col_flops(lay, J, nI), s,
+                         [&] { return launch_gemm_col(lay, mats, info, J, nI, kk, s); }));
+        }
+        if (J < lay.Nv) {
+          PL_CHECK(timed(PL_KC_POTRF, 0.0, s,
+                         [&] { return launch_potrf(lay, mats, W, logdet, info, J, kk, s); }));
+          PL_CHECK(timed(PL_KC_TRSM, 0.0, s,
+                         [&] { return launch_trsm(lay, mats, W, info, J, lay.Nv - J, kk, s); }));
+        }
       }
-      if (J < lay.Nv) {
+    } else {
+      for (int J = 0; J < lay.Nv; ++J) {
+        // J = 0 has no update: the diagonal kernel then copies V's FP64 tile
+        const int nI = (J == 0) ? 1 : lay.Nv - J + 1;
+        PL_CHECK(timed(PL_KC_GEMM, kk * gemm_col_flops(lay, J, nI), s, [&] {
+          return launch_gemm_col_mx(lay, m32, m64, v_stride64(lay), dscr, info, J, nI, kk, s);
+        }));
         PL_CHECK(timed(PL_KC_POTRF, 0.0, s,
-                       [&] { return launch_potrf(lay, mats, W, logdet, info, J, kk, s); }));
+                       [&] { return launch_potrf_mx(lay, dscr, W32, logdet, info, J, kk, s); }));
         PL_CHECK(timed(PL_KC_TRSM, 0.0, s,
-                       [&] { return launch_trsm(lay, mats, W, info, J, lay.Nv - J, kk, s); }));
+                       [&] { return launch_trsm_mx(lay, m32, W32, info, J, lay.Nv - J, kk, s); }));
       }
+      PL_CHECK(timed(PL_KC_OTHER, 0.0, s, [&] {
+        hipError_t e = launch_backsolve(lay, m32, W32, info, x0, kk, s);
+        if (e == hipSuccess)
+          e = launch_qform(lay, m64, v_stride64(lay), x0, rhs, info, slots, refine, kk, s);
+        return e;
+      }));
     }
     PL_CHECK(timed(PL_KC_OTHER, 0.0, s, [&] {
-      return launch_finalize(lay, mats, logdet, info, jac, flags, lam_d, (int)n, (int)p, (int)M,
-                             kk, out + c0 * M, beta_hat ? beta_hat + c0 * M * p : nullptr, s);
+      hipError_t e = launch_finalize(lay, mats, slots, logdet, info, jac, yflags, lam_d, (int)n,
+                                     (int)p, (int)M, kk, out + c0 * M,
+                                     beta_hat ? beta_hat + c0 * M * p : nullptr, s);
+      if (e == hipSuccess) e = launch_copy_i32(info, info_all + c0, kk, s);
+      return e;
     }));
+  }
+
+  if (mixed && !(flags & PL_OPT_NO_FALLBACK)) {
+    // Points whose FP32 factorisation broke down are redone with the FP64 form
+    // into their own records, then flagged.
+    std::vector<int32_t> hinfo(K);
+    if (hipMemcpyAsync(hinfo.data(), info_all, K * sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return PL_E_HIP;
+    pl_opts o64{};
+    o64.precision = PL_FP64;
+    o64.chunk = 1;
+    for (int64_t k = 0; k < K; ++k) {
+      if (hinfo[k] > 0) {
+        const int rc = pl_profile_loglik(locs, y, X, n, p, omega + 5 * k, 1, lambda, M,
+                                         out + k * M, beta_hat ? beta_hat + k * M * p : nullptr,
+                                         &o64, work, work_bytes, stream);
+        if (rc != PL_OK) return rc;
+        PL_CHECK(launch_mark_fallback(out + k * M, (int)M, s));
+      }
+    }
   }
   return PL_OK;
 }

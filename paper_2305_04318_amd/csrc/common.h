@@ -99,9 +99,29 @@ hipError_t launch_boxcox_rhs(const double* y, const double* X, const double* lam
                              hipStream_t s);
 hipError_t launch_border_init(const Lay& lay, double* mats, const double* rhs, int K,
                               hipStream_t s);
-hipError_t launch_finalize(const Lay& lay, const double* mats, const double* logdet,
-                           const int32_t* info, const double* jac, const int32_t* flags,
-                           const double* lam, int n, int p, int M, int K,
+hipError_t launch_finalize(const Lay& lay, const double* mats, const double* slots,
+                           const double* logdet, const int32_t* info, const double* jac,
+                           const int32_t* flags, const double* lam, int n, int p, int M, int K,
                            pl_result* out, double* beta, hipStream_t s);
+// mixed form
+hipError_t launch_matern_mixed(const Lay& lay, double* m64, int64_t stride64, float* m32,
+                               const double* locs, const MaternParams* mp, const double* tables,
+                               int K, hipStream_t s);
+hipError_t launch_border_init_f32(const Lay& lay, float* mats, const double* rhs, int K,
+                                  hipStream_t s);
+hipError_t launch_gemm_col_mx(const Lay& lay, float* m32, const double* m64, int64_t m64stride,
+                              double* dscratch, const int32_t* info, int J, int nI, int K,
+                              hipStream_t s);
+hipError_t launch_potrf_mx(const Lay& lay, double* dscratch, float* W32, double* logdet,
+                           int32_t* info, int J, int K, hipStream_t s);
+hipError_t launch_trsm_mx(const Lay& lay, float* m32, const float* W32, const int32_t* info, int J,
+                          int nI, int K, hipStream_t s);
+hipError_t launch_backsolve(const Lay& lay, const float* m32, const float* W32,
+                            const int32_t* info, double* X, int K, hipStream_t s);
+hipError_t launch_qform(const Lay& lay, const double* m64, int64_t stride64, const double* X,
+                        const double* rhs, const int32_t* info, double* slots, int refine, int K,
+                        hipStream_t s);
+hipError_t launch_mark_fallback(pl_result* out, int M, hipStream_t s);
+hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int n, hipStream_t s);
 
 }  // namespace plk

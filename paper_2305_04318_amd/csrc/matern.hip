@@ -118,10 +118,12 @@ hipError_t launch_cheb_tables(const MaternParams* mp, double* nodes, double* tab
 // omega's table are staged in LDS; thread (r, h) owns row r of the tile and
 // every other column, so each column store is one contiguous 1 KB run.
 
-template <int MODE>  // 0: packed tiles (full diagonal tiles); 1: column-major, lower only
+// MODE 0: packed FP64 tiles (full diagonal tiles); MODE 1: column-major,
+// lower triangle only; MODE 2: packed FP64 tiles plus an FP32 copy.
+template <int MODE>
 __device__ __forceinline__ void matern_tile(const MaternParams& P, const double* tab,
                                             const double* __restrict__ locs, int n, int I, int J,
-                                            double* C, int64_t ldc, const double* cx,
+                                            double* C, int64_t ldc, float* C32, const double* cx,
                                             const double* cy) {
   const int r = threadIdx.x & (T - 1);
   const int hh = threadIdx.x >> 7;
@@ -143,11 +145,14 @@ __device__ __forceinline__ void matern_tile(const MaternParams& P, const double*
       v = rho_eval(P, tab, a * a + b * b);
     }
     C[(int64_t)c * ldc + r] = v;
+    if (MODE == 2) C32[(int64_t)c * ldc + r] = (float)v;
   }
 }
 
 template <int MODE>
 __global__ __launch_bounds__(256) void k_matern(Lay lay, double* __restrict__ mats,
+                                                int64_t stride64, float* __restrict__ m32,
+                                                int64_t stride32,
                                                 const double* __restrict__ locs,
                                                 const MaternParams* __restrict__ mp,
                                                 const double* __restrict__ tables, int ntiles,
@@ -170,8 +175,10 @@ __global__ __launch_bounds__(256) void k_matern(Lay lay, double* __restrict__ ma
   }
   __syncthreads();
   const MaternParams P = mp[k];
-  double* C = mats + (int64_t)k * lay.mstride + lay.tile_off(I, J);
-  matern_tile<MODE>(P, tab, locs, lay.n, I, J, C, lay.tile_ld(I), cx, cy);
+  const int64_t off = lay.tile_off(I, J);
+  double* C = mats + (int64_t)k * stride64 + off;
+  float* C32 = (MODE == 2) ? m32 + (int64_t)k * stride32 + off : nullptr;
+  matern_tile<MODE>(P, tab, locs, lay.n, I, J, C, lay.tile_ld(I), C32, cx, cy);
 }
 
 hipError_t launch_matern_packed(const Lay& lay, double* mats, const double* locs,
@@ -179,7 +186,18 @@ hipError_t launch_matern_packed(const Lay& lay, double* mats, const double* locs
                                 hipStream_t s) {
   const int ntiles = lay.Nv * (lay.Nv + 1) / 2;
   const int G = K * ntiles;
-  hipLaunchKernelGGL(k_matern<0>, dim3(G), dim3(256), 0, s, lay, mats, locs, mp, tables, ntiles, G);
+  hipLaunchKernelGGL(k_matern<0>, dim3(G), dim3(256), 0, s, lay, mats, lay.mstride, (float*)nullptr,
+                     (int64_t)0, locs, mp, tables, ntiles, G);
+  return hipGetLastError();
+}
+
+hipError_t launch_matern_mixed(const Lay& lay, double* m64, int64_t stride64, float* m32,
+                               const double* locs, const MaternParams* mp, const double* tables,
+                               int K, hipStream_t s) {
+  const int ntiles = lay.Nv * (lay.Nv + 1) / 2;
+  const int G = K * ntiles;
+  hipLaunchKernelGGL(k_matern<2>, dim3(G), dim3(256), 0, s, lay, m64, stride64, m32, lay.mstride,
+                     locs, mp, tables, ntiles, G);
   return hipGetLastError();
 }
 
@@ -194,7 +212,8 @@ hipError_t launch_matern_colmajor(double* V, int64_t ld, int n, const double* lo
   lay.mstride = ld * (int64_t)n;
   const int ntiles = lay.Nv * (lay.Nv + 1) / 2;
   const int G = K * ntiles;
-  hipLaunchKernelGGL(k_matern<1>, dim3(G), dim3(256), 0, s, lay, V, locs, mp, tables, ntiles, G);
+  hipLaunchKernelGGL(k_matern<1>, dim3(G), dim3(256), 0, s, lay, V, lay.mstride, (float*)nullptr,
+                     (int64_t)0, locs, mp, tables, ntiles, G);
   return hipGetLastError();
 }
 

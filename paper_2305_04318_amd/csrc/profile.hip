@@ -86,18 +86,19 @@ hipError_t launch_boxcox_rhs(const double* y, const double* X, const double* lam
 
 // Copy the right-hand sides into each omega's bordered tile row (column i of
 // the bordered panel is rhs row i) and clear the final TB x TB tile.
-__global__ void k_border_init(Lay lay, double* __restrict__ mats, const double* __restrict__ rhs,
+template <typename TS>
+__global__ void k_border_init(Lay lay, TS* __restrict__ mats, const double* __restrict__ rhs,
                               int K) {
   const int64_t per = (int64_t)lay.n * lay.TB + (int64_t)lay.TB * lay.TB;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= per * K) return;
   const int k = (int)(idx / per);
   const int64_t e = idx % per;
-  double* base = mats + (int64_t)k * lay.mstride;
+  TS* base = mats + (int64_t)k * lay.mstride;
   if (e < (int64_t)lay.n * lay.TB) {
-    base[lay.tile_off(lay.Nv, 0) + e] = rhs[e];
+    base[lay.tile_off(lay.Nv, 0) + e] = (TS)rhs[e];
   } else {
-    base[lay.tile_off(lay.Nv, lay.Nv) + (e - (int64_t)lay.n * lay.TB)] = 0.0;
+    base[lay.tile_off(lay.Nv, lay.Nv) + (e - (int64_t)lay.n * lay.TB)] = (TS)0;
   }
 }
 
@@ -105,8 +106,232 @@ hipError_t launch_border_init(const Lay& lay, double* mats, const double* rhs, i
                               hipStream_t s) {
   const int64_t per = (int64_t)lay.n * lay.TB + (int64_t)lay.TB * lay.TB;
   const int64_t total = per * K;
-  hipLaunchKernelGGL(k_border_init, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, lay,
-                     mats, rhs, K);
+  hipLaunchKernelGGL(k_border_init<double>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                     lay, mats, rhs, K);
+  return hipGetLastError();
+}
+
+hipError_t launch_border_init_f32(const Lay& lay, float* mats, const double* rhs, int K,
+                                  hipStream_t s) {
+  const int64_t per = (int64_t)lay.n * lay.TB + (int64_t)lay.TB * lay.TB;
+  const int64_t total = per * K;
+  hipLaunchKernelGGL(k_border_init<float>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                     lay, mats, rhs, K);
+  return hipGetLastError();
+}
+
+// ---- mixed form: back substitution x0 = L^-T Z (one workgroup per omega) -------
+// The FP32 factorisation leaves Z^T = (L^-1 B)^T in the bordered tile row.
+// Sweeping tile rows from the bottom: R_I = Z_I - sum_{J>I} L_JI^T X_J, then
+// X_I = W_I^T R_I with the stored FP32 inverse W_I = L_II^-1.  Thread (r, h)
+// owns row r of the tile and columns h, h+2, ... of the TB right-hand sides.
+// x0 is written in FP64 (n x TB rows, like the right-hand-side array).
+constexpr int BS_MAXC = 16;  // accumulators per thread: TB <= 32
+
+__global__ __launch_bounds__(256) void k_backsolve(Lay lay, const float* __restrict__ m32,
+                                                   const float* __restrict__ W32,
+                                                   const int32_t* __restrict__ info,
+                                                   double* __restrict__ X) {
+  __shared__ float Ls[T * (T + 1)];
+  __shared__ float Xs[T * 32];
+  const int k = blockIdx.x;
+  if (info[k] != 0) return;
+  const int tid = threadIdx.x, r = tid & (T - 1), h = tid >> 7;
+  const int TB = lay.TB, Nv = lay.Nv;
+  const int nc = TB / 2;
+  const float* base = m32 + (int64_t)k * lay.mstride;
+  const float* Wk = W32 + (int64_t)k * Nv * T * T;
+  double* Xk = X + (int64_t)k * lay.n * TB;
+  for (int I = Nv - 1; I >= 0; --I) {
+    const int ri = lay.rows(I);
+    float acc[BS_MAXC];
+    const float* Zt = base + lay.tile_off(Nv, I);   // TB x T, ld TB
+#pragma unroll
+    for (int m = 0; m < BS_MAXC; ++m) acc[m] = (m < nc && r < ri) ? Zt[(int64_t)r * TB + h + 2 * m] : 0.0f;
+    for (int J = I + 1; J < Nv; ++J) {
+      const int rj = lay.rows(J);
+      const float* Lt = base + lay.tile_off(J, I);  // rows: J-block, cols: I-block, ld T
+      // Ls[c][rr] padded, c = row of L_JI (J-block), rr = column (I-block)
+      for (int q = tid; q < T * T / 4; q += 256) {
+        const int idx = 4 * q, col = idx / T, row = idx % T;
+        const float4 v = *reinterpret_cast<const float4*>(Lt + idx);
+        float* dst = Ls + col * (T + 1) + row;
+        dst[0] = (row + 0 < rj) ? v.x : 0.0f;
+        dst[1] = (row + 1 < rj) ? v.y : 0.0f;
+        dst[2] = (row + 2 < rj) ? v.z : 0.0f;
+        dst[3] = (row + 3 < rj) ? v.w : 0.0f;
+      }
+      for (int idx = tid; idx < T * TB; idx += 256) {
+        const int c = idx / TB, a = idx % TB;
+        Xs[c * TB + a] = (c < rj) ? (float)Xk[(int64_t)(J * T + c) * TB + a] : 0.0f;
+      }
+      __syncthreads();
+      const float* lrow = Ls + r * (T + 1);
+      for (int c = 0; c < rj; ++c) {
+        const float l = lrow[c];
+#pragma unroll
+        for (int m = 0; m < BS_MAXC; ++m)
+          if (m < nc) acc[m] -= l * Xs[c * TB + h + 2 * m];
+      }
+      __syncthreads();
+    }
+    // X_I = W_I^T R
+    const float* Wt = Wk + (int64_t)I * T * T;
+    for (int q = tid; q < T * T / 4; q += 256) {
+      const int idx = 4 * q, col = idx / T, row = idx % T;
+      const float4 v = *reinterpret_cast<const float4*>(Wt + idx);
+      float* dst = Ls + col * (T + 1) + row;
+      dst[0] = v.x;
+      dst[1] = v.y;
+      dst[2] = v.z;
+      dst[3] = v.w;
+    }
+#pragma unroll
+    for (int m = 0; m < BS_MAXC; ++m)
+      if (m < nc) Xs[r * TB + h + 2 * m] = acc[m];
+    __syncthreads();
+    const float* wrow = Ls + r * (T + 1);
+    float out[BS_MAXC];
+#pragma unroll
+    for (int m = 0; m < BS_MAXC; ++m) out[m] = 0.0f;
+    for (int c = 0; c < ri; ++c) {
+      const float w = wrow[c];
+#pragma unroll
+      for (int m = 0; m < BS_MAXC; ++m)
+        if (m < nc) out[m] += w * Xs[c * TB + h + 2 * m];
+    }
+    if (r < ri) {
+#pragma unroll
+      for (int m = 0; m < BS_MAXC; ++m)
+        if (m < nc) Xk[(int64_t)(I * T + r) * TB + h + 2 * m] = (double)out[m];
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_backsolve(const Lay& lay, const float* m32, const float* W32,
+                            const int32_t* info, double* X, int K, hipStream_t s) {
+  hipLaunchKernelGGL(k_backsolve, dim3(K), dim3(256), 0, s, lay, m32, W32, info, X);
+  return hipGetLastError();
+}
+
+// ---- mixed form: FP64 quadratic forms from x0 -------------------------------
+// For SPD V the functional f(x) = 2 B^T x - x^T V x is maximised at x = V^-1 B
+// with value B^T V^-1 B, and f(x*) - f(x0) = (x*-x0)^T V (x*-x0): evaluating f
+// at the FP32 solution x0 in FP64 against the FP64 V gives the cross products
+// with an error second order in the solve error -- the effect of one FP64
+// refinement step on the quadratic forms.  With refine = 0 the first-order
+// B^T x0 is returned instead.  Workgroup (k, I) produces tile row I's share:
+//   2 B_I^T x0_I - [x0_I^T (V_II x0_I) + x0_I^T Y_I + Y_I^T x0_I],
+//   Y_I = sum_{J<I} V_IJ x0_J  (V read once, as lower tiles),
+// written to slot (k, I); the finalize sums the slots in a fixed order.
+__global__ __launch_bounds__(256) void k_qform(Lay lay, const double* __restrict__ m64,
+                                               int64_t stride64, const double* __restrict__ X,
+                                               const double* __restrict__ rhs,
+                                               const int32_t* __restrict__ info,
+                                               double* __restrict__ slots, int refine) {
+  extern __shared__ double qsm[];  // 3 x T x TB doubles: x0 tile, Y_low, Y_diag
+  const int TB = lay.TB, nc = TB / 2;
+  double* Xs = qsm;
+  double* YL = qsm + T * TB;
+  double* YD = qsm + 2 * T * TB;
+  const int k = blockIdx.x / lay.Nv;
+  const int I = blockIdx.x % lay.Nv;
+  if (info[k] != 0) return;
+  const int tid = threadIdx.x, r = tid & (T - 1), h = tid >> 7;
+  const int ri = lay.rows(I);
+  const double* Xk = X + (int64_t)k * lay.n * TB;
+  double* slot = slots + ((int64_t)k * lay.Nv + I) * TB * TB;
+  if (refine) {
+    double yl[BS_MAXC], yd[BS_MAXC];
+#pragma unroll
+    for (int m = 0; m < BS_MAXC; ++m) yl[m] = yd[m] = 0.0;
+    const double* Vk = m64 + (int64_t)k * stride64;
+    for (int J = 0; J <= I; ++J) {
+      const int rj = lay.rows(J);
+      for (int idx = tid; idx < T * TB; idx += 256) {
+        const int c = idx / TB, a = idx % TB;
+        Xs[idx] = (c < rj) ? Xk[(int64_t)(J * T + c) * TB + a] : 0.0;
+      }
+      __syncthreads();
+      const double* Vt = Vk + lay.tile_off(I, J);  // column-major, ld T
+      double y[BS_MAXC];
+#pragma unroll
+      for (int m = 0; m < BS_MAXC; ++m) y[m] = 0.0;
+      if (r < ri) {
+        // 16 independent column loads in flight per thread
+        for (int c0 = 0; c0 < rj; c0 += 16) {
+          double v[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) v[u] = (c0 + u < rj) ? Vt[(int64_t)(c0 + u) * T + r] : 0.0;
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const double* xr = Xs + (c0 + u) * TB + h;
+#pragma unroll
+            for (int m = 0; m < BS_MAXC; ++m)
+              if (m < nc) y[m] += v[u] * xr[2 * m];
+          }
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < BS_MAXC; ++m) {
+        if (J < I) yl[m] += y[m];
+        else yd[m] = y[m];
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int m = 0; m < BS_MAXC; ++m) {
+      if (m < nc) {
+        YL[r * TB + h + 2 * m] = yl[m];
+        YD[r * TB + h + 2 * m] = yd[m];
+      }
+    }
+  }
+  for (int idx = tid; idx < T * TB; idx += 256) {
+    const int c = idx / TB;
+    Xs[idx] = (c < ri) ? Xk[(int64_t)(I * T) * TB + idx] : 0.0;
+  }
+  __syncthreads();
+  const double* Bi = rhs + (int64_t)(I * T) * TB;
+  for (int pair = tid; pair < TB * TB; pair += 256) {
+    const int a = pair / TB, b = pair % TB;
+    double acc = 0.0;
+    for (int rr = 0; rr < ri; ++rr) {
+      const double xa = Xs[rr * TB + a], xb = Xs[rr * TB + b];
+      double v = (refine ? 2.0 : 1.0) * Bi[(int64_t)rr * TB + a] * xb;
+      if (refine) v -= xa * (YL[rr * TB + b] + YD[rr * TB + b]) + YL[rr * TB + a] * xb;
+      acc += v;
+    }
+    slot[pair] = acc;
+  }
+}
+
+hipError_t launch_qform(const Lay& lay, const double* m64, int64_t stride64, const double* X,
+                        const double* rhs, const int32_t* info, double* slots, int refine, int K,
+                        hipStream_t s) {
+  const size_t lds = (size_t)3 * T * lay.TB * sizeof(double);
+  hipLaunchKernelGGL(k_qform, dim3(K * lay.Nv), dim3(256), lds, s, lay, m64, stride64, X, rhs, info,
+                     slots, refine);
+  return hipGetLastError();
+}
+
+// OR the fallback flag into every record of omega k (after an FP64 redo).
+__global__ void k_mark_fallback(pl_result* out, int M) {
+  for (int m = threadIdx.x; m < M; m += blockDim.x) out[m].info |= PL_INFO_FALLBACK;
+}
+hipError_t launch_mark_fallback(pl_result* out, int M, hipStream_t s) {
+  hipLaunchKernelGGL(k_mark_fallback, dim3(1), dim3(64), 0, s, out, M);
+  return hipGetLastError();
+}
+
+__global__ void k_copy_i32(const int32_t* __restrict__ src, int32_t* __restrict__ dst, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_i32, dim3((n + 255) / 256), dim3(256), 0, s, src, dst, n);
   return hipGetLastError();
 }
 
@@ -118,6 +343,7 @@ hipError_t launch_border_init(const Lay& lay, double* mats, const double* rhs, i
 //   ssqBetahat_m = c_m^T c_m          (Step 7)
 //   ssqResidual_m = ssqY_m - ssqBetahat_m (Step 8); beta-hat = Q^-T c_m.
 __global__ __launch_bounds__(64) void k_finalize(Lay lay, const double* __restrict__ mats,
+                                                 const double* __restrict__ slots,
                                                  const double* __restrict__ logdet,
                                                  const int32_t* __restrict__ info,
                                                  const double* __restrict__ jac,
@@ -127,12 +353,27 @@ __global__ __launch_bounds__(64) void k_finalize(Lay lay, const double* __restri
                                                  double* __restrict__ beta) {
   __shared__ double Q[PL_MAX_P * PL_MAX_P];
   __shared__ double cm[PL_MAX_M * PL_MAX_P];
+  __shared__ double Sr[32 * 32];
   __shared__ int rank_bad;
   __shared__ double ldx;
   const int k = blockIdx.x;
   const int tid = threadIdx.x;
   const int TB = lay.TB;
+  // S holds minus the cross products: the Schur tile of the bordered FP64
+  // factorisation, or (mixed form) minus the symmetrised sum of the refined slots
   const double* S = mats + (int64_t)k * lay.mstride + lay.tile_off(lay.Nv, lay.Nv);
+  if (slots) {
+    const double* sk = slots + (int64_t)k * lay.Nv * TB * TB;
+    for (int pr = tid; pr < TB * TB; pr += 64) {
+      const int a = pr / TB, b = pr % TB;
+      double v = 0.0;
+      for (int I = 0; I < lay.Nv; ++I)
+        v += sk[(int64_t)I * TB * TB + a * TB + b] + sk[(int64_t)I * TB * TB + b * TB + a];
+      Sr[b * TB + a] = -0.5 * v;
+    }
+    __syncthreads();
+    S = Sr;
+  }
   const double J = jac[0];
   const int inf = info[k];
   const bool bady = flags[0] != 0;
@@ -234,12 +475,12 @@ __global__ __launch_bounds__(64) void k_finalize(Lay lay, const double* __restri
   }
 }
 
-hipError_t launch_finalize(const Lay& lay, const double* mats, const double* logdet,
-                           const int32_t* info, const double* jac, const int32_t* flags,
-                           const double* lam, int n, int p, int M, int K, pl_result* out,
-                           double* beta, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(K), dim3(64), 0, s, lay, mats, logdet, info, jac, flags, lam,
-                     n, p, M, out, beta);
+hipError_t launch_finalize(const Lay& lay, const double* mats, const double* slots,
+                           const double* logdet, const int32_t* info, const double* jac,
+                           const int32_t* flags, const double* lam, int n, int p, int M, int K,
+                           pl_result* out, double* beta, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(K), dim3(64), 0, s, lay, mats, slots, logdet, info, jac,
+                     flags, lam, n, p, M, out, beta);
   return hipGetLastError();
 }
 

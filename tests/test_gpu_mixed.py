@@ -1,0 +1,85 @@
+"""Mixed-precision form against the FP64 oracle: |delta l| <= 1e-2 absolute
+(well inside the 1.92 half-width of a 95% chi-square(1) likelihood interval),
+the effect of the FP64 refinement of the cross products, and the FP64
+fallback for points whose FP32 factorisation breaks down."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+TOL_LL = 1e-2
+
+
+def _run(pl, pr, **kw):
+    res = pl.profile_loglik(pr.locs, pr.y, pr.X, pr.omega, pr.lam, return_beta=True, **kw)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in res.items()}
+
+
+@pytest.mark.parametrize("n,p,K,M,seed", [(300, 2, 4, 3, 11), (700, 4, 4, 8, 12), (1100, 3, 3, 4, 13)])
+def test_mixed_parity(plprof_lib, n, p, K, M, seed):
+    pl = plprof_lib
+    pr = synth.small_problem(n, p=p, K=K, M=M, seed=seed)
+    got = _run(pl, pr, precision="mixed")
+    ref, refb = oracle.profile_loglik(pr.locs, pr.y, pr.X, pr.omega, pr.lam, return_beta=True)
+    assert np.all((got["info"] & ~pl.PL_INFO_FALLBACK) == 0)
+    dll = np.abs(got["loglik"] - ref["loglik"])
+    print(f"n={n}: max |dl| = {dll.max():.2e}, max |d logdet| = "
+          f"{np.abs(got['logdet_v'] - ref['logdet_v']).max():.2e}, max |d beta| = "
+          f"{np.abs(got['beta'] - refb).max():.2e}")
+    assert dll.max() <= TOL_LL
+    assert np.abs(got["loglik_reml"] - ref["loglik_reml"]).max() <= TOL_LL
+    np.testing.assert_allclose(got["beta"], refb, rtol=0, atol=1e-3 * max(1.0, np.abs(refb).max()))
+
+
+def test_refinement_reduces_error(plprof_lib):
+    pl = plprof_lib
+    pr = synth.small_problem(900, p=3, K=4, M=4, seed=21)
+    ref = oracle.profile_loglik(pr.locs, pr.y, pr.X, pr.omega, pr.lam)
+    e1 = np.abs(_run(pl, pr, precision="mixed", refine=1)["ssq_resid"] - ref["ssq_resid"]) / ref["ssq_resid"]
+    e0 = np.abs(_run(pl, pr, precision="mixed", refine=0)["ssq_resid"] - ref["ssq_resid"]) / ref["ssq_resid"]
+    print(f"relative SSR error: refined {e1.max():.2e}, unrefined {e0.max():.2e}")
+    assert e1.max() < e0.max()
+
+
+def test_mixed_full_size_sampled(plprof_lib):
+    # n=4000, K=256, M=8 (the mixed-precision workload), a seeded sample of
+    # omega points against the oracle
+    pl = plprof_lib
+    pr = synth.config_mixed()
+    got = _run(pl, pr, precision="mixed")
+    ok = (got["info"] & ~pl.PL_INFO_FALLBACK) == 0
+    assert np.all(ok)
+    idx = np.random.default_rng(1).choice(pr.K, 3, replace=False)
+    ref, refb = oracle.profile_loglik(pr.locs, pr.y, pr.X, pr.omega[idx], pr.lam, return_beta=True)
+    dll = np.abs(got["loglik"][idx] - ref["loglik"])
+    print(f"n=4000 sample: max |dl| = {dll.max():.2e}, fallbacks = "
+          f"{int(np.sum((got['info'][:, 0] & pl.PL_INFO_FALLBACK) != 0))}")
+    assert dll.max() <= TOL_LL
+
+
+def test_fallback_redoes_fp32_breakdowns_in_fp64(plprof_lib):
+    # duplicated locations in different tiles with a tiny nugget: V is SPD in
+    # FP64 but the FP32 Schur complements lose positivity
+    pl = plprof_lib
+    pr = synth.small_problem(260, p=2, K=3, M=2, seed=31)
+    locs = pr.locs.copy()
+    for i in range(0, 40):
+        locs[130 + i] = locs[i] + 1e-9
+    om = pr.omega.copy()
+    om[1] = [2.0, 2.5, 1e-7, 1.0, 0.0]
+    got = pl.profile_loglik(locs, pr.y, pr.X, om, pr.lam, precision="mixed")
+    torch.cuda.synchronize()
+    info = got["info"].cpu().numpy()
+    ll = got["loglik"].cpu().numpy()
+    ref = oracle.profile_loglik(locs, pr.y, pr.X, om, pr.lam)
+    assert ref["info"][1, 0] == 0, "the constructed point must be SPD in FP64"
+    fb = (info[1] & pl.PL_INFO_FALLBACK) != 0
+    assert np.all(fb), "expected the FP32 factorisation of point 1 to break down"
+    assert np.all((info[1] & ~pl.PL_INFO_FALLBACK) == 0)
+    scale = np.maximum(np.abs(ref["loglik"][1]), pr.n)
+    assert np.max(np.abs(ll[1] - ref["loglik"][1]) / scale) <= 1e-8
+    assert np.max(np.abs(ll[[0, 2]] - ref["loglik"][[0, 2]])) <= TOL_LL
