@@ -82,7 +82,7 @@ size_t per_omega_bytes_mixed(const Lay& lay) {
   return align_up(lay.mstride * sizeof(float)) + align_up(v_stride64(lay) * sizeof(double)) +
          align_up((size_t)lay.Nv * T * T * sizeof(float)) + align_up((size_t)T * T * sizeof(double)) +
          align_up((size_t)lay.n * lay.TB * sizeof(double)) +
-         align_up((size_t)lay.Nv * lay.TB * lay.TB * sizeof(double)) + 2 * ALIGN;
+         align_up((size_t)lay.Nv * (lay.Nv + 1) / 2 * lay.TB * lay.TB * sizeof(double)) + 2 * ALIGN;
 }
 
 size_t fixed_bytes(int64_t n, int64_t K, int64_t M, const Lay& lay) {
@@ -349,7 +349,7 @@ int pl_profile_loglik(const double* locs, const double* y, const double* X, int6
     W32 = cv.take<float>((size_t)kc * lay.Nv * T * T * sizeof(float));
     dscr = cv.take<double>((size_t)kc * T * T * sizeof(double));
     x0 = cv.take<double>((size_t)kc * n * lay.TB * sizeof(double));
-    slots = cv.take<double>((size_t)kc * lay.Nv * lay.TB * lay.TB * sizeof(double));
+    slots = cv.take<double>((size_t)kc * lay.Nv * (lay.Nv + 1) / 2 * lay.TB * lay.TB * sizeof(double));
   }
   double* logdet = cv.take<double>((size_t)kc * sizeof(double));
   int32_t* info = cv.take<int32_t>((size_t)kc * sizeof(int32_t));

@@ -23,6 +23,7 @@
 // item i % 4.  The kernels pass the B-panel fragment as the first operand, so
 // sixteen consecutive lanes hold 16 consecutive rows of one result column.
 #include <math.h>
+#include <stdlib.h>
 
 #include "common.h"
 
@@ -348,8 +349,19 @@ __global__ __launch_bounds__(256, 2) void k_gemm_col(Lay lay, double* __restrict
 // sums are accumulated in FP64, subtracted from V's FP64 tile and rounded to
 // FP32 once.  The diagonal tile: FP64 MFMA on the FP32 panels, subtracted from
 // the FP64 tile of V, written to an FP64 scratch tile for k_potrf.
-constexpr int MX_FLUSH = 2;  // FP32 MFMA k-steps (8 products) per FP64 flush
-template <bool VEC>
+constexpr int MX_FLUSH = 4;  // FP32 MFMA k-steps (16 products) per FP64 flush (default)
+
+// FP64 flush interval of the mixed update: MX_FLUSH, or 1/2/4/8 from the
+// environment variable PLPROF_MX_FLUSH (an accuracy/speed study knob).
+static int mx_flush() {
+  static int v = [] {
+    const char* e = getenv("PLPROF_MX_FLUSH");
+    const int f = e ? atoi(e) : MX_FLUSH;
+    return (f == 1 || f == 2 || f == 4 || f == 8) ? f : MX_FLUSH;
+  }();
+  return v;
+}
+template <bool VEC, int FLUSH>
 __global__ __launch_bounds__(256, 2) void k_gemm_col_mx(Lay lay, float* __restrict__ m32,
                                                         const double* __restrict__ m64,
                                                         int64_t m64stride,
@@ -371,8 +383,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_col_mx(Lay lay, float* __restri
   const bool act = ni > 0 && nj > 0;
   d4 acc[4][4];
   zero_acc<double>(acc);
-  wg_gemm_nt_f32x64<MX_FLUSH>(acc, lds, base + lay.tile_off(I, 0), lay.tile_ld(I), arows,
-                              base + lay.tile_off(J, 0), lay.tile_ld(J), brows, kmax, act, ni, nj);
+  wg_gemm_nt_f32x64<FLUSH>(acc, lds, base + lay.tile_off(I, 0), lay.tile_ld(I), arows,
+                           base + lay.tile_off(J, 0), lay.tile_ld(J), brows, kmax, act, ni, nj);
   if (act) {
     const int64_t ldc = lay.tile_ld(I);
     float* C = base + lay.tile_off(I, J) + 64 * wr + 64 * wc * ldc;
@@ -439,8 +451,23 @@ hipError_t launch_gemm_col_mx(const Lay& lay, float* m32, const double* m64, int
                      dscratch, info, J);
   if (nI > 1) {
     const int G = K * (nI - 1);
-    hipLaunchKernelGGL(k_gemm_col_mx<true>, dim3(G), dim3(256), 0, s, lay, m32, m64, m64stride,
-                       info, J, nI - 1, G);
+    switch (mx_flush()) {
+      case 1:
+        hipLaunchKernelGGL((k_gemm_col_mx<true, 1>), dim3(G), dim3(256), 0, s, lay, m32, m64,
+                           m64stride, info, J, nI - 1, G);
+        break;
+      case 4:
+        hipLaunchKernelGGL((k_gemm_col_mx<true, 4>), dim3(G), dim3(256), 0, s, lay, m32, m64,
+                           m64stride, info, J, nI - 1, G);
+        break;
+      case 8:
+        hipLaunchKernelGGL((k_gemm_col_mx<true, 8>), dim3(G), dim3(256), 0, s, lay, m32, m64,
+                           m64stride, info, J, nI - 1, G);
+        break;
+      default:
+        hipLaunchKernelGGL((k_gemm_col_mx<true, 2>), dim3(G), dim3(256), 0, s, lay, m32, m64,
+                           m64stride, info, J, nI - 1, G);
+    }
   }
   return hipGetLastError();
 }
@@ -694,6 +721,83 @@ hipError_t launch_trsm_mx(const Lay& lay, float* m32, const float* W32, const in
   const int64_t ws = (int64_t)lay.Nv * T * T;
   hipLaunchKernelGGL((k_trsm<float, true>), dim3(G), dim3(256), 0, s, lay, m32,
                      W32 + (int64_t)J * T * T, info, J, nI, G, ws);
+  return hipGetLastError();
+}
+
+// ---- mixed form: FP64 cross products from x0 -------------------------------------
+// For SPD V the functional f(x) = 2 B^T x - x^T V x is maximised at x = V^-1 B
+// with value B^T V^-1 B, and f(x*) - f(x0) = (x*-x0)^T V (x*-x0): evaluating f
+// at the FP32-solve x0 in FP64 against the FP64 V gives the cross products with
+// an error second order in the solve error -- one FP64 refinement step applied
+// to the quadratic forms.  With refine = 0 the first-order B^T x0 is used.
+// Workgroup (omega, lower tile (I,J)) writes its q x q share to its own slot:
+//   Y = V_IJ x0_J on MFMA f64 (the GEMM core, x0 as a TB x T column-major panel),
+//   M = x0_I^T Y;  slot = -(M + M^T) for I > J,  2 B_I^T x0_I - M for I = J.
+// The slots are summed in a fixed order by k_finalize (deterministic).
+__global__ __launch_bounds__(256, 2) void k_qform(Lay lay, const double* __restrict__ m64,
+                                                  int64_t stride64, const double* __restrict__ X,
+                                                  const double* __restrict__ rhs,
+                                                  const int32_t* __restrict__ info,
+                                                  double* __restrict__ slots, int refine,
+                                                  int ntile, int G) {
+  __shared__ __attribute__((aligned(16))) char lds_raw[GEMM_LDS_BYTES];
+  double* lds = reinterpret_cast<double*>(lds_raw);
+  const int wg = xcd_remap(blockIdx.x, G);
+  const int k = wg / ntile;
+  const int t = wg % ntile;
+  int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while (I * (I + 1) / 2 > t) --I;
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  const int J = t - I * (I + 1) / 2;
+  if (info[k] != 0) return;  // uniform for the workgroup
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int TB = lay.TB, q = lay.q;
+  const int ri = lay.rows(I), rj = lay.rows(J);
+  const double* Xk = X + (int64_t)k * lay.n * TB;
+  double* slot = slots + ((int64_t)k * ntile + t) * TB * TB;
+  const double* Xi = Xk + (int64_t)I * T * TB;   // x0_I: element (r, a) at r*TB + a
+  double* Ys = lds;                              // Y, column-major T x TB, after the core
+  if (refine) {
+    const int war = ri - 64 * wr, wbr = q - 64 * wc;
+    const int ni = nblk(war), nj = nblk(wbr);
+    const bool act = ni > 0 && nj > 0;
+    d4 acc[4][4];
+    zero_acc<double>(acc);
+    wg_gemm_nt<double, double, true>(acc, lds, m64 + (int64_t)k * stride64 + lay.tile_off(I, J), T,
+                                     ri, Xk + (int64_t)J * T * TB, TB, q, rj, act, ni, nj);
+    // the core ends with a barrier: the LDS stages are free for Y
+    if (act) store64<double, false>(Ys + 64 * wr + 64 * wc * T, T, Ys + 64 * wr + 64 * wc * T, T,
+                                    acc, war, wbr, lane);
+    __syncthreads();
+  }
+  const double* Bi = rhs + (int64_t)I * T * TB;
+  for (int pr = tid; pr < TB * TB; pr += 256) {
+    const int a = pr / TB, b = pr % TB;
+    double v = 0.0;
+    if (refine) {
+      double mab = 0.0, mba = 0.0, bx = 0.0;
+      for (int r = 0; r < ri; ++r) {
+        const double xa = Xi[r * TB + a], xb = Xi[r * TB + b];
+        mab += xa * Ys[b * T + r];
+        mba += xb * Ys[a * T + r];
+        if (I == J) bx += Bi[r * TB + a] * xb;
+      }
+      v = (I > J) ? -(mab + mba) : 2.0 * bx - mab;
+    } else if (I == J) {
+      for (int r = 0; r < ri; ++r) v += Bi[r * TB + a] * Xi[r * TB + b];
+    }
+    slot[pr] = v;
+  }
+}
+
+hipError_t launch_qform(const Lay& lay, const double* m64, int64_t stride64, const double* X,
+                        const double* rhs, const int32_t* info, double* slots, int refine, int K,
+                        hipStream_t s) {
+  const int ntile = lay.Nv * (lay.Nv + 1) / 2;
+  const int G = K * ntile;
+  hipLaunchKernelGGL(k_qform, dim3(G), dim3(256), 0, s, lay, m64, stride64, X, rhs, info, slots,
+                     refine, ntile, G);
   return hipGetLastError();
 }
 

@@ -120,199 +120,119 @@ hipError_t launch_border_init_f32(const Lay& lay, float* mats, const double* rhs
   return hipGetLastError();
 }
 
-// ---- mixed form: back substitution x0 = L^-T Z (one workgroup per omega) -------
-// The FP32 factorisation leaves Z^T = (L^-1 B)^T in the bordered tile row.
-// Sweeping tile rows from the bottom: R_I = Z_I - sum_{J>I} L_JI^T X_J, then
-// X_I = W_I^T R_I with the stored FP32 inverse W_I = L_II^-1.  Thread (r, h)
-// owns row r of the tile and columns h, h+2, ... of the TB right-hand sides.
-// x0 is written in FP64 (n x TB rows, like the right-hand-side array).
-constexpr int BS_MAXC = 16;  // accumulators per thread: TB <= 32
+// ---- mixed form: back substitution x0 = L^-T Z -----------------------------------
+// The FP32 factorisation leaves Z^T = (L^-1 B)^T in the bordered tile row.  x0
+// (n rows of TB values, FP64) starts as Z and is swept from the bottom tile row:
+//   k_bs_diag(I)   : X_I <- W_I^T X_I           (W_I = L_II^-1, one workgroup per omega)
+//   k_bs_update(I) : X_J <- X_J - L_IJ^T X_I   (J < I, one workgroup per (omega, J))
+// Thread (r, h) owns row r of the output tile and columns h, h+2, ... (TB <= 32).
+constexpr int BS_MAXC = 16;
 
-__global__ __launch_bounds__(256) void k_backsolve(Lay lay, const float* __restrict__ m32,
-                                                   const float* __restrict__ W32,
-                                                   const int32_t* __restrict__ info,
-                                                   double* __restrict__ X) {
-  __shared__ float Ls[T * (T + 1)];
-  __shared__ float Xs[T * 32];
+__global__ void k_bs_init(Lay lay, const float* __restrict__ m32, const int32_t* __restrict__ info,
+                          double* __restrict__ X, int K) {
+  const int64_t per = (int64_t)lay.n * lay.TB;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= per * K) return;
+  const int k = (int)(idx / per);
+  const int64_t e = idx % per;
+  // bordered panel: element (a, i) at i*TB + a, the same index as x0 row i, column a
+  X[idx] = (double)m32[(int64_t)k * lay.mstride + lay.tile_off(lay.Nv, 0) + e];
+}
+
+// out[r][a] = sum_c M[c][r] Xin[c][a] for a T x T column-major tile M staged in
+// LDS with a padded stride (conflict-free reads along a row of M^T)
+__device__ __forceinline__ void stage_tile_t(float* Ls, const float* __restrict__ G, int valid_rows) {
+  for (int q = threadIdx.x; q < T * T / 4; q += blockDim.x) {
+    const int idx = 4 * q, col = idx / T, row = idx % T;
+    const float4 v = *reinterpret_cast<const float4*>(G + idx);
+    float* dst = Ls + col * (T + 1) + row;
+    dst[0] = (row + 0 < valid_rows) ? v.x : 0.0f;
+    dst[1] = (row + 1 < valid_rows) ? v.y : 0.0f;
+    dst[2] = (row + 2 < valid_rows) ? v.z : 0.0f;
+    dst[3] = (row + 3 < valid_rows) ? v.w : 0.0f;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_bs_diag(Lay lay, const float* __restrict__ W32,
+                                                 const int32_t* __restrict__ info,
+                                                 double* __restrict__ X, int I) {
+  extern __shared__ float bsm[];  // T x (T+1) tile + T x TB right-hand sides
+  float* Ls = bsm;
+  float* Xs = bsm + T * (T + 1);
   const int k = blockIdx.x;
   if (info[k] != 0) return;
   const int tid = threadIdx.x, r = tid & (T - 1), h = tid >> 7;
-  const int TB = lay.TB, Nv = lay.Nv;
-  const int nc = TB / 2;
-  const float* base = m32 + (int64_t)k * lay.mstride;
-  const float* Wk = W32 + (int64_t)k * Nv * T * T;
-  double* Xk = X + (int64_t)k * lay.n * TB;
-  for (int I = Nv - 1; I >= 0; --I) {
-    const int ri = lay.rows(I);
-    float acc[BS_MAXC];
-    const float* Zt = base + lay.tile_off(Nv, I);   // TB x T, ld TB
+  const int TB = lay.TB, nc = TB / 2, ri = lay.rows(I);
+  double* Xi = X + (int64_t)k * lay.n * TB + (int64_t)I * T * TB;
+  stage_tile_t(Ls, W32 + ((int64_t)k * lay.Nv + I) * T * T, T);
+  for (int idx = tid; idx < T * TB; idx += 256) {
+    const int c = idx / TB;
+    Xs[idx] = (c < ri) ? (float)Xi[idx] : 0.0f;
+  }
+  __syncthreads();
+  const float* wrow = Ls + r * (T + 1);
+  float out[BS_MAXC];
 #pragma unroll
-    for (int m = 0; m < BS_MAXC; ++m) acc[m] = (m < nc && r < ri) ? Zt[(int64_t)r * TB + h + 2 * m] : 0.0f;
-    for (int J = I + 1; J < Nv; ++J) {
-      const int rj = lay.rows(J);
-      const float* Lt = base + lay.tile_off(J, I);  // rows: J-block, cols: I-block, ld T
-      // Ls[c][rr] padded, c = row of L_JI (J-block), rr = column (I-block)
-      for (int q = tid; q < T * T / 4; q += 256) {
-        const int idx = 4 * q, col = idx / T, row = idx % T;
-        const float4 v = *reinterpret_cast<const float4*>(Lt + idx);
-        float* dst = Ls + col * (T + 1) + row;
-        dst[0] = (row + 0 < rj) ? v.x : 0.0f;
-        dst[1] = (row + 1 < rj) ? v.y : 0.0f;
-        dst[2] = (row + 2 < rj) ? v.z : 0.0f;
-        dst[3] = (row + 3 < rj) ? v.w : 0.0f;
-      }
-      for (int idx = tid; idx < T * TB; idx += 256) {
-        const int c = idx / TB, a = idx % TB;
-        Xs[c * TB + a] = (c < rj) ? (float)Xk[(int64_t)(J * T + c) * TB + a] : 0.0f;
-      }
-      __syncthreads();
-      const float* lrow = Ls + r * (T + 1);
-      for (int c = 0; c < rj; ++c) {
-        const float l = lrow[c];
-#pragma unroll
-        for (int m = 0; m < BS_MAXC; ++m)
-          if (m < nc) acc[m] -= l * Xs[c * TB + h + 2 * m];
-      }
-      __syncthreads();
-    }
-    // X_I = W_I^T R
-    const float* Wt = Wk + (int64_t)I * T * T;
-    for (int q = tid; q < T * T / 4; q += 256) {
-      const int idx = 4 * q, col = idx / T, row = idx % T;
-      const float4 v = *reinterpret_cast<const float4*>(Wt + idx);
-      float* dst = Ls + col * (T + 1) + row;
-      dst[0] = v.x;
-      dst[1] = v.y;
-      dst[2] = v.z;
-      dst[3] = v.w;
-    }
+  for (int m = 0; m < BS_MAXC; ++m) out[m] = 0.0f;
+  for (int c = 0; c < ri; ++c) {
+    const float w = wrow[c];
 #pragma unroll
     for (int m = 0; m < BS_MAXC; ++m)
-      if (m < nc) Xs[r * TB + h + 2 * m] = acc[m];
-    __syncthreads();
-    const float* wrow = Ls + r * (T + 1);
-    float out[BS_MAXC];
-#pragma unroll
-    for (int m = 0; m < BS_MAXC; ++m) out[m] = 0.0f;
-    for (int c = 0; c < ri; ++c) {
-      const float w = wrow[c];
-#pragma unroll
-      for (int m = 0; m < BS_MAXC; ++m)
-        if (m < nc) out[m] += w * Xs[c * TB + h + 2 * m];
-    }
-    if (r < ri) {
-#pragma unroll
-      for (int m = 0; m < BS_MAXC; ++m)
-        if (m < nc) Xk[(int64_t)(I * T + r) * TB + h + 2 * m] = (double)out[m];
-    }
-    __syncthreads();
+      if (m < nc) out[m] += w * Xs[c * TB + h + 2 * m];
   }
+  if (r < ri) {
+#pragma unroll
+    for (int m = 0; m < BS_MAXC; ++m)
+      if (m < nc) Xi[r * TB + h + 2 * m] = (double)out[m];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_bs_update(Lay lay, const float* __restrict__ m32,
+                                                   const int32_t* __restrict__ info,
+                                                   double* __restrict__ X, int I) {
+  extern __shared__ float bsm[];
+  float* Ls = bsm;
+  float* Xs = bsm + T * (T + 1);
+  const int k = blockIdx.x / I;
+  const int J = blockIdx.x % I;
+  if (info[k] != 0) return;
+  const int tid = threadIdx.x, r = tid & (T - 1), h = tid >> 7;
+  const int TB = lay.TB, nc = TB / 2, ri = lay.rows(I);
+  const double* Xi = X + (int64_t)k * lay.n * TB + (int64_t)I * T * TB;
+  double* Xj = X + (int64_t)k * lay.n * TB + (int64_t)J * T * TB;
+  // tile (I, J): rows in block I (the contraction index), columns in block J
+  stage_tile_t(Ls, m32 + (int64_t)k * lay.mstride + lay.tile_off(I, J), ri);
+  for (int idx = tid; idx < T * TB; idx += 256) {
+    const int c = idx / TB;
+    Xs[idx] = (c < ri) ? (float)Xi[idx] : 0.0f;
+  }
+  __syncthreads();
+  const float* lrow = Ls + r * (T + 1);
+  float out[BS_MAXC];
+#pragma unroll
+  for (int m = 0; m < BS_MAXC; ++m) out[m] = 0.0f;
+  for (int c = 0; c < ri; ++c) {
+    const float l = lrow[c];
+#pragma unroll
+    for (int m = 0; m < BS_MAXC; ++m)
+      if (m < nc) out[m] += l * Xs[c * TB + h + 2 * m];
+  }
+  // tile row J < I is complete (T rows)
+#pragma unroll
+  for (int m = 0; m < BS_MAXC; ++m)
+    if (m < nc) Xj[r * TB + h + 2 * m] -= (double)out[m];
 }
 
 hipError_t launch_backsolve(const Lay& lay, const float* m32, const float* W32,
                             const int32_t* info, double* X, int K, hipStream_t s) {
-  hipLaunchKernelGGL(k_backsolve, dim3(K), dim3(256), 0, s, lay, m32, W32, info, X);
-  return hipGetLastError();
-}
-
-// ---- mixed form: FP64 quadratic forms from x0 -------------------------------
-// For SPD V the functional f(x) = 2 B^T x - x^T V x is maximised at x = V^-1 B
-// with value B^T V^-1 B, and f(x*) - f(x0) = (x*-x0)^T V (x*-x0): evaluating f
-// at the FP32 solution x0 in FP64 against the FP64 V gives the cross products
-// with an error second order in the solve error -- the effect of one FP64
-// refinement step on the quadratic forms.  With refine = 0 the first-order
-// B^T x0 is returned instead.  Workgroup (k, I) produces tile row I's share:
-//   2 B_I^T x0_I - [x0_I^T (V_II x0_I) + x0_I^T Y_I + Y_I^T x0_I],
-//   Y_I = sum_{J<I} V_IJ x0_J  (V read once, as lower tiles),
-// written to slot (k, I); the finalize sums the slots in a fixed order.
-__global__ __launch_bounds__(256) void k_qform(Lay lay, const double* __restrict__ m64,
-                                               int64_t stride64, const double* __restrict__ X,
-                                               const double* __restrict__ rhs,
-                                               const int32_t* __restrict__ info,
-                                               double* __restrict__ slots, int refine) {
-  extern __shared__ double qsm[];  // 3 x T x TB doubles: x0 tile, Y_low, Y_diag
-  const int TB = lay.TB, nc = TB / 2;
-  double* Xs = qsm;
-  double* YL = qsm + T * TB;
-  double* YD = qsm + 2 * T * TB;
-  const int k = blockIdx.x / lay.Nv;
-  const int I = blockIdx.x % lay.Nv;
-  if (info[k] != 0) return;
-  const int tid = threadIdx.x, r = tid & (T - 1), h = tid >> 7;
-  const int ri = lay.rows(I);
-  const double* Xk = X + (int64_t)k * lay.n * TB;
-  double* slot = slots + ((int64_t)k * lay.Nv + I) * TB * TB;
-  if (refine) {
-    double yl[BS_MAXC], yd[BS_MAXC];
-#pragma unroll
-    for (int m = 0; m < BS_MAXC; ++m) yl[m] = yd[m] = 0.0;
-    const double* Vk = m64 + (int64_t)k * stride64;
-    for (int J = 0; J <= I; ++J) {
-      const int rj = lay.rows(J);
-      for (int idx = tid; idx < T * TB; idx += 256) {
-        const int c = idx / TB, a = idx % TB;
-        Xs[idx] = (c < rj) ? Xk[(int64_t)(J * T + c) * TB + a] : 0.0;
-      }
-      __syncthreads();
-      const double* Vt = Vk + lay.tile_off(I, J);  // column-major, ld T
-      double y[BS_MAXC];
-#pragma unroll
-      for (int m = 0; m < BS_MAXC; ++m) y[m] = 0.0;
-      if (r < ri) {
-        // 16 independent column loads in flight per thread
-        for (int c0 = 0; c0 < rj; c0 += 16) {
-          double v[16];
-#pragma unroll
-          for (int u = 0; u < 16; ++u) v[u] = (c0 + u < rj) ? Vt[(int64_t)(c0 + u) * T + r] : 0.0;
-#pragma unroll
-          for (int u = 0; u < 16; ++u) {
-            const double* xr = Xs + (c0 + u) * TB + h;
-#pragma unroll
-            for (int m = 0; m < BS_MAXC; ++m)
-              if (m < nc) y[m] += v[u] * xr[2 * m];
-          }
-        }
-      }
-#pragma unroll
-      for (int m = 0; m < BS_MAXC; ++m) {
-        if (J < I) yl[m] += y[m];
-        else yd[m] = y[m];
-      }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int m = 0; m < BS_MAXC; ++m) {
-      if (m < nc) {
-        YL[r * TB + h + 2 * m] = yl[m];
-        YD[r * TB + h + 2 * m] = yd[m];
-      }
-    }
+  const int64_t total = (int64_t)lay.n * lay.TB * K;
+  hipLaunchKernelGGL(k_bs_init, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, lay, m32,
+                     info, X, K);
+  const size_t lds = (size_t)(T * (T + 1) + T * lay.TB) * sizeof(float);
+  for (int I = lay.Nv - 1; I >= 0; --I) {
+    hipLaunchKernelGGL(k_bs_diag, dim3(K), dim3(256), lds, s, lay, W32, info, X, I);
+    if (I > 0) hipLaunchKernelGGL(k_bs_update, dim3(K * I), dim3(256), lds, s, lay, m32, info, X, I);
   }
-  for (int idx = tid; idx < T * TB; idx += 256) {
-    const int c = idx / TB;
-    Xs[idx] = (c < ri) ? Xk[(int64_t)(I * T) * TB + idx] : 0.0;
-  }
-  __syncthreads();
-  const double* Bi = rhs + (int64_t)(I * T) * TB;
-  for (int pair = tid; pair < TB * TB; pair += 256) {
-    const int a = pair / TB, b = pair % TB;
-    double acc = 0.0;
-    for (int rr = 0; rr < ri; ++rr) {
-      const double xa = Xs[rr * TB + a], xb = Xs[rr * TB + b];
-      double v = (refine ? 2.0 : 1.0) * Bi[(int64_t)rr * TB + a] * xb;
-      if (refine) v -= xa * (YL[rr * TB + b] + YD[rr * TB + b]) + YL[rr * TB + a] * xb;
-      acc += v;
-    }
-    slot[pair] = acc;
-  }
-}
-
-hipError_t launch_qform(const Lay& lay, const double* m64, int64_t stride64, const double* X,
-                        const double* rhs, const int32_t* info, double* slots, int refine, int K,
-                        hipStream_t s) {
-  const size_t lds = (size_t)3 * T * lay.TB * sizeof(double);
-  hipLaunchKernelGGL(k_qform, dim3(K * lay.Nv), dim3(256), lds, s, lay, m64, stride64, X, rhs, info,
-                     slots, refine);
   return hipGetLastError();
 }
 
@@ -363,12 +283,13 @@ __global__ __launch_bounds__(64) void k_finalize(Lay lay, const double* __restri
   // factorisation, or (mixed form) minus the symmetrised sum of the refined slots
   const double* S = mats + (int64_t)k * lay.mstride + lay.tile_off(lay.Nv, lay.Nv);
   if (slots) {
-    const double* sk = slots + (int64_t)k * lay.Nv * TB * TB;
+    const int ntile = lay.Nv * (lay.Nv + 1) / 2;
+    const double* sk = slots + (int64_t)k * ntile * TB * TB;
     for (int pr = tid; pr < TB * TB; pr += 64) {
       const int a = pr / TB, b = pr % TB;
       double v = 0.0;
-      for (int I = 0; I < lay.Nv; ++I)
-        v += sk[(int64_t)I * TB * TB + a * TB + b] + sk[(int64_t)I * TB * TB + b * TB + a];
+      for (int t = 0; t < ntile; ++t)
+        v += sk[(int64_t)t * TB * TB + a * TB + b] + sk[(int64_t)t * TB * TB + b * TB + a];
       Sr[b * TB + a] = -0.5 * v;
     }
     __syncthreads();
