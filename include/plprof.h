@@ -176,6 +176,57 @@ int pl_profile_loglik(const double* locs, const double* y, const double* X,
                       size_t work_bytes, void* stream);
 
 /*
+ * Many independent datasets of uneven size (each with its own omega points)
+ * in one persistent launch (Section 3.3's Step 3 per (dataset, omega) unit;
+ * the paper's memory-bounded chunking of parameter sets, Section 3.3, becomes
+ * a pool of recycled matrix slabs).
+ *
+ * One dataset: locs (device, n x 2 row-major), y (device, n, > 0), X (device,
+ * n x p column-major), omega (host, K x 5), all shared lambda values.
+ */
+typedef struct pl_dataset {
+  const double* locs;
+  const double* y;
+  const double* X;
+  int64_t n;
+  const double* omega;
+  int64_t K;
+} pl_dataset;
+
+/* Opaque plan: the task list of every unit, its slab assignment and, after
+ * the first pl_batch_run, a captured HIP graph of the whole launch sequence. */
+typedef struct pl_batch pl_batch;
+
+/*
+ * Build a plan on the host (no GPU call).  opts->chunk, when > 0, caps the
+ * number of matrix slabs (default min(units, 2048)); only PL_FP64 is
+ * supported.  The plan keeps the dataset pointers, which must stay valid.
+ * Errors: -1 datasets NULL or a dataset invalid (n < 2, n <= p, pointers
+ * NULL, K < 1, omega out of domain), -2 D out of range, -3 p out of range,
+ * -4 lambda NULL or not finite, -5 M out of range, -6 bad option, -7 plan NULL;
+ * PL_E_UNSUPPORTED if the task list cannot be built.
+ */
+int pl_batch_create(const pl_dataset* datasets, int64_t D, int64_t p, const double* lambda,
+                    int64_t M, const pl_opts* opts, pl_batch** plan);
+int pl_batch_workspace_size(const pl_batch* plan, size_t* bytes);
+/* Units (sum of K over datasets), tasks and slabs of a plan (NULL to skip). */
+int pl_batch_stats(const pl_batch* plan, int64_t* units, int64_t* tasks, int64_t* slabs);
+/*
+ * Evaluate every record: out (device) receives sum_d K_d * M records, dataset
+ * by dataset, omega-major then lambda; beta_hat (device, or NULL) p doubles per
+ * record.  The first call (and any call with a different work, out or
+ * beta_hat) uploads the plan into the workspace and captures the launch
+ * sequence into a HIP graph; every call then launches that graph on `stream`.
+ * Errors: -1 plan NULL, -2 out NULL, -4 work NULL, -5 work too small, PL_E_HIP.
+ */
+int pl_batch_run(pl_batch* plan, pl_result* out, double* beta_hat, void* work, size_t work_bytes,
+                 void* stream);
+/* After the stream has been synchronised: *err = 1 if a task wait exceeded
+ * its bound (the results are then not valid), else 0.  Synchronous. */
+int pl_batch_error(const pl_batch* plan, void* work, int32_t* err);
+void pl_batch_destroy(pl_batch* plan);
+
+/*
  * Optional timing of the library's own kernels with HIP events recorded on
  * the caller's stream around every launch (benchmarks and tracing; off by
  * default, no cost when off).  Kernel classes:

@@ -13,7 +13,9 @@ PL_MAX_P, PL_MAX_M = 32, 64
 # every symbol the header declares
 EXPORTS = ("pl_version", "pl_error_string", "pl_workspace_size", "pl_matern_workspace_size",
            "pl_matern_cov", "pl_chol_workspace_size", "pl_chol_batched", "pl_profile_loglik",
-           "pl_profiling_enable", "pl_profiling_read")
+           "pl_profiling_enable", "pl_profiling_read", "pl_batch_create",
+           "pl_batch_workspace_size", "pl_batch_stats", "pl_batch_run", "pl_batch_error",
+           "pl_batch_destroy")
 KERNEL_CLASSES = ("tables", "matern", "gemm", "potrf", "trsm", "other")
 
 
@@ -33,6 +35,11 @@ class PlOpts(ctypes.Structure):
 
 
 PL_OPT_NO_FALLBACK = 1
+
+
+class PlDataset(ctypes.Structure):
+    _fields_ = [("locs", ctypes.c_void_p), ("y", ctypes.c_void_p), ("X", ctypes.c_void_p),
+                ("n", ctypes.c_int64), ("omega", ctypes.c_void_p), ("K", ctypes.c_int64)]
 
 
 class PlError(RuntimeError):
@@ -78,6 +85,20 @@ def load(path: str = None):
     lib.pl_profiling_read.restype = ctypes.c_int
     lib.pl_profiling_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+    lib.pl_batch_create.restype = ctypes.c_int
+    lib.pl_batch_create.argtypes = [ctypes.POINTER(PlDataset), _I64, _I64, _P, _I64,
+                                    ctypes.POINTER(PlOpts), ctypes.POINTER(ctypes.c_void_p)]
+    lib.pl_batch_workspace_size.restype = ctypes.c_int
+    lib.pl_batch_workspace_size.argtypes = [_P, ctypes.POINTER(_SZ)]
+    lib.pl_batch_stats.restype = ctypes.c_int
+    lib.pl_batch_stats.argtypes = [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
+                                   ctypes.POINTER(_I64)]
+    lib.pl_batch_run.restype = ctypes.c_int
+    lib.pl_batch_run.argtypes = [_P, _P, _P, _P, _SZ, _P]
+    lib.pl_batch_error.restype = ctypes.c_int
+    lib.pl_batch_error.argtypes = [_P, _P, ctypes.POINTER(ctypes.c_int32)]
+    lib.pl_batch_destroy.restype = None
+    lib.pl_batch_destroy.argtypes = [_P]
     if path is None:
         _lib = lib
     return lib

@@ -1,0 +1,83 @@
+"""Uneven batches of datasets in one persistent launch (pl_batch_* of the C ABI)."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import PlDataset, check, load
+from .api import Inputs, _host_f64, _opts, _stream_ptr, unpack_records
+
+
+class Batch:
+    """A plan over many datasets; run() evaluates every (dataset, omega, lambda)
+    record with one graph launch (a persistent kernel plus small prologue)."""
+
+    def __init__(self, problems, lam, device="cuda", max_slabs=0, inputs=None):
+        lib = load()
+        self.device = device
+        self.inputs = inputs if inputs is not None else [
+            Inputs(pr.locs, pr.y, pr.X, device) for pr in problems]
+        self.omegas = [_host_f64(pr.omega, 5) for pr in problems]
+        self.lam = _host_f64(lam).reshape(-1)
+        ps = {inp.p for inp in self.inputs}
+        if len(ps) != 1:
+            raise ValueError("all datasets must have the same number of covariates")
+        self.p = ps.pop()
+        D = len(self.inputs)
+        arr = (PlDataset * D)()
+        for i, (inp, om) in enumerate(zip(self.inputs, self.omegas)):
+            arr[i] = PlDataset(inp.locs.data_ptr(), inp.y.data_ptr(), inp.Xc.data_ptr(), inp.n,
+                               om.ctypes.data, om.shape[0])
+        self._arr = arr
+        o = _opts("fp64", max_slabs)
+        h = ctypes.c_void_p()
+        check(lib.pl_batch_create(arr, D, self.p, self.lam.ctypes.data_as(ctypes.c_void_p),
+                                  self.lam.shape[0], ctypes.byref(o), ctypes.byref(h)),
+              "pl_batch_create")
+        self._h = h
+        sz = ctypes.c_size_t(0)
+        check(lib.pl_batch_workspace_size(h, ctypes.byref(sz)), "pl_batch_workspace_size")
+        self.work = torch.empty(sz.value, dtype=torch.uint8, device=device)
+        u, t, s = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        check(lib.pl_batch_stats(h, ctypes.byref(u), ctypes.byref(t), ctypes.byref(s)),
+              "pl_batch_stats")
+        self.units, self.tasks, self.slabs = u.value, t.value, s.value
+        M = self.lam.shape[0]
+        self.offsets = np.concatenate([[0], np.cumsum([om.shape[0] for om in self.omegas])])
+        self.out = torch.empty((self.units, M, 10), dtype=torch.float64, device=device)
+        self.beta = torch.empty((self.units, M, self.p), dtype=torch.float64, device=device)
+
+    def run(self, stream=None):
+        rc = load().pl_batch_run(self._h, ctypes.c_void_p(self.out.data_ptr()),
+                                 ctypes.c_void_p(self.beta.data_ptr()),
+                                 ctypes.c_void_p(self.work.data_ptr()), self.work.numel(),
+                                 _stream_ptr(stream))
+        check(rc, "pl_batch_run")
+        return self
+
+    def error(self) -> int:
+        e = ctypes.c_int32(0)
+        check(load().pl_batch_error(self._h, ctypes.c_void_p(self.work.data_ptr()), ctypes.byref(e)),
+              "pl_batch_error")
+        return e.value
+
+    def records(self, i=None):
+        """Records of dataset i (dict of (K_i, M) tensors) or of all units."""
+        rec = self.out if i is None else self.out[self.offsets[i]:self.offsets[i + 1]]
+        out = unpack_records(rec)
+        out["beta"] = self.beta if i is None else self.beta[self.offsets[i]:self.offsets[i + 1]]
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pl_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,127 @@
+// Device side of the Matern correlation (Section 2.1): the quadrature
+// evaluation of K_kappa, the per-element table evaluation and the tile task.
+#pragma once
+
+#include <math.h>
+
+#include "common.h"
+
+namespace plk {
+
+// log(e^x K_nu(x)), x > 0, by the trapezoid rule on the even integrand of
+// DLMF 10.32.9 with a running log-sum-exp.  The step is a quarter of the
+// peak width ~ 1/sqrt(max(nu, x, 1)); the sum stops once the (unimodal)
+// log-integrand has dropped 60 below its maximum.
+static __device__ double log_scaled_kv_quad(double nu, double x) {
+  const double h = 0.25 / sqrt(fmax(fmax(nu, x), 1.0));
+  double m = -INFINITY, s = 0.0, prev = -INFINITY;
+  for (int k = 0; k < 400000; ++k) {
+    const double u = k * h;
+    const double sh = sinh(0.5 * u);
+    const double a = nu * u;
+    // -x (cosh u - 1) + log cosh(nu u)
+    const double f = -2.0 * x * sh * sh + a + log1p(exp(-2.0 * a)) - M_LN2;
+    const double w = (k == 0) ? 0.5 : 1.0;
+    if (f > m) {
+      s = s * exp(m - f) + w;
+      m = f;
+    } else {
+      s += w * exp(f - m);
+    }
+    if (f < m - 60.0 && f < prev) break;
+    prev = f;
+  }
+  return m + log(s * h);
+}
+
+// h(u) = log rho(x) + x at x = e^u, from the quadrature.
+static __device__ double h_direct(const MaternParams& P, double u) {
+  const double x = exp(u);
+  return P.log_norm + P.kappa * u + log_scaled_kv_quad(P.kappa, x);
+}
+
+// rho(x) for one element given the omega's table (NP*NC doubles).
+__device__ __forceinline__ double rho_eval(const MaternParams& P, const double* tab, double d2) {
+  const double x = P.sqrt8k * sqrt(d2);
+  if (x <= X_ZERO) return 1.0;
+  if (x >= P.x_hi) return 0.0;
+  if (x < X_LO) {
+    const double lr = P.log_norm + P.kappa * log(x) + log_scaled_kv_quad(P.kappa, x) - x;
+    return fmin(exp(lr), 1.0);
+  }
+  const double t = (log(x) - P.u_a) * P.inv_w;
+  // t lies in [0, NP) for finite x in [X_LO, x_hi); the clamp keeps the
+  // table read in bounds for any input (a NaN coordinate included)
+  int piece = (t >= 0.0 && t < (double)NP) ? (int)t : (t >= (double)NP ? NP - 1 : 0);
+  const double s = 2.0 * (t - (double)piece) - 1.0;
+  const double s2 = s + s;
+  const double* c = tab + piece * NC;
+  double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+  for (int mm = NC - 1; mm >= 1; --mm) {
+    const double tmp = fma(s2, b1, c[mm] - b2);
+    b2 = b1;
+    b1 = tmp;
+  }
+  const double hv = fma(s, b1, c[0] - b2);
+  return fmin(exp(hv - x), 1.0);
+}
+
+// ---- covariance tiles -----------------------------------------------------
+// One workgroup per (omega, lower tile (I,J)).  Column coordinates and the
+// omega's table are staged in LDS; thread (r, h) owns row r of the tile and
+// every other column, so each column store is one contiguous 1 KB run.
+
+// MODE 0: packed FP64 tiles (full diagonal tiles); MODE 1: column-major,
+// lower triangle only; MODE 2: packed FP64 tiles plus an FP32 copy.
+template <int MODE>
+__device__ __forceinline__ void matern_tile(const MaternParams& P, const double* tab,
+                                            const double* __restrict__ locs, int n, int I, int J,
+                                            double* C, int64_t ldc, float* C32, const double* cx,
+                                            const double* cy) {
+  const int r = threadIdx.x & (T - 1);
+  const int hh = threadIdx.x >> 7;
+  const int gi = I * T + r;
+  if (gi >= n) return;
+  const double xi = locs[2 * gi], yi = locs[2 * gi + 1];
+  const int cmax = min(T, n - J * T);
+  for (int c = hh; c < cmax; c += 2) {
+    const int gj = J * T + c;
+    if (MODE == 1 && gj > gi) continue;
+    double v;
+    if (gi == gj) {
+      v = 1.0 + P.nugget;
+    } else {
+      const double dx = xi - cx[c], dy = yi - cy[c];
+      const double u1 = P.cosA * dx - P.sinA * dy;
+      const double u2 = P.sinA * dx + P.cosA * dy;
+      const double a = u1 * P.inv_phix, b = u2 * P.inv_phiy;
+      v = rho_eval(P, tab, a * a + b * b);
+    }
+    C[(int64_t)c * ldc + r] = v;
+    if (MODE == 2) C32[(int64_t)c * ldc + r] = (float)v;
+  }
+}
+
+// One T x T tile (I, J) of V for one omega: the omega's table and the tile's
+// column coordinates are staged in smem (NP*NC + 2T doubles).  C points at the
+// tile (leading dimension ldc); MODE 2 also writes C32.
+template <int MODE>
+__device__ __forceinline__ void dev_matern_tile(const Lay& lay, const MaternParams& P,
+                                                const double* __restrict__ tab_g,
+                                                const double* __restrict__ locs, int I, int J,
+                                                double* C, int64_t ldc, float* C32, double* smem) {
+  double* tab = smem;
+  double* cx = smem + NP * NC;
+  double* cy = cx + T;
+  for (int i = threadIdx.x; i < NP * NC; i += blockDim.x) tab[i] = tab_g[i];
+  for (int i = threadIdx.x; i < T; i += blockDim.x) {
+    const int gj = J * T + i;
+    cx[i] = gj < lay.n ? locs[2 * gj] : 0.0;
+    cy[i] = gj < lay.n ? locs[2 * gj + 1] : 0.0;
+  }
+  __syncthreads();
+  matern_tile<MODE>(P, tab, locs, lay.n, I, J, C, ldc, C32, cx, cy);
+}
+
+}  // namespace plk

@@ -4,7 +4,7 @@
 // log-likelihood (equations "betahat", (4), "profile", Appendix "remlpro").
 #include <math.h>
 
-#include "common.h"
+#include "finalize_dev.h"
 
 namespace plk {
 
@@ -255,13 +255,9 @@ hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int n, hipStream_t 
   return hipGetLastError();
 }
 
-// ---- p x p stage ----------------------------------------------------------
-// One wave per omega.  The final tile holds S = -(y',X)^T V^-1 (y',X) (the
-// Schur complement of V in the bordered matrix), so ssqYX = -S:
-//   A = X^T V^-1 X = Q Q^T           (Step 5; log|X^T V^-1 X| = 2 sum log Q_ii)
-//   c_m = Q^-1 X^T V^-1 y'_m          (Step 6)
-//   ssqBetahat_m = c_m^T c_m          (Step 7)
-//   ssqResidual_m = ssqY_m - ssqBetahat_m (Step 8); beta-hat = Q^-T c_m.
+// ---- p x p stage (dev_finalize) -----------------------------------------------------
+// One wave per omega.  S: the Schur tile of the bordered FP64 factorisation, or
+// (mixed form) minus the symmetrised sum of the refined cross-product slots.
 __global__ __launch_bounds__(64) void k_finalize(Lay lay, const double* __restrict__ mats,
                                                  const double* __restrict__ slots,
                                                  const double* __restrict__ logdet,
@@ -271,16 +267,11 @@ __global__ __launch_bounds__(64) void k_finalize(Lay lay, const double* __restri
                                                  const double* __restrict__ lam, int n, int p,
                                                  int M, pl_result* __restrict__ out,
                                                  double* __restrict__ beta) {
-  __shared__ double Q[PL_MAX_P * PL_MAX_P];
-  __shared__ double cm[PL_MAX_M * PL_MAX_P];
+  __shared__ double smem[FIN_SMEM_DOUBLES];
   __shared__ double Sr[32 * 32];
-  __shared__ int rank_bad;
-  __shared__ double ldx;
   const int k = blockIdx.x;
   const int tid = threadIdx.x;
   const int TB = lay.TB;
-  // S holds minus the cross products: the Schur tile of the bordered FP64
-  // factorisation, or (mixed form) minus the symmetrised sum of the refined slots
   const double* S = mats + (int64_t)k * lay.mstride + lay.tile_off(lay.Nv, lay.Nv);
   if (slots) {
     const int ntile = lay.Nv * (lay.Nv + 1) / 2;
@@ -295,105 +286,8 @@ __global__ __launch_bounds__(64) void k_finalize(Lay lay, const double* __restri
     __syncthreads();
     S = Sr;
   }
-  const double J = jac[0];
-  const int inf = info[k];
-  const bool bady = flags[0] != 0;
-  const double LOG2PI = 1.8378770664093454836;
-  const double ldv = logdet[k];
-
-  if (!bady && inf == 0) {
-    // A (lower) into LDS: ssq(a,b) = -S[b*TB + a] for a >= b
-    for (int idx = tid; idx < p * p; idx += 64) {
-      const int i = idx / p, j = idx % p;
-      const int a = M + (i > j ? i : j), b = M + (i > j ? j : i);
-      Q[i * PL_MAX_P + j] = -S[(int64_t)b * TB + a];
-    }
-    __syncthreads();
-    if (tid == 0) {
-      // Cholesky of the p x p matrix (row-major, lower used)
-      int bad = 0;
-      double sl = 0.0;
-      for (int j = 0; j < p && !bad; ++j) {
-        double d = Q[j * PL_MAX_P + j];
-        for (int m = 0; m < j; ++m) d -= Q[j * PL_MAX_P + m] * Q[j * PL_MAX_P + m];
-        if (!(d > 0.0)) { bad = 1; break; }
-        const double l = sqrt(d);
-        Q[j * PL_MAX_P + j] = l;
-        sl += log(l);
-        for (int i = j + 1; i < p; ++i) {
-          double v = Q[i * PL_MAX_P + j];
-          for (int m = 0; m < j; ++m) v -= Q[i * PL_MAX_P + m] * Q[j * PL_MAX_P + m];
-          Q[i * PL_MAX_P + j] = v / l;
-        }
-      }
-      rank_bad = bad;
-      ldx = 2.0 * sl;
-    }
-    __syncthreads();
-  } else {
-    if (tid == 0) { rank_bad = 0; ldx = NAN; }
-    __syncthreads();
-  }
-
-  for (int m = tid; m < M; m += 64) {
-    pl_result rec;
-    rec.jacobian = J;
-    rec.pad = 0;
-    rec.logdet_v = ldv;
-    rec.logdet_xvx = ldx;
-    const double lm = lam[m];
-    if (bady) {
-      rec.loglik = NAN; rec.loglik_reml = NAN; rec.info = PL_INFO_BAD_Y;
-      rec.logdet_v = NAN; rec.logdet_xvx = NAN;
-      rec.ssq_y = rec.ssq_betahat = rec.ssq_resid = rec.sigma2_hat = NAN;
-    } else if (inf != 0) {
-      rec.loglik = -INFINITY; rec.loglik_reml = -INFINITY; rec.info = inf;
-      rec.logdet_v = NAN;
-      rec.ssq_y = rec.ssq_betahat = rec.ssq_resid = rec.sigma2_hat = NAN;
-    } else if (rank_bad) {
-      rec.loglik = NAN; rec.loglik_reml = NAN; rec.info = PL_INFO_RANK;
-      rec.ssq_y = -S[(int64_t)m * TB + m];
-      rec.ssq_betahat = rec.ssq_resid = rec.sigma2_hat = NAN;
-    } else {
-      double* c = cm + m * PL_MAX_P;
-      // c = Q^-1 B_m, B_m[i] = ssq(M+i, m) = -S[m*TB + M+i]
-      double ssb = 0.0;
-      for (int i = 0; i < p; ++i) {
-        double v = -S[(int64_t)m * TB + M + i];
-        for (int j = 0; j < i; ++j) v -= Q[i * PL_MAX_P + j] * c[j];
-        v /= Q[i * PL_MAX_P + i];
-        c[i] = v;
-        ssb += v * v;
-      }
-      const double ssy = -S[(int64_t)m * TB + m];
-      const double ssr = ssy - ssb;
-      const double s2 = ssr / n;
-      rec.ssq_y = ssy;
-      rec.ssq_betahat = ssb;
-      rec.ssq_resid = ssr;
-      rec.sigma2_hat = s2;
-      rec.info = 0;
-      rec.loglik = -0.5 * (n * log(s2) + ldv + n * LOG2PI + n) + (lm - 1.0) * J;
-      rec.loglik_reml = -0.5 * ((n - p) * log(ssr / (n - p)) + ldv + ldx + n * LOG2PI + n - p) +
-                        (lm - 1.0) * J;
-      if (beta) {
-        // beta-hat = Q^-T c (back substitution), written in place of c
-        double* bo = beta + ((int64_t)k * M + m) * p;
-        for (int i = p - 1; i >= 0; --i) {
-          double v = c[i];
-          for (int j = i + 1; j < p; ++j) v -= Q[j * PL_MAX_P + i] * c[j];
-          v /= Q[i * PL_MAX_P + i];
-          c[i] = v;
-        }
-        for (int i = 0; i < p; ++i) bo[i] = c[i];
-      }
-    }
-    if (beta && rec.info != 0) {
-      double* bo = beta + ((int64_t)k * M + m) * p;
-      for (int i = 0; i < p; ++i) bo[i] = NAN;
-    }
-    out[(int64_t)k * M + m] = rec;
-  }
+  dev_finalize(S, TB, logdet[k], info[k], jac[0], flags[0] != 0, lam, n, p, M,
+               out + (int64_t)k * M, beta ? beta + (int64_t)k * M * p : nullptr, smem);
 }
 
 hipError_t launch_finalize(const Lay& lay, const double* mats, const double* slots,

@@ -1,0 +1,512 @@
+// Device building blocks shared by the step kernels and the persistent batch
+// kernel: the MFMA GEMM core and the tile tasks of the blocked factorisation.
+#pragma once
+
+#include <math.h>
+
+#include "common.h"
+
+namespace plk {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+// ---- MFMA flavours -------------------------------------------------------------
+template <typename TC> struct MF;
+template <> struct MF<double> {
+  typedef d4 acc;
+  static __device__ __forceinline__ acc op(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // result column (within a 16x16 block) of accumulator item e in lane group lg
+  static __device__ __forceinline__ int col(int lg, int e) { return lg + 4 * e; }
+};
+template <> struct MF<float> {
+  typedef f4 acc;
+  static __device__ __forceinline__ acc op(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int col(int lg, int e) { return 4 * lg + e; }
+};
+
+// ---- 16-byte pieces of a column of a panel ---------------------------------------
+template <typename TS> struct Piece;
+template <> struct Piece<double> {
+  typedef dbl2 type;
+  static constexpr int N = 2;
+};
+template <> struct Piece<float> {
+  typedef flt4 type;
+  static constexpr int N = 4;
+};
+
+template <typename TS, bool VEC>
+__device__ __forceinline__ typename Piece<TS>::type fetch_piece(const TS* __restrict__ P, int64_t ld,
+                                                                int rows, int k, int kmax, int row) {
+  typedef typename Piece<TS>::type V;
+  constexpr int N = Piece<TS>::N;
+  V v;
+#pragma unroll
+  for (int e = 0; e < N; ++e) v[e] = (TS)0;
+  if (k < kmax) {
+    const TS* p = P + (int64_t)k * ld + row;
+    if (VEC && row + N - 1 < rows) {
+      v = *reinterpret_cast<const V*>(p);
+    } else {
+#pragma unroll
+      for (int e = 0; e < N; ++e)
+        if (row + e < rows) v[e] = p[e];
+    }
+  }
+  return v;
+}
+
+// ---- workgroup GEMM core: acc += A[0:128, 0:kmax] B[0:128, 0:kmax]^T ----------
+// 256 threads = 4 waves in a 2x2 grid, each owning a 64x64 quarter of the
+// 128x128 result as 4x4 MFMA blocks.  The k range is consumed in chunks of
+// KC = 128 / sizeof(TS) columns (16 KB per operand), double-buffered through
+// LDS: every thread fetches 4 + 4 16-byte pieces of the next chunk from
+// global memory while the waves run the current chunk's MFMAs, then writes
+// them to the other LDS stage; one barrier per chunk.  Rows at or beyond
+// arows / brows and columns at or beyond kmax read as zero.  TS is the storage
+// type, TC the MFMA type (float storage may be widened to FP64 MFMA).
+constexpr int LROW = T + 4;         // LDS stride per k column (elements)
+constexpr int GEMM_LDS_BYTES = 2 * 2 * 16 * LROW * 8;
+
+template <typename TS, typename TC, bool VEC>
+__device__ __forceinline__ void wg_gemm_nt(typename MF<TC>::acc (&acc)[4][4], TS* lds,
+                                           const TS* __restrict__ A, int64_t lda, int arows,
+                                           const TS* __restrict__ B, int64_t ldb, int brows,
+                                           int kmax, bool do_mfma, int ni, int nj) {
+  constexpr int N = Piece<TS>::N;
+  constexpr int KC = 128 / (int)sizeof(TS);
+  constexpr int PPC = T / N;  // pieces per column
+  typedef typename Piece<TS>::type V;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int nchunks = (kmax + KC - 1) / KC;
+  if (nchunks <= 0) return;
+  V ra[4], rb[4];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q;
+      const int col = idx / PPC, row = (idx % PPC) * N;
+      ra[q] = fetch_piece<TS, VEC>(A, lda, arows, k0 + col, kmax, row);
+      rb[q] = fetch_piece<TS, VEC>(B, ldb, brows, k0 + col, kmax, row);
+    }
+  };
+  auto stash = [&](int stage) {
+    TS* sa = lds + (stage * 2 + 0) * KC * LROW;
+    TS* sb = lds + (stage * 2 + 1) * KC * LROW;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q;
+      const int col = idx / PPC, row = (idx % PPC) * N;
+      *reinterpret_cast<V*>(sa + col * LROW + row) = ra[q];
+      *reinterpret_cast<V*>(sb + col * LROW + row) = rb[q];
+    }
+  };
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int c = 0; c < nchunks; ++c) {
+    const bool more = c + 1 < nchunks;
+    if (more) fetch((c + 1) * KC);
+    if (do_mfma) {
+      const TS* sa = lds + ((c & 1) * 2 + 0) * KC * LROW + 64 * wr + lr;
+      const TS* sb = lds + ((c & 1) * 2 + 1) * KC * LROW + 64 * wc + lr;
+#pragma unroll
+      for (int s4 = 0; s4 < KC / 4; ++s4) {
+        const int kk = 4 * s4 + lk;
+        TC a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          a[i] = (TC)sa[kk * LROW + 16 * i];
+          b[i] = (TC)sb[kk * LROW + 16 * i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (i < ni) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              if (j < nj) acc[i][j] = MF<TC>::op(b[j], a[i], acc[i][j]);
+          }
+        }
+      }
+    }
+    if (more) stash((c + 1) & 1);
+    __syncthreads();
+  }
+}
+
+// FP32 MFMA whose partial sums are flushed into FP64 accumulators every
+// FLUSH k-steps (FLUSH * 4 products): the FP32 rounding then only touches short
+// partial sums instead of the long running sums that cancel in the Schur
+// complements of an ill-conditioned V.  Same LDS pipeline as wg_gemm_nt.
+template <int FLUSH>
+__device__ __forceinline__ void wg_gemm_nt_f32x64(d4 (&acc)[4][4], float* lds,
+                                                  const float* __restrict__ A, int64_t lda,
+                                                  int arows, const float* __restrict__ B,
+                                                  int64_t ldb, int brows, int kmax, bool do_mfma,
+                                                  int ni, int nj) {
+  constexpr int N = 4;
+  constexpr int KC = 32;
+  constexpr int PPC = T / N;
+  typedef flt4 V;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int nchunks = (kmax + KC - 1) / KC;
+  if (nchunks <= 0) return;
+  V ra[4], rb[4];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q;
+      const int col = idx / PPC, row = (idx % PPC) * N;
+      ra[q] = fetch_piece<float, true>(A, lda, arows, k0 + col, kmax, row);
+      rb[q] = fetch_piece<float, true>(B, ldb, brows, k0 + col, kmax, row);
+    }
+  };
+  auto stash = [&](int stage) {
+    float* sa = lds + (stage * 2 + 0) * KC * LROW;
+    float* sb = lds + (stage * 2 + 1) * KC * LROW;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q;
+      const int col = idx / PPC, row = (idx % PPC) * N;
+      *reinterpret_cast<V*>(sa + col * LROW + row) = ra[q];
+      *reinterpret_cast<V*>(sb + col * LROW + row) = rb[q];
+    }
+  };
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int c = 0; c < nchunks; ++c) {
+    const bool more = c + 1 < nchunks;
+    if (more) fetch((c + 1) * KC);
+    if (do_mfma) {
+      const float* sa = lds + ((c & 1) * 2 + 0) * KC * LROW + 64 * wr + lr;
+      const float* sb = lds + ((c & 1) * 2 + 1) * KC * LROW + 64 * wc + lr;
+      // rolled: only one group's fragments and partial sums are live at a time
+#pragma unroll 1
+      for (int g = 0; g < KC / 4 / FLUSH; ++g) {
+        float a[FLUSH][4], b[FLUSH][4];
+#pragma unroll
+        for (int s4 = 0; s4 < FLUSH; ++s4) {
+          const int kk = 4 * (g * FLUSH + s4) + lk;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            a[s4][i] = sa[kk * LROW + 16 * i];
+            b[s4][i] = sb[kk * LROW + 16 * i];
+          }
+        }
+        // one block row at a time keeps only 4 FP32 partial blocks live
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (i < ni) {
+            f4 part[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) part[j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int s4 = 0; s4 < FLUSH; ++s4)
+#pragma unroll
+              for (int j = 0; j < 4; ++j)
+                if (j < nj) part[j] = MF<float>::op(b[s4][j], a[s4][i], part[j]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+              for (int e = 0; e < 4; ++e) acc[i][j][e] += (double)part[j][e];
+          }
+        }
+      }
+    }
+    if (more) stash((c + 1) & 1);
+    __syncthreads();
+  }
+}
+
+template <typename TC>
+__device__ __forceinline__ void zero_acc(typename MF<TC>::acc (&acc)[4][4]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[i][j][e] = (TC)0;
+}
+
+// Cout[r][c] = (SUB ? Cin[r][c] - acc : acc) for the valid part of a wave's
+// 64x64 tile; LAYOUT names the MFMA whose result layout acc follows.
+template <typename LAYOUT, bool SUB, typename TI, typename TO, typename ACC>
+__device__ __forceinline__ void store64_l(const TI* Cin, int64_t ldin, TO* Cout, int64_t ldout,
+                                          const ACC (&acc)[4][4], int arows, int brows, int lane) {
+  const int lr = lane & 15, lg = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = 16 * i + lr;
+    if (r >= arows) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = 16 * j + MF<LAYOUT>::col(lg, e);
+        if (c < brows) {
+          const double v = (double)acc[i][j][e];
+          TO* po = Cout + (int64_t)c * ldout + r;
+          if (SUB) *po = (TO)((double)Cin[(int64_t)c * ldin + r] - v);
+          else *po = (TO)v;
+        }
+      }
+    }
+  }
+}
+
+template <typename TC, bool SUB, typename TI, typename TO>
+__device__ __forceinline__ void store64(const TI* Cin, int64_t ldin, TO* Cout, int64_t ldout,
+                                        const typename MF<TC>::acc (&acc)[4][4], int arows,
+                                        int brows, int lane) {
+  const int lr = lane & 15, lg = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = 16 * i + lr;
+    if (r >= arows) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = 16 * j + MF<TC>::col(lg, e);
+        if (c < brows) {
+          const double v = (double)acc[i][j][e];
+          TO* po = Cout + (int64_t)c * ldout + r;
+          if (SUB) *po = (TO)((double)Cin[(int64_t)c * ldin + r] - v);
+          else *po = (TO)v;
+        }
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ int nblk(int rows) { return rows <= 0 ? 0 : min(4, (rows + 15) >> 4); }
+
+// ---- tile tasks -------------------------------------------------------------------
+
+// Left-looking update of tile (I, J), I >= J: C_IJ -= L_I,0:J L_J,0:J^T (FP64 MFMA).
+template <bool VEC>
+__device__ __forceinline__ void dev_gemm_col(const Lay& lay, double* base, int J, int I, double* lds) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int arows = lay.rows(I), brows = lay.rows(J);
+  const int war = arows - 64 * wr, wbr = brows - 64 * wc;
+  const int ni = nblk(war), nj = nblk(wbr);
+  const bool act = ni > 0 && nj > 0 && !(I == J && wc > wr);
+  const int kmax = min(J * T, lay.n);
+  d4 acc[4][4];
+  zero_acc<double>(acc);
+  wg_gemm_nt<double, double, VEC>(acc, lds, base + lay.tile_off(I, 0), lay.tile_ld(I), arows,
+                                  base + lay.tile_off(J, 0), lay.tile_ld(J), brows, kmax, act, ni,
+                                  nj);
+  if (act) {
+    const int64_t ldc = lay.tile_ld(I);
+    double* C = base + lay.tile_off(I, J) + 64 * wr + 64 * wc * ldc;
+    store64<double, true>(C, ldc, C, ldc, acc, war, wbr, lane);
+  }
+}
+
+// Panel solve of tile (I, J), I > J: L_IJ = C_IJ W^T with W = L_JJ^-1 (ld T).
+template <typename TS, bool VEC, int FLUSH>
+__device__ __forceinline__ void dev_trsm(const Lay& lay, TS* base, const TS* W, int J, int I, TS* lds) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int arows = lay.rows(I), brows = lay.rows(J);
+  const int war = arows - 64 * wr, wbr = brows - 64 * wc;
+  const int ni = nblk(war), nj = nblk(wbr);
+  const bool act = ni > 0 && nj > 0;
+  TS* Ct = base + lay.tile_off(I, J);
+  const int64_t ldc = lay.tile_ld(I);
+  TS* Co = Ct + 64 * wr + 64 * wc * ldc;
+  d4 acc[4][4];
+  zero_acc<double>(acc);
+  // the core's final barrier orders every read of C_IJ before the overwrite
+  if constexpr (sizeof(TS) == 8) {
+    wg_gemm_nt<TS, TS, VEC>(acc, lds, Ct, ldc, arows, W, T, brows, brows, act, ni, nj);
+    if (act) store64<double, false>(Co, ldc, Co, ldc, acc, war, wbr, lane);
+  } else {
+    wg_gemm_nt_f32x64<FLUSH>(acc, lds, Ct, ldc, arows, W, T, brows, brows, act, ni, nj);
+    if (act) store64_l<float, false>(Co, ldc, Co, ldc, acc, war, wbr, lane);
+  }
+}
+
+// Diagonal tile J: factor and invert, register-blocked.
+// Thread t owns the 8x8 block (rows 8*(t/16).., columns 8*(t%16)..) of the
+// unit-padded tile; LDS only broadcasts one column (and one row) per step, with
+// two alternating buffers so that a single barrier separates the steps.
+//  factor (right-looking): publish column j unscaled; every owner of a lower
+//    block updates a_rc -= a_rj a_cj / a_jj for c > j; owners of column j
+//    scale it by 1/sqrt(a_jj).
+//  inverse (in place, W = L^-1 row by row): at step m scale W's row m by
+//    1/L_mm (it then holds its final values), publish it and L's column m;
+//    W_rc -= L_rm W_mc for r > m, c < m; W_rm = -L_rm / L_mm; W_mm = 1/L_mm.
+// C (leading dimension ld) holds the tile's lower triangle.  MODE 0: L is
+// written back to C and W (FP64, ld T) to Wd.  MODE 1: C is read only and W is
+// written in FP32 to W32.  log|V| is added to *logdet_k; a non-positive pivot
+// sets *info_k and returns (uniformly).  smem: at least 5*T + 256 doubles.
+constexpr int POTRF_SMEM_DOUBLES = 5 * T + 256;
+
+template <int MODE>
+__device__ __forceinline__ void dev_potrf(const Lay& lay, double* C, int64_t ld, double* Wd,
+                                          float* W32, double* logdet_k, int32_t* info_k, int J,
+                                          double* smem) {
+  double (*bc0)[T] = reinterpret_cast<double (*)[T]>(smem);
+  double (*bc1)[T] = reinterpret_cast<double (*)[T]>(smem + 2 * T);
+  double* dinv = smem + 4 * T;
+  double* red = smem + 5 * T;
+  const int tid = threadIdx.x, bi = tid >> 4, bj = tid & 15;
+  const bool low = bi >= bj;
+  const int nv = lay.rows(J);
+  double a[8][8];
+#pragma unroll
+  for (int rr = 0; rr < 8; ++rr)
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc) {
+      const int r = 8 * bi + rr, c = 8 * bj + cc;
+      double v;
+      if (r < nv && c < nv) v = (r >= c) ? C[(int64_t)c * ld + r] : 0.0;
+      else v = (r == c) ? 1.0 : 0.0;
+      a[rr][cc] = v;
+    }
+
+  for (int jb = 0; jb < T / 8; ++jb) {
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) {
+      const int j = 8 * jb + jj;
+      const int buf = jj & 1;
+      if (bj == jb) {
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr) bc0[buf][8 * bi + rr] = a[rr][jj];
+      }
+      __syncthreads();
+      const double d = bc0[buf][j];
+      if (!(d > 0.0)) {  // the same value in every thread: uniform exit
+        if (tid == 0) *info_k = J * T + j + 1;
+        return;
+      }
+      if (low && bj >= jb) {
+        const double invd = 1.0 / d;
+        double cr[8], cc8[8];
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr) cr[rr] = bc0[buf][8 * bi + rr] * invd;
+        // columns c <= j of the owner block get a zero multiplier instead of a
+        // per-element branch, so the 64 FMAs run unconditionally
+#pragma unroll
+        for (int c8 = 0; c8 < 8; ++c8)
+          cc8[c8] = (bj > jb || c8 > jj) ? bc0[buf][8 * bj + c8] : 0.0;
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr)
+#pragma unroll
+          for (int c8 = 0; c8 < 8; ++c8) a[rr][c8] = fma(-cr[rr], cc8[c8], a[rr][c8]);
+        if (bj == jb) {
+          const double sc = 1.0 / sqrt(d);
+#pragma unroll
+          for (int rr = 0; rr < 8; ++rr)
+            if (bi > jb || rr >= jj) a[rr][jj] *= sc;
+        }
+      }
+    }
+  }
+
+  // log|V| contribution, 1/L_jj, and (FP64 form) the factor itself
+  double sl = 0.0;
+  if (bi == bj) {
+#pragma unroll
+    for (int rr = 0; rr < 8; ++rr) {
+      const int r = 8 * bi + rr;
+      if (r < nv) sl += log(a[rr][rr]);
+      dinv[r] = 1.0 / a[rr][rr];
+    }
+  }
+  red[tid] = sl;
+  if (MODE == 0 && low) {
+#pragma unroll
+    for (int rr = 0; rr < 8; ++rr)
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc) {
+        const int r = 8 * bi + rr, c = 8 * bj + cc;
+        if (r < nv && c < nv && r >= c) C[(int64_t)c * ld + r] = a[rr][cc];
+      }
+  }
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
+    __syncthreads();
+  }
+  if (tid == 0) *logdet_k += 2.0 * red[0];
+
+  for (int mb = 0; mb < T / 8; ++mb) {
+#pragma unroll
+    for (int mm = 0; mm < 8; ++mm) {
+      const int m = 8 * mb + mm;
+      const int buf = mm & 1;
+      if (low && bj == mb) {
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr) bc0[buf][8 * bi + rr] = a[rr][mm];
+      }
+      if (low && bi == mb) {
+        // row m of W is complete up to the factor 1/L_mm
+        const double dm = dinv[m];
+#pragma unroll
+        for (int c8 = 0; c8 < 8; ++c8) {
+          if (bj < mb || c8 < mm) a[mm][c8] *= dm;
+          bc1[buf][8 * bj + c8] = a[mm][c8];
+        }
+      }
+      __syncthreads();
+      const double wmm = dinv[m];
+      if (low && bi >= mb && bj <= mb) {
+        double lr[8], wv[8];
+        // rows r <= m and columns c >= m get zero multipliers (no branches)
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr) lr[rr] = (bi > mb || rr > mm) ? bc0[buf][8 * bi + rr] : 0.0;
+#pragma unroll
+        for (int c8 = 0; c8 < 8; ++c8) wv[c8] = (bj < mb || c8 < mm) ? bc1[buf][8 * bj + c8] : 0.0;
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr)
+#pragma unroll
+          for (int c8 = 0; c8 < 8; ++c8) a[rr][c8] = fma(-lr[rr], wv[c8], a[rr][c8]);
+        if (bj == mb) {
+          // column m becomes W_rm = -L_rm / L_mm (r > m), W_mm = 1 / L_mm
+#pragma unroll
+          for (int rr = 0; rr < 8; ++rr) {
+            if (bi > mb || rr > mm) a[rr][mm] = -lr[rr] * wmm;
+          }
+          if (bi == mb) a[mm][mm] = wmm;
+        }
+      }
+    }
+  }
+  if (MODE == 0) {
+    double* W = Wd;
+#pragma unroll
+    for (int rr = 0; rr < 8; ++rr)
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc) {
+        const int r = 8 * bi + rr, c = 8 * bj + cc;
+        W[c * T + r] = (low && r >= c) ? a[rr][cc] : 0.0;
+      }
+  } else {
+    float* W = W32;
+#pragma unroll
+    for (int rr = 0; rr < 8; ++rr)
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc) {
+        const int r = 8 * bi + rr, c = 8 * bj + cc;
+        W[c * T + r] = (low && r >= c) ? (float)a[rr][cc] : 0.0f;
+      }
+  }
+}
+
+}  // namespace plk
