@@ -4,12 +4,20 @@
 A step is one pl_profile_loglik call over the whole anisotropic workload
 (n = 2000 locations, p = 4 covariates, K = 1024 omega points x M = 8 Box-Cox
 values = 8192 profile log-likelihoods; Matern build, bordered Cholesky,
-solves, cross products and the p x p stage), with the inputs already resident
-in HBM.  Prints one JSON line (rank 0, one GPU).
+solves, cross products and the p x p stage) in FP64, with the inputs already
+resident in HBM.  Prints one JSON line (one GPU).
+
+Beside the headline the line carries the other forms of the path, each on
+seeded synthetic inputs of the stated shape:
+  mixed_n2000   the mixed-precision form on the same inputs, with its
+                log-likelihood error against the FP64 records;
+  n4000, n8000  FP64 and mixed at n = 4000 (K = 256) and n = 8000 (K = 256);
+  uneven_batch  2048 datasets of n in [100, 1500] in one persistent launch;
+  serving       Poisson arrivals of requests of n in [500, 8000], p50/p99
+                latency and points/s for both forms.
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -19,36 +27,211 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("profile-loglik points/sec at n=2000 (FP64 vs mixed, |Δℓ|≤1e-2); "
           "p99 latency")
-PEAK_FP64_TFLOPS = 78.6    # MI355X dense FP64 matrix peak
-HBM_PEAK_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 matrix peak
+PEAK_FP32_TFLOPS = 157.3    # MI355X dense FP32 matrix peak
+EXTRAS = ("mixed", "n4000", "n8000", "batch", "serve")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(pr, n_omega, gpu_ll):
-    """The oracle as it stands, on a bounded sample of the same workload."""
-    import numpy as np
+# --------------------------------------------------------------------------
+# CPU baseline: the oracle, one omega point per task on a process pool with
+# one BLAS thread per worker.  Runs before the process touches the GPU.
+# --------------------------------------------------------------------------
+_CPU_PR = None
+
+
+def _oracle_point(k):
+    from threadpoolctl import threadpool_limits
 
     import oracle
-    try:
-        from threadpoolctl import threadpool_info
-        blas = [i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"]
-        cores = int(max(blas)) if blas else 1
-    except Exception:
-        cores = 1
-    idx = np.arange(n_omega)
+    pr = _CPU_PR
+    with threadpool_limits(1):
+        return k, oracle.profile_loglik(pr.locs, pr.y, pr.X, pr.omega[k:k + 1], pr.lam)["loglik"][0]
+
+
+def cpu_baseline(pr, n_omega, workers):
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    import numpy as np
+    global _CPU_PR
+    _CPU_PR = pr
     t0 = time.perf_counter()
-    ref = oracle.profile_loglik(pr.locs, pr.y, pr.X, pr.omega[idx], pr.lam)
+    ll = np.empty((n_omega, pr.M))
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+        for k, row in ex.map(_oracle_point, range(n_omega)):
+            ll[k] = row
     dt = time.perf_counter() - t0
     pts = n_omega * pr.M
-    err = float(np.max(np.abs(gpu_ll[idx] - ref["loglik"]) /
-                       np.maximum(np.abs(ref["loglik"]), pr.n)))
-    return {"value": pts / dt, "unit": "points/s", "cores": cores, "kind": "oracle",
+    return {"value": pts / dt, "unit": "points/s", "cores": workers, "kind": "oracle",
             "sample": (f"first {n_omega} of the {pr.K} omega points x {pr.M} lambdas at n={pr.n} "
-                       f"({pts} points, {dt:.1f} s; SciPy Bessel on one thread, LAPACK with "
-                       f"{cores} BLAS threads)")}, err
+                       f"({pts} points in {dt:.1f} s; one omega per task on {workers} processes, "
+                       f"one BLAS thread each; SciPy Bessel, LAPACK dpotrf)")}, ll
+
+
+# --------------------------------------------------------------------------
+# GPU legs
+# --------------------------------------------------------------------------
+
+def _pct(a, q):
+    import numpy as np
+    return float(np.percentile(a, q))
+
+
+def time_steps(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    return ts
+
+
+def run_form(pl, pr, precision, steps, warmup, chunk=0):
+    """Time `steps` calls of one form over problem `pr`; returns stats, records."""
+    import numpy as np
+    import torch
+    n, p, K, M = pr.n, pr.p, pr.K, pr.M
+    inp = pl.Inputs(pr.locs, pr.y, pr.X, device="cuda")
+    out = torch.empty((K, M, 10), dtype=torch.float64, device="cuda")
+    beta = torch.empty((K, M, p), dtype=torch.float64, device="cuda")
+    work = torch.empty(pl.workspace_size(n, p, K, M, precision, chunk), dtype=torch.uint8,
+                       device="cuda")
+
+    def step():
+        pl.profile_loglik(None, None, None, pr.omega, pr.lam, inputs=inp, out=out, beta=beta,
+                          return_beta=True, work=work, precision=precision, chunk=chunk)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    pl.profiling_enable(True)
+    ts = time_steps(step, steps, 0)
+    prof = pl.profiling_read()
+    pl.profiling_enable(False)
+    rec = {k: v.cpu().numpy() for k, v in pl.unpack_records(out).items()}
+    rec["beta"] = beta.cpu().numpy()
+    med = float(np.median(ts))
+    st = {"precision": precision, "n": n, "K": K, "M": M,
+          "ms_median": med, "ms_p10": _pct(ts, 10), "ms_p90": _pct(ts, 90),
+          "points_per_s": K * M / (med / 1e3), "omega_per_s": K / (med / 1e3),
+          "chol_path_tflops": K * n ** 3 / 3.0 / (med / 1e3) / 1e12,
+          "workspace_gib": work.numel() / 2 ** 30,
+          "kernel_ms_per_step": {c: round(v["ms"] / steps, 3) for c, v in prof.items()},
+          "gemm_tflops": (prof["gemm"]["flops"] / (prof["gemm"]["ms"] / 1e3) / 1e12
+                          if prof["gemm"]["ms"] > 0 else 0.0)}
+    del inp, out, beta, work
+    torch.cuda.empty_cache()
+    return st, rec
+
+
+def mixed_error(rec_mx, rec_64, n):
+    """|dl| of mixed against FP64 records (FP64 matches the oracle to 1e-8)."""
+    import numpy as np
+    from paper_2305_04318_amd import PL_INFO_FALLBACK
+    ok = (rec_64["info"] == 0)
+    d = np.abs(rec_mx["loglik"][ok] - rec_64["loglik"][ok])
+    db = np.abs(rec_mx["beta"][ok] - rec_64["beta"][ok])
+    inf = rec_mx["info"][:, 0]
+    fb = int(np.sum((inf > 0) & ((inf & PL_INFO_FALLBACK) != 0)))
+    return {"max_abs_dl": float(d.max()), "p99_abs_dl": _pct(d, 99), "median_abs_dl": _pct(d, 50),
+            "frac_over_1e-2": float(np.mean(d > 1e-2)), "max_abs_dbeta": float(db.max()),
+            "fallback_points": fb}
+
+
+def bench_uneven(pl, runs):
+    import numpy as np
+    import torch
+
+    import synth
+    t0 = time.perf_counter()
+    probs = synth.config_uneven()
+    log(f"uneven: generated {len(probs)} datasets in {time.perf_counter() - t0:.1f} s")
+    b = pl.batch.Batch(probs, probs[0].lam)
+    b.run()
+    torch.cuda.synchronize()
+    err = b.error()
+    ts = []
+    for _ in range(runs):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    info = b.records()["info"].cpu().numpy()
+    med = float(np.median(ts))
+    pts = b.units * probs[0].M
+    flops = sum(p.K * p.n ** 3 / 3.0 for p in probs)
+    st = {"datasets": len(probs), "units": b.units, "tasks": b.tasks, "slabs": b.slabs,
+          "workspace_gib": b.work.numel() / 2 ** 30, "ms_median": med,
+          "points_per_s": pts / (med / 1e3), "omega_per_s": b.units / (med / 1e3),
+          "chol_path_tflops": flops / (med / 1e3) / 1e12, "device_error": err,
+          "failed_points": int(np.sum(info[:, 0] != 0)), "precision": "fp64"}
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    return st
+
+
+def _gen_requests(arrivals):
+    from concurrent.futures import ThreadPoolExecutor
+
+    import synth
+
+    def mk(a):
+        t, n, K, seed = a
+        return synth.serving_problem(n, K, seed, 4)
+
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        probs = list(ex.map(mk, arrivals))
+    return probs
+
+
+def bench_serving(pl, seconds, rate, slots, budget_gib):
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2305_04318_amd import serve as sv
+    arrivals = synth.serving_requests(duration_s=seconds, rate=rate)
+    t0 = time.perf_counter()
+    probs = _gen_requests(arrivals)
+    log(f"serving: generated {len(probs)} requests in {time.perf_counter() - t0:.1f} s")
+    offered = sum(pr.K * pr.n ** 3 / 3.0 for pr in probs) / seconds / 1e12
+    out = {"rate_per_s": rate, "arrival_window_s": seconds, "requests": len(probs),
+           "slots": slots, "hbm_budget_gib": budget_gib, "offered_chol_tflops": offered}
+    for prec in ("fp64", "mixed"):
+        reqs = [sv.Request(i, t, pr.locs, pr.y, pr.X, pr.omega, pr.lam, prec)
+                for i, ((t, _, _, _), pr) in enumerate(zip(arrivals, probs))]
+        ex = sv.GpuExecutor(budget_gib << 30, slots=slots, max_request_work=48 << 30)
+        # untimed warm-up of the kernels for this form on a small request
+        warm = sv.Request(-1, 0.0, probs[0].locs, probs[0].y, probs[0].X, probs[0].omega[:4],
+                          probs[0].lam, prec)
+        sv.Server(ex).run([warm])
+        srv = sv.Server(ex)
+        done = srv.run(reqs)
+        ex.close()
+        del ex
+        torch.cuda.empty_cache()
+        s = sv.latency_summary(done)
+        s["achieved_chol_tflops"] = sum(r.K * r.n ** 3 / 3.0 for r in done) / s["span_s"] / 1e12
+        s["max_inflight"] = srv.max_inflight
+        s["peak_arena_gib"] = srv.peak_bytes / 2 ** 30
+        s["failed_points"] = int(sum(np.sum((r.result["info"] != 0) &
+                                            (r.result["info"] != pl.PL_INFO_FALLBACK))
+                                     for r in done))
+        out[prec] = s
+        log(f"serving {prec}: p50 {s['p50_s'] * 1e3:.0f} ms p99 {s['p99_s'] * 1e3:.0f} ms "
+            f"{s['points_per_s']:.0f} points/s over {s['span_s']:.1f} s")
+    return out
 
 
 def main():
@@ -56,47 +239,72 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-sample", type=int, default=8, help="omega points timed on the oracle")
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="omega points timed on the oracle (default 6 per worker)")
+    ap.add_argument("--cpu-workers", type=int, default=0, help="oracle processes (default min(16, cores))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=2000)
     ap.add_argument("--K", type=int, default=1024)
     ap.add_argument("--M", type=int, default=8)
+    ap.add_argument("--extras", default=",".join(EXTRAS),
+                    help=f"comma list from {EXTRAS}, or 'none'")
+    ap.add_argument("--serve-seconds", type=float, default=8.0)
+    ap.add_argument("--serve-rate", type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(omega points shard across GPUs by design only)", file=sys.stderr)
         sys.exit(2)
+    extras = [] if args.extras == "none" else [e for e in args.extras.split(",") if e]
+    for e in extras:
+        if e not in EXTRAS:
+            sys.exit(f"unknown extra {e!r}")
 
     import numpy as np
-    import torch
 
     import synth
-    import paper_2305_04318_amd as pl
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    pl.load()
     pr = synth.config_aniso(n=args.n, K=args.K, M=args.M)
     n, p, K, M = pr.n, pr.p, pr.K, pr.M
     log(f"workload {pr.name}, p={p}")
+
+    cb = None
+    if not args.no_cpu_baseline:
+        workers = args.cpu_workers or min(16, os.cpu_count() or 1)
+        n_omega = args.cpu_sample or 6 * workers
+        log(f"timing the oracle on {n_omega} omega points, {workers} processes")
+        cb, cpu_ll = cpu_baseline(pr, n_omega, workers)
+        log(f"oracle {cb['value']:.1f} points/s")
+
+    import torch
+
+    import paper_2305_04318_amd as pl
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    pl.load()
+
+    # ---- headline: FP64, with per-kernel-class HIP-event timing -------------
     inp = pl.Inputs(pr.locs, pr.y, pr.X, device="cuda")
     out = torch.empty((K, M, 10), dtype=torch.float64, device="cuda")
+    beta = torch.empty((K, M, p), dtype=torch.float64, device="cuda")
     work = torch.empty(pl.workspace_size(n, p, K, M), dtype=torch.uint8, device="cuda")
     log(f"workspace {work.numel() / 2**30:.2f} GiB")
 
     def step():
-        pl.profile_loglik(None, None, None, pr.omega, pr.lam, inputs=inp, out=out, work=work)
+        pl.profile_loglik(None, None, None, pr.omega, pr.lam, inputs=inp, out=out, beta=beta,
+                          return_beta=True, work=work)
 
     for i in range(args.warmup):
         step()
         torch.cuda.synchronize()
         log(f"warmup {i + 1}/{args.warmup} done")
-
     pl.profiling_enable(True)
     torch.cuda.synchronize()
+    ts = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        a = time.perf_counter()
         step()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - a) * 1e3)
     t1 = time.perf_counter()
     prof = pl.profiling_read()
     pl.profiling_enable(False)
@@ -105,11 +313,13 @@ def main():
     log(f"timed {args.steps} steps: {ms:.2f} ms/step, {value:.0f} points/s")
 
     g = prof["gemm"]
+    gemm_ms = g["ms"] / max(1, g["launches"])
+    gemm_flops = g["flops"] / max(1, g["launches"])
     gemm_tflops = g["flops"] / (g["ms"] / 1e3) / 1e12 if g["ms"] > 0 else 0.0
-    chol_flops = K * n ** 3 / 3.0
-    per_class = {c: round(v["ms"] / args.steps, 3) for c, v in prof.items()}
-    info = pl.unpack_records(out)["info"].cpu().numpy()
-    gpu_ll = pl.unpack_records(out)["loglik"].cpu().numpy()
+    rec64 = {k: v.cpu().numpy() for k, v in pl.unpack_records(out).items()}
+    rec64["beta"] = beta.cpu().numpy()
+    del inp, out, beta, work
+    torch.cuda.empty_cache()
 
     line = {
         "metric": METRIC,
@@ -129,18 +339,60 @@ def main():
         "roofline": {"bound": "mfma", "achieved": gemm_tflops, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": gemm_tflops / PEAK_FP64_TFLOPS, "traffic": None,
                      "kernel": "k_gemm_col (left-looking block-column update, MFMA f64)",
-                     "launches_per_step": g["launches"] // args.steps},
+                     "launches_per_step": g["launches"] // args.steps,
+                     "avg_launch_ms": gemm_ms, "alg_flops_per_launch": gemm_flops},
+        "ms_p10": _pct(ts, 10), "ms_median": float(np.median(ts)), "ms_p90": _pct(ts, 90),
         "omega_per_s": K / (ms / 1e3),
-        "chol_path_tflops": chol_flops / (ms / 1e3) / 1e12,
-        "kernel_ms_per_step": per_class,
-        "failed_points": int(np.sum(info != 0)),
+        "chol_path_tflops": K * n ** 3 / 3.0 / (ms / 1e3) / 1e12,
+        "kernel_ms_per_step": {c: round(v["ms"] / args.steps, 3) for c, v in prof.items()},
+        "failed_points": int(np.sum(rec64["info"] != 0)),
     }
-    if not args.no_cpu_baseline:
-        log(f"timing the oracle on {args.cpu_sample} omega points")
-        cb, err = cpu_baseline(pr, args.cpu_sample, gpu_ll)
+    if cb is not None:
+        k = cpu_ll.shape[0]
+        ref = cpu_ll
+        err = float(np.max(np.abs(rec64["loglik"][:k] - ref) / np.maximum(np.abs(ref), n)))
         line["cpu_baseline"] = cb
         line["oracle_max_rel_err"] = err
-        log(f"oracle {cb['value']:.1f} points/s, max rel err vs GPU {err:.2e}")
+        log(f"max rel err vs oracle {err:.2e}")
+
+    def guarded(name, fn):
+        try:
+            line[name] = fn()
+        except Exception as e:  # an extra must not lose the headline line
+            log(f"{name} failed: {type(e).__name__}: {e}")
+            line[name] = {"error": f"{type(e).__name__}: {e}"}
+        torch.cuda.empty_cache()
+
+    if "mixed" in extras:
+        def mixed2000():
+            st, rec = run_form(pl, pr, "mixed", args.steps, args.warmup)
+            st.update(mixed_error(rec, rec64, n))
+            log(f"mixed n={n}: {st['ms_median']:.1f} ms, max |dl| {st['max_abs_dl']:.2e}")
+            return st
+        guarded("mixed_n2000", mixed2000)
+
+    for big, key in ((4000, "n4000"), (8000, "n8000")):
+        if key not in extras:
+            continue
+
+        def both(big=big):
+            q = synth.config_mixed() if big == 4000 else synth.config_aniso(n=8000, K=256, M=8)
+            res = {}
+            s64, r64 = run_form(pl, q, "fp64", max(2, args.steps // 2), 1)
+            res["fp64"] = s64
+            smx, rmx = run_form(pl, q, "mixed", max(2, args.steps // 2), 1)
+            smx.update(mixed_error(rmx, r64, q.n))
+            res["mixed"] = smx
+            log(f"n={big}: fp64 {s64['ms_median']:.1f} ms, mixed {smx['ms_median']:.1f} ms, "
+                f"max |dl| {smx['max_abs_dl']:.2e}")
+            return res
+        guarded(key, both)
+
+    if "batch" in extras:
+        guarded("uneven_batch", lambda: bench_uneven(pl, max(3, args.steps // 2)))
+    if "serve" in extras:
+        guarded("serving", lambda: bench_serving(pl, args.serve_seconds, args.serve_rate, 4, 160))
+
     print(json.dumps(line), flush=True)
 
 

@@ -25,6 +25,7 @@ anisotropy ratio phi_R, angle phi_A) with phi_Y = phi_X / phi_R.
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -71,16 +72,28 @@ def _aniso_map(phi_x: float, ratio: float, angle: float) -> np.ndarray:
     return np.diag([1.0 / phi_x, 1.0 / phi_y]) @ rot
 
 
-def gaussian_field(rng, locs, phi_x, kappa, ratio=1.0, angle=0.0, n_features=N_FEATURES):
-    """Zero-mean, unit-variance stationary field with (approximately) Matern
-    correlation, drawn by random Fourier features (see module docstring)."""
-    A = _aniso_map(phi_x, ratio, angle)
-    scaled = locs @ A.T                       # (n, 2) scaled coordinates
+def field_draws(rng, kappa, n_features=N_FEATURES):
+    """Random frequencies and phases of one random-Fourier-feature field
+    (see module docstring); drawn in the order z, g, b."""
     z = rng.standard_normal((n_features, 2))
     g = rng.chisquare(2.0 * kappa, size=n_features)
     w = 2.0 * z / np.sqrt(g / (2.0 * kappa))[:, None]
     b = rng.uniform(0.0, 2.0 * math.pi, size=n_features)
-    return math.sqrt(2.0 / n_features) * np.cos(scaled @ w.T + b).sum(axis=1)
+    return w, b
+
+
+def field_eval(locs, A, w, b):
+    """sqrt(2/F) sum_f cos(w_f . A s + b_f) at every location."""
+    scaled = locs @ A.T                       # (n, 2) scaled coordinates
+    return math.sqrt(2.0 / w.shape[0]) * np.cos(scaled @ w.T + b).sum(axis=1)
+
+
+def gaussian_field(rng, locs, phi_x, kappa, ratio=1.0, angle=0.0, n_features=N_FEATURES):
+    """Zero-mean, unit-variance stationary field with (approximately) Matern
+    correlation, drawn by random Fourier features (see module docstring)."""
+    A = _aniso_map(phi_x, ratio, angle)
+    w, b = field_draws(rng, kappa, n_features)
+    return field_eval(locs, A, w, b)
 
 
 def inverse_boxcox(yt, lam, floor=0.01):
@@ -91,12 +104,16 @@ def inverse_boxcox(yt, lam, floor=0.01):
     return base ** (1.0 / lam)
 
 
-def simulate(rng, locs, X, beta, sigma, phi_x, kappa, nugget, ratio, angle, lam_true):
-    u = gaussian_field(rng, locs, phi_x, kappa, ratio, angle)
-    eps = rng.standard_normal(locs.shape[0])
+def _finish_obs(u, eps, X, beta, sigma, nugget, lam_true):
     yt = X @ np.asarray(beta) + sigma * (u + math.sqrt(nugget) * eps)
     floored = int(np.sum(1.0 + lam_true * yt <= 0.01)) if lam_true != 0.0 else 0
     return inverse_boxcox(yt, lam_true), floored
+
+
+def simulate(rng, locs, X, beta, sigma, phi_x, kappa, nugget, ratio, angle, lam_true):
+    u = gaussian_field(rng, locs, phi_x, kappa, ratio, angle)
+    eps = rng.standard_normal(locs.shape[0])
+    return _finish_obs(u, eps, X, beta, sigma, nugget, lam_true)
 
 
 def omega_box(rng, K, range_lo=0.5, range_hi=4.5, ratio_lo=1.0, ratio_hi=6.0,
@@ -159,24 +176,36 @@ def config_uneven(n_datasets: int = 2048, k_per: int = 16, rep: int = 0,
     [0,5]^2, X=[1, z], shape in {0.5, 1.5, 3}, range U[0.2, 1], nugget 0.1,
     y = exp(y'), 16 omega points jittered around each truth, lambda in {0,1}."""
     rng = rng_for(4, rep)
-    out = []
+    # all random draws in sequence (the same order as simulate), then the
+    # field sums, which dominate the cost, on a thread pool
+    drawn = []
     for _ in range(n_datasets):
         n = int(rng.integers(n_lo, n_hi + 1))
         locs = rng.uniform(0.0, 5.0, (n, 2))
         X = np.column_stack([np.ones(n), rng.standard_normal(n)])
         kap = float(rng.choice([0.5, 1.5, 3.0]))
         rng_ = float(rng.uniform(0.2, 1.0))
-        y, _ = simulate(rng, locs, X, (1.0, 0.5), 1.0, rng_, kap, 0.1, 1.0, 0.0, 0.0)
+        w, b = field_draws(rng, kap)
+        eps = rng.standard_normal(n)
         om = np.empty((k_per, 5))
         om[:, 0] = rng_ * np.exp(rng.uniform(-0.7, 0.7, k_per))
         om[:, 1] = kap * np.exp(rng.uniform(-0.7, 0.7, k_per))
         om[:, 2] = 0.1 * np.exp(rng.uniform(-1.0, 1.0, k_per))
         om[:, 3] = 1.0
         om[:, 4] = 0.0
-        out.append(Problem(locs, y, X, om, np.array([0.0, 1.0]),
-                           truth=dict(range=rng_, shape=kap, nugget=0.1, lam=0.0),
-                           name=f"uneven n={n}"))
-    return out
+        drawn.append((locs, X, kap, rng_, w, b, eps, om))
+
+    def make(d):
+        locs, X, kap, rng_, w, b, eps, om = d
+        u = field_eval(locs, _aniso_map(rng_, 1.0, 0.0), w, b)
+        y, _ = _finish_obs(u, eps, X, (1.0, 0.5), 1.0, 0.1, 0.0)
+        return Problem(locs, y, X, om, np.array([0.0, 1.0]),
+                       truth=dict(range=rng_, shape=kap, nugget=0.1, lam=0.0),
+                       name=f"uneven n={locs.shape[0]}")
+
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as pool:
+        return list(pool.map(make, drawn))
 
 
 def serving_requests(duration_s: float = 30.0, rate: float = 20.0, rep: int = 0,
