@@ -81,7 +81,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_col_mx(Lay lay, float* __restri
   d4 acc[4][4];
   zero_acc<double>(acc);
   wg_gemm_nt_f32x64<FLUSH>(acc, lds, base + lay.tile_off(I, 0), lay.tile_ld(I), arows,
-                           base + lay.tile_off(J, 0), lay.tile_ld(J), brows, kmax, act, ni, nj);
+                           base + lay.tile_off(J, 0), lay.tile_ld(J), brows, kmax, act, ni);
   if (act) {
     const int64_t ldc = lay.tile_ld(I);
     float* C = base + lay.tile_off(I, J) + 64 * wr + 64 * wc * ldc;
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_diag_mx(Lay lay, const float* _
   d4 acc[4][4];
   zero_acc<double>(acc);
   wg_gemm_nt<float, double, VEC>(acc, lds, P, lay.tile_ld(J), rows, P, lay.tile_ld(J), rows, kmax,
-                                 act, ni, nj);
+                                 act, ni);
   if (act) {
     const double* Cin = m64 + (int64_t)k * m64stride + lay.tile_off(J, J) + 64 * wr + 64 * wc * T;
     double* Cout = dscratch + (int64_t)k * T * T + 64 * wr + 64 * wc * T;
@@ -252,6 +252,7 @@ hipError_t launch_trsm_mx(const Lay& lay, float* m32, const float* W32, const in
 //   Y = V_IJ x0_J on MFMA f64 (the GEMM core, x0 as a TB x T column-major panel),
 //   M = x0_I^T Y;  slot = -(M + M^T) for I > J,  2 B_I^T x0_I - M for I = J.
 // The slots are summed in a fixed order by k_finalize (deterministic).
+template <int TB>
 __global__ __launch_bounds__(256, 2) void k_qform(Lay lay, const double* __restrict__ m64,
                                                   int64_t stride64, const double* __restrict__ X,
                                                   const double* __restrict__ rhs,
@@ -270,40 +271,78 @@ __global__ __launch_bounds__(256, 2) void k_qform(Lay lay, const double* __restr
   if (info[k] != 0) return;  // uniform for the workgroup
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = wave >> 1, wc = wave & 1;
-  const int TB = lay.TB, q = lay.q;
+  const int q = lay.q;
   const int ri = lay.rows(I), rj = lay.rows(J);
   const double* Xk = X + (int64_t)k * lay.n * TB;
   double* slot = slots + ((int64_t)k * ntile + t) * TB * TB;
   const double* Xi = Xk + (int64_t)I * T * TB;   // x0_I: element (r, a) at r*TB + a
-  double* Ys = lds;                              // Y, column-major T x TB, after the core
+  const double* Bi = rhs + (int64_t)I * T * TB;  // B_I, same layout
+  // LDS after the core: Y = V_IJ x0_J column-major with the odd stride T + 1
+  // (the pair loop below reads 16 columns of Y at once), then x0_I.  With
+  // TB <= 32 both fit the core's LDS block.
+  constexpr int LY = T + 1;
+  double* Ys = lds;
+  double* Xs = lds + LY * TB;
   if (refine) {
     const int war = ri - 64 * wr, wbr = q - 64 * wc;
     const int ni = nblk(war), nj = nblk(wbr);
     const bool act = ni > 0 && nj > 0;
     d4 acc[4][4];
     zero_acc<double>(acc);
-    wg_gemm_nt<double, double, true>(acc, lds, m64 + (int64_t)k * stride64 + lay.tile_off(I, J), T,
-                                     ri, Xk + (int64_t)J * T * TB, TB, q, rj, act, ni, nj);
+    // B = x0_J has q <= TB rows: TB / 16 block columns
+    wg_gemm_nt<double, double, true, TB / 16>(acc, lds,
+                                              m64 + (int64_t)k * stride64 + lay.tile_off(I, J), T,
+                                              ri, Xk + (int64_t)J * T * TB, TB, q, rj, act, ni);
     // the core ends with a barrier: the LDS stages are free for Y
-    if (act) store64<double, false>(Ys + 64 * wr + 64 * wc * T, T, Ys + 64 * wr + 64 * wc * T, T,
+    if (act) store64<double, false>(Ys + 64 * wr + 64 * wc * LY, LY, Ys + 64 * wr + 64 * wc * LY, LY,
                                     acc, war, wbr, lane);
-    __syncthreads();
   }
-  const double* Bi = rhs + (int64_t)I * T * TB;
+  // stage x0_I, and on a diagonal tile fold B_I into Y: since V_II is
+  // symmetric, 2 B_I^T x0_I - x0_I^T V_II x0_I = (2 B_I - V_II x0_I)^T x0_I
+  // (without refinement the slot is B_I^T x0_I, so Y is replaced by B_I).
+  // Loads use a clamped address and a select, so they are all in flight at once.
+  constexpr int PER = T * TB / 256;
+  double xv[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int idx = 256 * u + tid;
+    const bool ok = idx / TB < ri;
+    xv[u] = Xi[ok ? idx : 0];
+    xv[u] = ok ? xv[u] : 0.0;
+  }
+  if (refine) __syncthreads();  // Y is complete
+#pragma unroll
+  for (int u = 0; u < PER; ++u) Xs[256 * u + tid] = xv[u];
+  if (I == J) {
+    double bv[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = 256 * u + tid;
+      const bool ok = idx / TB < ri;
+      bv[u] = Bi[ok ? idx : 0];
+      bv[u] = ok ? bv[u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = 256 * u + tid, r = idx / TB, a = idx % TB;
+      Ys[a * LY + r] = refine ? 2.0 * bv[u] - Ys[a * LY + r] : bv[u];
+    }
+  }
+  __syncthreads();
   for (int pr = tid; pr < TB * TB; pr += 256) {
     const int a = pr / TB, b = pr % TB;
     double v = 0.0;
-    if (refine) {
-      double mab = 0.0, mba = 0.0, bx = 0.0;
+    if (I == J) {
+#pragma unroll 8
+      for (int r = 0; r < ri; ++r) v += Ys[a * LY + r] * Xs[r * TB + b];
+    } else if (refine) {
+      double mab = 0.0, mba = 0.0;
+#pragma unroll 8
       for (int r = 0; r < ri; ++r) {
-        const double xa = Xi[r * TB + a], xb = Xi[r * TB + b];
-        mab += xa * Ys[b * T + r];
-        mba += xb * Ys[a * T + r];
-        if (I == J) bx += Bi[r * TB + a] * xb;
+        mab += Xs[r * TB + a] * Ys[b * LY + r];
+        mba += Xs[r * TB + b] * Ys[a * LY + r];
       }
-      v = (I > J) ? -(mab + mba) : 2.0 * bx - mab;
-    } else if (I == J) {
-      for (int r = 0; r < ri; ++r) v += Bi[r * TB + a] * Xi[r * TB + b];
+      v = -(mab + mba);
     }
     slot[pr] = v;
   }
@@ -312,10 +351,18 @@ __global__ __launch_bounds__(256, 2) void k_qform(Lay lay, const double* __restr
 hipError_t launch_qform(const Lay& lay, const double* m64, int64_t stride64, const double* X,
                         const double* rhs, const int32_t* info, double* slots, int refine, int K,
                         hipStream_t s) {
+  // Y and x0_I share the core's LDS block: (T + 1) TB + T TB doubles
+  static_assert((2 * T + 1) * 32 * (int)sizeof(double) <= GEMM_LDS_BYTES, "qform LDS");
   const int ntile = lay.Nv * (lay.Nv + 1) / 2;
   const int G = K * ntile;
-  hipLaunchKernelGGL(k_qform, dim3(G), dim3(256), 0, s, lay, m64, stride64, X, rhs, info, slots,
-                     refine, ntile, G);
+  if (lay.TB == 16)
+    hipLaunchKernelGGL(k_qform<16>, dim3(G), dim3(256), 0, s, lay, m64, stride64, X, rhs, info,
+                       slots, refine, ntile, G);
+  else if (lay.TB == 32)
+    hipLaunchKernelGGL(k_qform<32>, dim3(G), dim3(256), 0, s, lay, m64, stride64, X, rhs, info,
+                       slots, refine, ntile, G);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

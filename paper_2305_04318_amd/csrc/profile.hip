@@ -120,13 +120,17 @@ hipError_t launch_border_init_f32(const Lay& lay, float* mats, const double* rhs
   return hipGetLastError();
 }
 
+static_assert(T * (T + 1) % 4 == 0, "right-hand sides follow the tile in LDS, 16-byte aligned");
+
 // ---- mixed form: back substitution x0 = L^-T Z -----------------------------------
 // The FP32 factorisation leaves Z^T = (L^-1 B)^T in the bordered tile row.  x0
 // (n rows of TB values, FP64) starts as Z and is swept from the bottom tile row:
 //   k_bs_diag(I)   : X_I <- W_I^T X_I           (W_I = L_II^-1, one workgroup per omega)
 //   k_bs_update(I) : X_J <- X_J - L_IJ^T X_I   (J < I, one workgroup per (omega, J))
-// Thread (r, h) owns row r of the output tile and columns h, h+2, ... (TB <= 32).
-constexpr int BS_MAXC = 16;
+// TB (16 or 32: the mixed form takes M + p <= 32) is a template parameter so
+// that the per-thread column loop is straight-line code.  Thread (r, h) owns
+// row r of the output tile and the contiguous columns h*TB/2 .. h*TB/2+TB/2-1;
+// a wave has one h, so its reads of the right-hand sides are LDS broadcasts.
 
 __global__ void k_bs_init(Lay lay, const float* __restrict__ m32, const int32_t* __restrict__ info,
                           double* __restrict__ X, int K) {
@@ -139,100 +143,142 @@ __global__ void k_bs_init(Lay lay, const float* __restrict__ m32, const int32_t*
   X[idx] = (double)m32[(int64_t)k * lay.mstride + lay.tile_off(lay.Nv, 0) + e];
 }
 
-// out[r][a] = sum_c M[c][r] Xin[c][a] for a T x T column-major tile M staged in
-// LDS with a padded stride (conflict-free reads along a row of M^T)
+// Ls[c][r] (stride T + 1) = G[c][r] for the T x T column-major tile G, rows
+// r >= valid_rows as zero.  Every thread (blockDim.x == 256) issues all 16 of
+// its 16-byte loads before its first LDS store.
+constexpr int STAGE_PER = T * T / 4 / 256;
 __device__ __forceinline__ void stage_tile_t(float* Ls, const float* __restrict__ G, int valid_rows) {
-  for (int q = threadIdx.x; q < T * T / 4; q += blockDim.x) {
-    const int idx = 4 * q, col = idx / T, row = idx % T;
-    const float4 v = *reinterpret_cast<const float4*>(G + idx);
+  float4 v[STAGE_PER];
+#pragma unroll
+  for (int u = 0; u < STAGE_PER; ++u)
+    v[u] = *reinterpret_cast<const float4*>(G + 4 * (threadIdx.x + 256 * u));
+#pragma unroll
+  for (int u = 0; u < STAGE_PER; ++u) {
+    const int idx = 4 * (threadIdx.x + 256 * u), col = idx / T, row = idx % T;
     float* dst = Ls + col * (T + 1) + row;
-    dst[0] = (row + 0 < valid_rows) ? v.x : 0.0f;
-    dst[1] = (row + 1 < valid_rows) ? v.y : 0.0f;
-    dst[2] = (row + 2 < valid_rows) ? v.z : 0.0f;
-    dst[3] = (row + 3 < valid_rows) ? v.w : 0.0f;
+    dst[0] = (row + 0 < valid_rows) ? v[u].x : 0.0f;
+    dst[1] = (row + 1 < valid_rows) ? v[u].y : 0.0f;
+    dst[2] = (row + 2 < valid_rows) ? v[u].z : 0.0f;
+    dst[3] = (row + 3 < valid_rows) ? v[u].w : 0.0f;
   }
 }
 
+// Xs[c][a] = (float) Xg[c][a] for the T x TB block of right-hand sides; rows
+// c >= valid_rows read as zero.  Loads go to a clamped (always valid) address
+// and are selected afterwards, so all of a thread's loads are in flight at once.
+template <int TB>
+__device__ __forceinline__ void stage_rhs(float* Xs, const double* __restrict__ Xg, int valid_rows) {
+  constexpr int PER = T * TB / 256;
+  double v[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int idx = 256 * u + threadIdx.x;
+    const bool ok = idx / TB < valid_rows;
+    v[u] = Xg[ok ? idx : 0];
+    v[u] = ok ? v[u] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) Xs[256 * u + threadIdx.x] = (float)v[u];
+}
+
+// out[m] = sum_c Ls[r][c]-row . Xs[c][h*NC + m] over c < rows (NC = TB / 2)
+template <int TB>
+__device__ __forceinline__ void bs_rowdot(const float* Ls, const float* Xs, int r, int h, int rows,
+                                          float (&out)[TB / 2]) {
+  constexpr int NC = TB / 2;
+  const float* lrow = Ls + r * (T + 1);
+  const float* xcol = Xs + h * NC;
+#pragma unroll
+  for (int m = 0; m < NC; ++m) out[m] = 0.0f;
+#pragma unroll 4
+  for (int c = 0; c < rows; ++c) {
+    const float l = lrow[c];
+    const float4* xv = reinterpret_cast<const float4*>(xcol + c * TB);
+#pragma unroll
+    for (int m4 = 0; m4 < NC / 4; ++m4) {
+      const float4 x = xv[m4];
+      out[4 * m4 + 0] += l * x.x;
+      out[4 * m4 + 1] += l * x.y;
+      out[4 * m4 + 2] += l * x.z;
+      out[4 * m4 + 3] += l * x.w;
+    }
+  }
+}
+
+template <int TB>
 __global__ __launch_bounds__(256) void k_bs_diag(Lay lay, const float* __restrict__ W32,
                                                  const int32_t* __restrict__ info,
                                                  double* __restrict__ X, int I) {
-  extern __shared__ float bsm[];  // T x (T+1) tile + T x TB right-hand sides
+  extern __shared__ __attribute__((aligned(16))) float bsm[];  // T x (T+1) tile, T x TB rhs
   float* Ls = bsm;
-  float* Xs = bsm + T * (T + 1);
+  float* Xs = bsm + T * (T + 1);  // T (T + 1) = 16512 floats: 16-byte aligned
+  constexpr int NC = TB / 2;
   const int k = blockIdx.x;
   if (info[k] != 0) return;
   const int tid = threadIdx.x, r = tid & (T - 1), h = tid >> 7;
-  const int TB = lay.TB, nc = TB / 2, ri = lay.rows(I);
+  const int ri = lay.rows(I);
   double* Xi = X + (int64_t)k * lay.n * TB + (int64_t)I * T * TB;
   stage_tile_t(Ls, W32 + ((int64_t)k * lay.Nv + I) * T * T, T);
-  for (int idx = tid; idx < T * TB; idx += 256) {
-    const int c = idx / TB;
-    Xs[idx] = (c < ri) ? (float)Xi[idx] : 0.0f;
-  }
+  stage_rhs<TB>(Xs, Xi, ri);
   __syncthreads();
-  const float* wrow = Ls + r * (T + 1);
-  float out[BS_MAXC];
-#pragma unroll
-  for (int m = 0; m < BS_MAXC; ++m) out[m] = 0.0f;
-  for (int c = 0; c < ri; ++c) {
-    const float w = wrow[c];
-#pragma unroll
-    for (int m = 0; m < BS_MAXC; ++m)
-      if (m < nc) out[m] += w * Xs[c * TB + h + 2 * m];
-  }
+  float out[NC];
+  bs_rowdot<TB>(Ls, Xs, r, h, ri, out);
   if (r < ri) {
+    double* dst = Xi + r * TB + h * NC;
 #pragma unroll
-    for (int m = 0; m < BS_MAXC; ++m)
-      if (m < nc) Xi[r * TB + h + 2 * m] = (double)out[m];
+    for (int m = 0; m < NC; ++m) dst[m] = (double)out[m];
   }
 }
 
+template <int TB>
 __global__ __launch_bounds__(256) void k_bs_update(Lay lay, const float* __restrict__ m32,
                                                    const int32_t* __restrict__ info,
                                                    double* __restrict__ X, int I) {
-  extern __shared__ float bsm[];
+  extern __shared__ __attribute__((aligned(16))) float bsm[];
   float* Ls = bsm;
   float* Xs = bsm + T * (T + 1);
+  constexpr int NC = TB / 2;
   const int k = blockIdx.x / I;
   const int J = blockIdx.x % I;
   if (info[k] != 0) return;
   const int tid = threadIdx.x, r = tid & (T - 1), h = tid >> 7;
-  const int TB = lay.TB, nc = TB / 2, ri = lay.rows(I);
+  const int ri = lay.rows(I);
   const double* Xi = X + (int64_t)k * lay.n * TB + (int64_t)I * T * TB;
   double* Xj = X + (int64_t)k * lay.n * TB + (int64_t)J * T * TB;
   // tile (I, J): rows in block I (the contraction index), columns in block J
   stage_tile_t(Ls, m32 + (int64_t)k * lay.mstride + lay.tile_off(I, J), ri);
-  for (int idx = tid; idx < T * TB; idx += 256) {
-    const int c = idx / TB;
-    Xs[idx] = (c < ri) ? (float)Xi[idx] : 0.0f;
-  }
+  stage_rhs<TB>(Xs, Xi, ri);
   __syncthreads();
-  const float* lrow = Ls + r * (T + 1);
-  float out[BS_MAXC];
-#pragma unroll
-  for (int m = 0; m < BS_MAXC; ++m) out[m] = 0.0f;
-  for (int c = 0; c < ri; ++c) {
-    const float l = lrow[c];
-#pragma unroll
-    for (int m = 0; m < BS_MAXC; ++m)
-      if (m < nc) out[m] += l * Xs[c * TB + h + 2 * m];
-  }
+  float out[NC];
+  bs_rowdot<TB>(Ls, Xs, r, h, ri, out);
   // tile row J < I is complete (T rows)
+  double* dst = Xj + r * TB + h * NC;
+  double cur[NC];
 #pragma unroll
-  for (int m = 0; m < BS_MAXC; ++m)
-    if (m < nc) Xj[r * TB + h + 2 * m] -= (double)out[m];
+  for (int m = 0; m < NC; ++m) cur[m] = dst[m];
+#pragma unroll
+  for (int m = 0; m < NC; ++m) dst[m] = cur[m] - (double)out[m];
+}
+
+template <int TB>
+static void backsolve_sweep(const Lay& lay, const float* m32, const float* W32, const int32_t* info,
+                            double* X, int K, hipStream_t s) {
+  const size_t lds = (size_t)(T * (T + 1) + T * TB) * sizeof(float);
+  for (int I = lay.Nv - 1; I >= 0; --I) {
+    hipLaunchKernelGGL(k_bs_diag<TB>, dim3(K), dim3(256), lds, s, lay, W32, info, X, I);
+    if (I > 0)
+      hipLaunchKernelGGL(k_bs_update<TB>, dim3(K * I), dim3(256), lds, s, lay, m32, info, X, I);
+  }
 }
 
 hipError_t launch_backsolve(const Lay& lay, const float* m32, const float* W32,
                             const int32_t* info, double* X, int K, hipStream_t s) {
+  if (lay.TB != 16 && lay.TB != 32) return hipErrorInvalidValue;
   const int64_t total = (int64_t)lay.n * lay.TB * K;
   hipLaunchKernelGGL(k_bs_init, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, lay, m32,
                      info, X, K);
-  const size_t lds = (size_t)(T * (T + 1) + T * lay.TB) * sizeof(float);
-  for (int I = lay.Nv - 1; I >= 0; --I) {
-    hipLaunchKernelGGL(k_bs_diag, dim3(K), dim3(256), lds, s, lay, W32, info, X, I);
-    if (I > 0) hipLaunchKernelGGL(k_bs_update, dim3(K * I), dim3(256), lds, s, lay, m32, info, X, I);
-  }
+  if (lay.TB == 16) backsolve_sweep<16>(lay, m32, W32, info, X, K, s);
+  else backsolve_sweep<32>(lay, m32, W32, info, X, K, s);
   return hipGetLastError();
 }
 

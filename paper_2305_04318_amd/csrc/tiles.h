@@ -70,16 +70,21 @@ __device__ __forceinline__ typename Piece<TS>::type fetch_piece(const TS* __rest
 // LDS: every thread fetches 4 + 4 16-byte pieces of the next chunk from
 // global memory while the waves run the current chunk's MFMAs, then writes
 // them to the other LDS stage; one barrier per chunk.  Rows at or beyond
-// arows / brows and columns at or beyond kmax read as zero.  TS is the storage
-// type, TC the MFMA type (float storage may be widened to FP64 MFMA).
+// arows / brows and columns at or beyond kmax read as zero.  A wave skips its
+// block rows at or beyond ni (16-row blocks holding rows below arows) but
+// runs all four block columns: those beyond brows multiply zeros and are
+// never stored, which keeps the MFMA stream free of per-block branches (a
+// caller whose B has at most 16 NJ rows passes NJ < 4 to skip the rest at
+// compile time).  TS is the storage type, TC the MFMA type (float storage may
+// be widened to FP64 MFMA).
 constexpr int LROW = T + 4;         // LDS stride per k column (elements)
 constexpr int GEMM_LDS_BYTES = 2 * 2 * 16 * LROW * 8;
 
-template <typename TS, typename TC, bool VEC>
+template <typename TS, typename TC, bool VEC, int NJ = 4>
 __device__ __forceinline__ void wg_gemm_nt(typename MF<TC>::acc (&acc)[4][4], TS* lds,
                                            const TS* __restrict__ A, int64_t lda, int arows,
                                            const TS* __restrict__ B, int64_t ldb, int brows,
-                                           int kmax, bool do_mfma, int ni, int nj) {
+                                           int kmax, bool do_mfma, int ni) {
   constexpr int N = Piece<TS>::N;
   constexpr int KC = 128 / (int)sizeof(TS);
   constexpr int PPC = T / N;  // pieces per column
@@ -88,6 +93,10 @@ __device__ __forceinline__ void wg_gemm_nt(typename MF<TC>::acc (&acc)[4][4], TS
   const int wr = wave >> 1, wc = wave & 1;
   const int nchunks = (kmax + KC - 1) / KC;
   if (nchunks <= 0) return;
+  // per-wave values: keep them in scalar registers so that the block-row
+  // guards below are scalar branches, not exec masks
+  ni = __builtin_amdgcn_readfirstlane(ni);
+  do_mfma = __builtin_amdgcn_readfirstlane((int)do_mfma) != 0;
   V ra[4], rb[4];
   auto fetch = [&](int k0) {
 #pragma unroll
@@ -132,8 +141,7 @@ __device__ __forceinline__ void wg_gemm_nt(typename MF<TC>::acc (&acc)[4][4], TS
         for (int i = 0; i < 4; ++i) {
           if (i < ni) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-              if (j < nj) acc[i][j] = MF<TC>::op(b[j], a[i], acc[i][j]);
+            for (int j = 0; j < NJ; ++j) acc[i][j] = MF<TC>::op(b[j], a[i], acc[i][j]);
           }
         }
       }
@@ -152,7 +160,7 @@ __device__ __forceinline__ void wg_gemm_nt_f32x64(d4 (&acc)[4][4], float* lds,
                                                   const float* __restrict__ A, int64_t lda,
                                                   int arows, const float* __restrict__ B,
                                                   int64_t ldb, int brows, int kmax, bool do_mfma,
-                                                  int ni, int nj) {
+                                                  int ni) {
   constexpr int N = 4;
   constexpr int KC = 32;
   constexpr int PPC = T / N;
@@ -161,6 +169,10 @@ __device__ __forceinline__ void wg_gemm_nt_f32x64(d4 (&acc)[4][4], float* lds,
   const int wr = wave >> 1, wc = wave & 1;
   const int nchunks = (kmax + KC - 1) / KC;
   if (nchunks <= 0) return;
+  // per-wave values: keep them in scalar registers so that the block-row
+  // guards below are scalar branches, not exec masks
+  ni = __builtin_amdgcn_readfirstlane(ni);
+  do_mfma = __builtin_amdgcn_readfirstlane((int)do_mfma) != 0;
   V ra[4], rb[4];
   auto fetch = [&](int k0) {
 #pragma unroll
@@ -186,6 +198,9 @@ __device__ __forceinline__ void wg_gemm_nt_f32x64(d4 (&acc)[4][4], float* lds,
   stash(0);
   __syncthreads();
   const int lr = lane & 15, lk = lane >> 4;
+  f4 pp[4];  // FP32 partials of the block row that is folded in next
+#pragma unroll
+  for (int j = 0; j < 4; ++j) pp[j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
   for (int c = 0; c < nchunks; ++c) {
     const bool more = c + 1 < nchunks;
     if (more) fetch((c + 1) * KC);
@@ -195,38 +210,47 @@ __device__ __forceinline__ void wg_gemm_nt_f32x64(d4 (&acc)[4][4], float* lds,
       // rolled: only one group's fragments and partial sums are live at a time
 #pragma unroll 1
       for (int g = 0; g < KC / 4 / FLUSH; ++g) {
-        float a[FLUSH][4], b[FLUSH][4];
+        float b[FLUSH][4];
 #pragma unroll
-        for (int s4 = 0; s4 < FLUSH; ++s4) {
-          const int kk = 4 * (g * FLUSH + s4) + lk;
+        for (int s4 = 0; s4 < FLUSH; ++s4)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            a[s4][i] = sa[kk * LROW + 16 * i];
-            b[s4][i] = sb[kk * LROW + 16 * i];
-          }
-        }
-        // one block row at a time keeps only 4 FP32 partial blocks live
+          for (int j = 0; j < 4; ++j) b[s4][j] = sb[(4 * (g * FLUSH + s4) + lk) * LROW + 16 * j];
+        // software pipeline over block rows: issue row i's MFMAs, then fold
+        // the previous row's FP32 partials into FP64 while they run
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          if (i < ni) {
-            f4 part[4];
+          float a[FLUSH];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) part[j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+          for (int s4 = 0; s4 < FLUSH; ++s4) a[s4] = sa[(4 * (g * FLUSH + s4) + lk) * LROW + 16 * i];
+          f4 pc[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) pc[j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+          if (i < ni) {
 #pragma unroll
             for (int s4 = 0; s4 < FLUSH; ++s4)
 #pragma unroll
-              for (int j = 0; j < 4; ++j)
-                if (j < nj) part[j] = MF<float>::op(b[s4][j], a[s4][i], part[j]);
+              for (int j = 0; j < 4; ++j) pc[j] = MF<float>::op(b[s4][j], a[s4], pc[j]);
+          }
+          const int ip = (i + 3) & 3;
+          if (ip < ni) {
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
-              for (int e = 0; e < 4; ++e) acc[i][j][e] += (double)part[j][e];
+              for (int e = 0; e < 4; ++e) acc[ip][j][e] += (double)pp[j][e];
           }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) pp[j] = pc[j];
         }
       }
     }
     if (more) stash((c + 1) & 1);
     __syncthreads();
+  }
+  if (do_mfma && 3 < ni) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[3][j][e] += (double)pp[j][e];
   }
 }
 
@@ -308,8 +332,7 @@ __device__ __forceinline__ void dev_gemm_col(const Lay& lay, double* base, int J
   d4 acc[4][4];
   zero_acc<double>(acc);
   wg_gemm_nt<double, double, VEC>(acc, lds, base + lay.tile_off(I, 0), lay.tile_ld(I), arows,
-                                  base + lay.tile_off(J, 0), lay.tile_ld(J), brows, kmax, act, ni,
-                                  nj);
+                                  base + lay.tile_off(J, 0), lay.tile_ld(J), brows, kmax, act, ni);
   if (act) {
     const int64_t ldc = lay.tile_ld(I);
     double* C = base + lay.tile_off(I, J) + 64 * wr + 64 * wc * ldc;
@@ -333,10 +356,10 @@ __device__ __forceinline__ void dev_trsm(const Lay& lay, TS* base, const TS* W, 
   zero_acc<double>(acc);
   // the core's final barrier orders every read of C_IJ before the overwrite
   if constexpr (sizeof(TS) == 8) {
-    wg_gemm_nt<TS, TS, VEC>(acc, lds, Ct, ldc, arows, W, T, brows, brows, act, ni, nj);
+    wg_gemm_nt<TS, TS, VEC>(acc, lds, Ct, ldc, arows, W, T, brows, brows, act, ni);
     if (act) store64<double, false>(Co, ldc, Co, ldc, acc, war, wbr, lane);
   } else {
-    wg_gemm_nt_f32x64<FLUSH>(acc, lds, Ct, ldc, arows, W, T, brows, brows, act, ni, nj);
+    wg_gemm_nt_f32x64<FLUSH>(acc, lds, Ct, ldc, arows, W, T, brows, brows, act, ni);
     if (act) store64_l<float, false>(Co, ldc, Co, ldc, acc, war, wbr, lane);
   }
 }
