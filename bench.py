@@ -30,6 +30,30 @@ METRIC = ("profile-loglik points/sec at n=2000 (FP64 vs mixed, |Δℓ|≤1e-2); 
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 matrix peak
 PEAK_FP32_TFLOPS = 157.3    # MI355X dense FP32 matrix peak
 EXTRAS = ("mixed", "n4000", "n8000", "batch", "serve")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "gemm_col_hbm_traffic_aniso_n2000_K1024.md")
+GEMM_SOURCES = ("common.h", "tiles.h", "chol.hip")
+
+
+def measured_traffic():
+    """HBM bytes per k_gemm_col launch from the committed FETCH_SIZE/WRITE_SIZE
+    summary, or None when the kernel sources changed since it was taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        want = {}
+        for line in text.splitlines():
+            k, _, v = line.strip().partition(": ")
+            if k in ("traffic_bytes_per_launch", "sources_sha256"):
+                want[k] = v.strip()
+        h = hashlib.sha256()
+        for f in GEMM_SOURCES:
+            with open(os.path.join(ROOT, "paper_2305_04318_amd", "csrc", f), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest() != want.get("sources_sha256"):
+            return None
+        return float(want["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def log(msg):
@@ -234,6 +258,19 @@ def bench_serving(pl, seconds, rate, slots, budget_gib):
     return out
 
 
+def copy_calibration(mib):
+    """Three device-to-device copies of `mib` MiB: each reads and writes
+    exactly mib MiB, the scale for FETCH_SIZE / WRITE_SIZE readings."""
+    import torch
+    n = mib * 2 ** 20 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n * 8, "copies": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -246,11 +283,19 @@ def main():
     ap.add_argument("--n", type=int, default=2000)
     ap.add_argument("--K", type=int, default=1024)
     ap.add_argument("--M", type=int, default=8)
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
+                    help="form of the headline steps (the metric is quoted on fp64)")
     ap.add_argument("--extras", default=",".join(EXTRAS),
                     help=f"comma list from {EXTRAS}, or 'none'")
     ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device three times (the known-size "
+                         "reference for HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(omega points shard across GPUs by design only)", file=sys.stderr)
@@ -285,12 +330,13 @@ def main():
     inp = pl.Inputs(pr.locs, pr.y, pr.X, device="cuda")
     out = torch.empty((K, M, 10), dtype=torch.float64, device="cuda")
     beta = torch.empty((K, M, p), dtype=torch.float64, device="cuda")
-    work = torch.empty(pl.workspace_size(n, p, K, M), dtype=torch.uint8, device="cuda")
+    prec = args.precision
+    work = torch.empty(pl.workspace_size(n, p, K, M, prec), dtype=torch.uint8, device="cuda")
     log(f"workspace {work.numel() / 2**30:.2f} GiB")
 
     def step():
         pl.profile_loglik(None, None, None, pr.omega, pr.lam, inputs=inp, out=out, beta=beta,
-                          return_beta=True, work=work)
+                          return_beta=True, work=work, precision=prec)
 
     for i in range(args.warmup):
         step()
@@ -316,6 +362,17 @@ def main():
     gemm_ms = g["ms"] / max(1, g["launches"])
     gemm_flops = g["flops"] / max(1, g["launches"])
     gemm_tflops = g["flops"] / (g["ms"] / 1e3) / 1e12 if g["ms"] > 0 else 0.0
+    if prec == "fp64":
+        peak = PEAK_FP64_TFLOPS
+        kernel_name = "k_gemm_col (left-looking block-column update, MFMA f64)"
+        # counters were taken on this workload's launches only
+        default_shape = (n, K, M) == (2000, 1024, 8)
+        traffic = measured_traffic() if default_shape else None
+    else:
+        peak = PEAK_FP32_TFLOPS
+        kernel_name = ("k_gemm_col_mx + k_gemm_diag_mx (block-column update: FP32 MFMA with "
+                       "FP64 flushes off the diagonal, FP64 MFMA on diagonal tiles)")
+        traffic = None
     rec64 = {k: v.cpu().numpy() for k, v in pl.unpack_records(out).items()}
     rec64["beta"] = beta.cpu().numpy()
     del inp, out, beta, work
@@ -332,13 +389,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if prec == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"anisotropic Matern, n={n}, p={p}, K={K} omega x M={M} lambda, FP64",
-                   "n": n, "p": p, "K": K, "M": M, "precision": "fp64"},
-        "roofline": {"bound": "mfma", "achieved": gemm_tflops, "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": gemm_tflops / PEAK_FP64_TFLOPS, "traffic": None,
-                     "kernel": "k_gemm_col (left-looking block-column update, MFMA f64)",
+        "config": {"workload": (f"anisotropic Matern, n={n}, p={p}, K={K} omega x M={M} lambda, "
+                                f"{prec.upper() if prec == 'fp64' else 'mixed precision'}"),
+                   "n": n, "p": p, "K": K, "M": M, "precision": prec},
+        "roofline": {"bound": "mfma", "achieved": gemm_tflops, "peak": peak,
+                     "unit": "TFLOP/s", "frac": gemm_tflops / peak, "traffic": traffic,
+                     "kernel": kernel_name,
                      "launches_per_step": g["launches"] // args.steps,
                      "avg_launch_ms": gemm_ms, "alg_flops_per_launch": gemm_flops},
         "ms_p10": _pct(ts, 10), "ms_median": float(np.median(ts)), "ms_p90": _pct(ts, 90),
@@ -363,7 +421,7 @@ def main():
             line[name] = {"error": f"{type(e).__name__}: {e}"}
         torch.cuda.empty_cache()
 
-    if "mixed" in extras:
+    if "mixed" in extras and prec == "fp64":
         def mixed2000():
             st, rec = run_form(pl, pr, "mixed", args.steps, args.warmup)
             st.update(mixed_error(rec, rec64, n))
