@@ -171,6 +171,14 @@ def mixed_error(rec_mx, rec_64, n):
             "fallback_points": fb}
 
 
+def tune(pl, pr, tol=1e-3, sample=0):
+    """pl_autotune's choice of form for this workload under an error budget,
+    timed on `sample` omega points (0: all K of the workload)."""
+    sample = sample or pr.K
+    choice, report = pl.autotune(pr.locs, pr.y, pr.X, pr.omega, pr.lam, tol=tol, sample=sample)
+    return {"choice": choice, "report": report, "sample": sample}
+
+
 def bench_uneven(pl, runs):
     import numpy as np
     import torch
@@ -425,6 +433,7 @@ def main():
         def mixed2000():
             st, rec = run_form(pl, pr, "mixed", args.steps, args.warmup)
             st.update(mixed_error(rec, rec64, n))
+            st["autotune_tol_1e-3"] = tune(pl, pr)
             log(f"mixed n={n}: {st['ms_median']:.1f} ms, max |dl| {st['max_abs_dl']:.2e}")
             return st
         guarded("mixed_n2000", mixed2000)
@@ -441,6 +450,7 @@ def main():
             smx, rmx = run_form(pl, q, "mixed", max(2, args.steps // 2), 1)
             smx.update(mixed_error(rmx, r64, q.n))
             res["mixed"] = smx
+            res["autotune_tol_1e-3"] = tune(pl, q, sample=64 if big == 8000 else 0)
             log(f"n={big}: fp64 {s64['ms_median']:.1f} ms, mixed {smx['ms_median']:.1f} ms, "
                 f"max |dl| {smx['max_abs_dl']:.2e}")
             return res

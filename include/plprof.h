@@ -82,7 +82,11 @@ typedef struct pl_opts {
                            cross products (see pl_profile_loglik); 0 = none      */
   int64_t chunk;        /* max omega per device pass; 0 = as many as fit          */
   int32_t flags;        /* PL_OPT_* bits                                         */
-  int32_t reserved[3];
+  int32_t flush;        /* PL_MIXED: FP32 MFMA k-steps (4 products each) summed
+                           in FP32 before each FP64 fold in the off-diagonal
+                           updates: 1, 2 or 4; 0 = default (4).  Longer runs are
+                           faster and less accurate; see pl_autotune            */
+  int32_t reserved[2];
 } pl_opts;
 
 /* pl_opts.flags */
@@ -174,6 +178,37 @@ int pl_profile_loglik(const double* locs, const double* y, const double* X,
                       const double* lambda, int64_t M, pl_result* out,
                       double* beta_hat, const pl_opts* opts, void* work,
                       size_t work_bytes, void* stream);
+
+/*
+ * Autotuner for the form of pl_profile_loglik on one workload.  Candidates:
+ * PL_FP64, and PL_MIXED with flush 4, 2 and 1 (the k-depth, 16/8/4 products,
+ * of the FP32 partial-sum tiles of the mixed update).  Each is run on the
+ * first S = min(K, sample) omega points (sample 0: 64) -- one untimed call,
+ * then two timed with HIP events on `stream` -- and every mixed candidate's
+ * records are compared with the FP64 records of the same points.  The time
+ * per point depends on how many points share a launch (the mixed form issues
+ * more launches per block column), so S should be close to the number of
+ * points the caller will evaluate per call.  The fastest candidate whose
+ * largest |delta loglik| over the sampled records is <= tol is written to
+ * opts->precision and opts->flush (FP64 always qualifies; opts->refine, chunk
+ * and flags are used as given).  Mixed candidates are skipped when M + p > 32.
+ *   report  host, 8 doubles or NULL: per candidate (FP64, mixed flush 4, 2,
+ *           1) the measured milliseconds per omega point, then the max
+ *           |delta loglik| against FP64 (0 for FP64 itself, -1 if skipped).
+ *   work    device workspace of pl_autotune_workspace_size bytes (same
+ *           sample).
+ * The call synchronises `stream` (it reads the records back).
+ * Errors: as pl_profile_loglik for arguments 1-9; -10 sample < 0; -11 tol not
+ * finite or < 0; -12 opts NULL; -14/-15 workspace NULL or too small.
+ * pl_autotune_workspace_size: -1..-4 as pl_workspace_size, -5 sample < 0,
+ * -6 bytes NULL.
+ */
+int pl_autotune_workspace_size(int64_t n, int64_t p, int64_t K, int64_t M, int64_t sample,
+                               size_t* bytes);
+int pl_autotune(const double* locs, const double* y, const double* X, int64_t n, int64_t p,
+                const double* omega, int64_t K, const double* lambda, int64_t M, int64_t sample,
+                double tol, pl_opts* opts, double* report, void* work, size_t work_bytes,
+                void* stream);
 
 /*
  * Many independent datasets of uneven size (each with its own omega points)

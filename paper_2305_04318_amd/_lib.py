@@ -13,7 +13,8 @@ PL_MAX_P, PL_MAX_M = 32, 64
 # every symbol the header declares
 EXPORTS = ("pl_version", "pl_error_string", "pl_workspace_size", "pl_matern_workspace_size",
            "pl_matern_cov", "pl_chol_workspace_size", "pl_chol_batched", "pl_profile_loglik",
-           "pl_profiling_enable", "pl_profiling_read", "pl_batch_create",
+           "pl_profiling_enable", "pl_profiling_read", "pl_autotune_workspace_size",
+           "pl_autotune", "pl_batch_create",
            "pl_batch_workspace_size", "pl_batch_stats", "pl_batch_run", "pl_batch_error",
            "pl_batch_destroy")
 KERNEL_CLASSES = ("tables", "matern", "gemm", "potrf", "trsm", "other")
@@ -31,7 +32,7 @@ class PlResult(ctypes.Structure):
 class PlOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("refine", ctypes.c_int32),
                 ("chunk", ctypes.c_int64), ("flags", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("flush", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 PL_OPT_NO_FALLBACK = 1
@@ -85,6 +86,12 @@ def load(path: str = None):
     lib.pl_profiling_read.restype = ctypes.c_int
     lib.pl_profiling_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+    lib.pl_autotune_workspace_size.restype = ctypes.c_int
+    lib.pl_autotune_workspace_size.argtypes = [_I64, _I64, _I64, _I64, _I64, ctypes.POINTER(_SZ)]
+    lib.pl_autotune.restype = ctypes.c_int
+    lib.pl_autotune.argtypes = [_P, _P, _P, _I64, _I64, _P, _I64, _P, _I64, _I64, ctypes.c_double,
+                                ctypes.POINTER(PlOpts), ctypes.POINTER(ctypes.c_double), _P, _SZ,
+                                _P]
     lib.pl_batch_create.restype = ctypes.c_int
     lib.pl_batch_create.argtypes = [ctypes.POINTER(PlDataset), _I64, _I64, _P, _I64,
                                     ctypes.POINTER(PlOpts), ctypes.POINTER(ctypes.c_void_p)]

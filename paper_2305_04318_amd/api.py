@@ -38,12 +38,13 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _opts(precision="fp64", chunk=0, refine=1, fallback=True):
+def _opts(precision="fp64", chunk=0, refine=1, fallback=True, flush=0):
     o = PlOpts()
     o.precision = _PREC[precision]
     o.refine = int(refine)
     o.chunk = int(chunk or 0)
     o.flags = 0 if fallback else _lib.PL_OPT_NO_FALLBACK
+    o.flush = int(flush or 0)
     return o
 
 
@@ -119,7 +120,7 @@ class Inputs:
 
 def profile_loglik(locs, y, X, omega, lam, precision="fp64", chunk=0, return_beta=False,
                    out=None, beta=None, work=None, stream=None, device="cuda", inputs=None,
-                   refine=1, fallback=True):
+                   refine=1, fallback=True, flush=0):
     """Records for every (omega_k, lambda_m): dict of (K, M) tensors on the
     device, plus "beta" (K, M, p) when return_beta."""
     lib = load()
@@ -132,7 +133,7 @@ def profile_loglik(locs, y, X, omega, lam, precision="fp64", chunk=0, return_bet
         out = torch.empty((K, M, 10), dtype=torch.float64, device=dev)
     if return_beta and beta is None:
         beta = torch.empty((K, M, inp.p), dtype=torch.float64, device=dev)
-    o = _opts(precision, chunk, refine, fallback)
+    o = _opts(precision, chunk, refine, fallback, flush)
     if work is None:
         work = torch.empty(workspace_size(inp.n, inp.p, K, M, precision, chunk),
                            dtype=torch.uint8, device=dev)
@@ -146,6 +147,38 @@ def profile_loglik(locs, y, X, omega, lam, precision="fp64", chunk=0, return_bet
     if return_beta:
         res["beta"] = beta
     return res
+
+
+AUTOTUNE_CANDIDATES = (("fp64", 0), ("mixed", 4), ("mixed", 2), ("mixed", 1))
+
+
+def autotune(locs, y, X, omega, lam, tol=1e-3, sample=0, device="cuda", stream=None,
+             inputs=None):
+    """pl_autotune: the fastest form whose |delta loglik| against FP64 on the
+    first `sample` omega points (0: 64) is <= tol.  Returns (choice, report) with
+    choice = {"precision", "flush"} (keyword arguments of profile_loglik) and
+    report = per candidate {"ms_per_omega", "max_abs_dl"}."""
+    lib = load()
+    inp = inputs if inputs is not None else Inputs(locs, y, X, device)
+    om = _host_f64(omega, 5)
+    lm = _host_f64(lam).reshape(-1)
+    K, M = om.shape[0], lm.shape[0]
+    sz = ctypes.c_size_t(0)
+    check(lib.pl_autotune_workspace_size(inp.n, inp.p, K, M, int(sample), ctypes.byref(sz)),
+          "pl_autotune_workspace_size")
+    work = torch.empty(sz.value, dtype=torch.uint8, device=inp.device)
+    o = _opts()
+    rep = (ctypes.c_double * 8)()
+    rc = lib.pl_autotune(_ptr(inp.locs), _ptr(inp.y), _ptr(inp.Xc), inp.n, inp.p,
+                         om.ctypes.data_as(ctypes.c_void_p), K,
+                         lm.ctypes.data_as(ctypes.c_void_p), M, int(sample), float(tol),
+                         ctypes.byref(o), rep,
+                         _ptr(work), work.numel(), _stream_ptr(stream))
+    check(rc, "pl_autotune")
+    choice = {"precision": "mixed" if o.precision == _lib.PL_MIXED else "fp64", "flush": o.flush}
+    report = {f"{pr}" + (f"/flush{f}" if f else ""): {"ms_per_omega": rep[i], "max_abs_dl": rep[4 + i]}
+              for i, (pr, f) in enumerate(AUTOTUNE_CANDIDATES)}
+    return choice, report
 
 
 def profiling_enable(on: bool = True):

@@ -299,15 +299,17 @@ int pl_profile_loglik(const double* locs, const double* y, const double* X, int6
     if (!std::isfinite(lambda[m])) return -8;
   if (M < 1 || M > PL_MAX_M) return -9;
   if (!out) return -10;
-  int precision = PL_FP64, refine = 1, flags = 0;
+  int precision = PL_FP64, refine = 1, flags = 0, flush = MX_FLUSH;
   int64_t chunk = 0;
   if (opts) {
     precision = opts->precision;
     chunk = opts->chunk;
     refine = opts->refine;
     flags = opts->flags;
+    if (opts->flush != 0) flush = opts->flush;
     if (precision != PL_FP64 && precision != PL_MIXED) return -12;
     if (chunk < 0 || refine < 0 || refine > 1) return -12;
+    if (flush != 1 && flush != 2 && flush != 4) return -12;
   }
   const bool mixed = precision == PL_MIXED;
   if (mixed && M + p > 32) return PL_E_UNSUPPORTED;
@@ -399,7 +401,8 @@ int pl_profile_loglik(const double* locs, const double* y, const double* X, int6
         // J = 0 has no update: the diagonal kernel then copies V's FP64 tile
         const int nI = (J == 0) ? 1 : lay.Nv - J + 1;
         PL_CHECK(timed(PL_KC_GEMM, kk * gemm_col_flops(lay, J, nI), s, [&] {
-          return launch_gemm_col_mx(lay, m32, m64, v_stride64(lay), dscr, info, J, nI, kk, s);
+          return launch_gemm_col_mx(lay, m32, m64, v_stride64(lay), dscr, info, J, nI, kk, flush,
+                                    s);
         }));
         PL_CHECK(timed(PL_KC_POTRF, 0.0, s,
                        [&] { return launch_potrf_mx(lay, dscr, W32, logdet, info, J, kk, s); }));
@@ -441,6 +444,143 @@ int pl_profile_loglik(const double* locs, const double* y, const double* X, int6
         if (rc != PL_OK) return rc;
         PL_CHECK(launch_mark_fallback(out + k * M, (int)M, s));
       }
+    }
+  }
+  return PL_OK;
+}
+
+// ---- autotuner ------------------------------------------------------------------
+namespace {
+constexpr int TUNE_SAMPLE = 64;
+constexpr int TUNE_NCAND = 4;
+const int kTuneFlush[TUNE_NCAND] = {0, 4, 2, 1};  // 0: the FP64 form
+
+size_t tune_records_bytes(int64_t S, int64_t M) { return align_up((size_t)S * M * sizeof(pl_result)); }
+
+size_t tune_call_bytes(int64_t n, int64_t p, int64_t S, int64_t M, bool with_mixed) {
+  size_t b64 = 0, bmx = 0;
+  pl_opts o{};
+  o.precision = PL_FP64;
+  if (pl_workspace_size(n, p, S, M, &o, &b64) != PL_OK) return 0;
+  if (with_mixed) {
+    o.precision = PL_MIXED;
+    if (pl_workspace_size(n, p, S, M, &o, &bmx) != PL_OK) return 0;
+  }
+  return std::max(b64, bmx);
+}
+}  // namespace
+
+int pl_autotune_workspace_size(int64_t n, int64_t p, int64_t K, int64_t M, int64_t sample,
+                               size_t* bytes) {
+  if (n < 2 || n > (1 << 30)) return -1;
+  if (p < 1 || p >= n || p > PL_MAX_P) return -2;
+  if (K < 1 || K > (1 << 24)) return -3;
+  if (M < 1 || M > PL_MAX_M) return -4;
+  if (sample < 0) return -5;
+  if (!bytes) return -6;
+  const int64_t S = std::min<int64_t>(K, sample > 0 ? sample : TUNE_SAMPLE);
+  *bytes = tune_call_bytes(n, p, S, M, M + p <= 32) + 2 * tune_records_bytes(S, M);
+  return PL_OK;
+}
+
+int pl_autotune(const double* locs, const double* y, const double* X, int64_t n, int64_t p,
+                const double* omega, int64_t K, const double* lambda, int64_t M, int64_t sample,
+                double tol, pl_opts* opts, double* report, void* work, size_t work_bytes,
+                void* stream) {
+  if (!locs) return -1;
+  if (!y) return -2;
+  if (!X) return -3;
+  if (n < 2 || n > (1 << 30)) return -4;
+  if (p < 1 || p >= n || p > PL_MAX_P) return -5;
+  if (!omega) return -6;
+  if (K < 1 || K > (1 << 24)) return -7;
+  for (int64_t k = 0; k < K; ++k)
+    if (!omega_ok(omega + 5 * k)) return -6;
+  if (!lambda) return -8;
+  if (M < 1 || M > PL_MAX_M) return -9;
+  for (int64_t m = 0; m < M; ++m)
+    if (!std::isfinite(lambda[m])) return -8;
+  if (sample < 0) return -10;
+  if (!std::isfinite(tol) || tol < 0.0) return -11;
+  if (!opts) return -12;
+  if (!work) return -14;
+  const int64_t S = std::min<int64_t>(K, sample > 0 ? sample : TUNE_SAMPLE);
+  const bool with_mixed = M + p <= 32;
+  const size_t call_bytes = tune_call_bytes(n, p, S, M, with_mixed);
+  const size_t rec_bytes = tune_records_bytes(S, M);
+  if (call_bytes == 0 || work_bytes < call_bytes + 2 * rec_bytes) return -15;
+  hipStream_t s = (hipStream_t)stream;
+  pl_result* rec_ref = reinterpret_cast<pl_result*>((char*)work + call_bytes);
+  pl_result* rec_c = reinterpret_cast<pl_result*>((char*)work + call_bytes + rec_bytes);
+
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return PL_E_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return PL_E_HIP;
+  }
+  std::vector<pl_result> href((size_t)S * M), hc((size_t)S * M);
+  double ms_per[TUNE_NCAND], err[TUNE_NCAND];
+  int rc = PL_OK;
+  for (int c = 0; c < TUNE_NCAND && rc == PL_OK; ++c) {
+    ms_per[c] = -1.0;
+    err[c] = -1.0;
+    if (c > 0 && !with_mixed) continue;
+    pl_opts o = *opts;
+    o.precision = c == 0 ? PL_FP64 : PL_MIXED;
+    o.flush = kTuneFlush[c];
+    pl_result* dst = c == 0 ? rec_ref : rec_c;
+    // one untimed call (first use of the kernels), then two timed
+    rc = pl_profile_loglik(locs, y, X, n, p, omega, S, lambda, M, dst, nullptr, &o, work,
+                           call_bytes, stream);
+    if (rc != PL_OK) break;
+    if (hipEventRecord(e0, s) != hipSuccess) { rc = PL_E_HIP; break; }
+    for (int r = 0; r < 2 && rc == PL_OK; ++r)
+      rc = pl_profile_loglik(locs, y, X, n, p, omega, S, lambda, M, dst, nullptr, &o, work,
+                             call_bytes, stream);
+    if (rc != PL_OK) break;
+    float ms = 0.0f;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      rc = PL_E_HIP;
+      break;
+    }
+    ms_per[c] = ms / 2.0 / (double)S;
+    std::vector<pl_result>& h = c == 0 ? href : hc;
+    if (hipMemcpy(h.data(), dst, (size_t)S * M * sizeof(pl_result), hipMemcpyDeviceToHost) !=
+        hipSuccess) {
+      rc = PL_E_HIP;
+      break;
+    }
+    if (c == 0) {
+      err[c] = 0.0;
+      continue;
+    }
+    // largest |delta loglik| over records that FP64 evaluated; a record that is
+    // finite in one form only disqualifies the candidate
+    double e = 0.0;
+    for (size_t i = 0; i < href.size(); ++i) {
+      const double a = href[i].loglik, b = hc[i].loglik;
+      if (std::isfinite(a) != std::isfinite(b)) {
+        e = INFINITY;
+        break;
+      }
+      if (std::isfinite(a)) e = std::max(e, fabs(a - b));
+    }
+    err[c] = e;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc != PL_OK) return rc;
+  int best = 0;
+  for (int c = 1; c < TUNE_NCAND; ++c)
+    if (ms_per[c] >= 0.0 && err[c] >= 0.0 && err[c] <= tol && ms_per[c] < ms_per[best]) best = c;
+  opts->precision = best == 0 ? PL_FP64 : PL_MIXED;
+  opts->flush = kTuneFlush[best];
+  if (report) {
+    for (int c = 0; c < TUNE_NCAND; ++c) {
+      report[c] = ms_per[c];
+      report[TUNE_NCAND + c] = err[c];
     }
   }
   return PL_OK;

@@ -46,18 +46,9 @@ __global__ __launch_bounds__(256, 2) void k_gemm_col(Lay lay, double* __restrict
 // sums are accumulated in FP64, subtracted from V's FP64 tile and rounded to
 // FP32 once.  The diagonal tile: FP64 MFMA on the FP32 panels, subtracted from
 // the FP64 tile of V, written to an FP64 scratch tile for k_potrf.
-constexpr int MX_FLUSH = 4;  // FP32 MFMA k-steps (16 products) per FP64 flush (default)
-
-// FP64 flush interval of the mixed update: MX_FLUSH, or 1/2/4/8 from the
-// environment variable PLPROF_MX_FLUSH (an accuracy/speed study knob).
-static int mx_flush() {
-  static int v = [] {
-    const char* e = getenv("PLPROF_MX_FLUSH");
-    const int f = e ? atoi(e) : MX_FLUSH;
-    return (f == 1 || f == 2 || f == 4 || f == 8) ? f : MX_FLUSH;
-  }();
-  return v;
-}
+// The FP32 partial sums span 4 * flush products (flush = FP32 MFMA k-steps per
+// FP64 fold): 1, 2 or 4, chosen by the caller (default MX_FLUSH; pl_autotune
+// measures the speed/accuracy trade-off per workload).
 template <bool VEC, int FLUSH>
 __global__ __launch_bounds__(256, 2) void k_gemm_col_mx(Lay lay, float* __restrict__ m32,
                                                         const double* __restrict__ m64,
@@ -142,28 +133,27 @@ hipError_t launch_gemm_col(const Lay& lay, double* mats, const int32_t* info, in
 
 hipError_t launch_gemm_col_mx(const Lay& lay, float* m32, const double* m64, int64_t m64stride,
                               double* dscratch, const int32_t* info, int J, int nI, int K,
-                              hipStream_t s) {
+                              int flush, hipStream_t s) {
   // nI counts the tile rows from J down (the diagonal tile included)
   hipLaunchKernelGGL(k_gemm_diag_mx<true>, dim3(K), dim3(256), 0, s, lay, m32, m64, m64stride,
                      dscratch, info, J);
   if (nI > 1) {
     const int G = K * (nI - 1);
-    switch (mx_flush()) {
+    switch (flush) {
       case 1:
         hipLaunchKernelGGL((k_gemm_col_mx<true, 1>), dim3(G), dim3(256), 0, s, lay, m32, m64,
+                           m64stride, info, J, nI - 1, G);
+        break;
+      case 2:
+        hipLaunchKernelGGL((k_gemm_col_mx<true, 2>), dim3(G), dim3(256), 0, s, lay, m32, m64,
                            m64stride, info, J, nI - 1, G);
         break;
       case 4:
         hipLaunchKernelGGL((k_gemm_col_mx<true, 4>), dim3(G), dim3(256), 0, s, lay, m32, m64,
                            m64stride, info, J, nI - 1, G);
         break;
-      case 8:
-        hipLaunchKernelGGL((k_gemm_col_mx<true, 8>), dim3(G), dim3(256), 0, s, lay, m32, m64,
-                           m64stride, info, J, nI - 1, G);
-        break;
       default:
-        hipLaunchKernelGGL((k_gemm_col_mx<true, 2>), dim3(G), dim3(256), 0, s, lay, m32, m64,
-                           m64stride, info, J, nI - 1, G);
+        return hipErrorInvalidValue;
     }
   }
   return hipGetLastError();

@@ -109,9 +109,10 @@ hipError_t launch_matern_mixed(const Lay& lay, double* m64, int64_t stride64, fl
                                int K, hipStream_t s);
 hipError_t launch_border_init_f32(const Lay& lay, float* mats, const double* rhs, int K,
                                   hipStream_t s);
+constexpr int MX_FLUSH = 4;  // default FP32 MFMA k-steps per FP64 fold of the mixed update
 hipError_t launch_gemm_col_mx(const Lay& lay, float* m32, const double* m64, int64_t m64stride,
                               double* dscratch, const int32_t* info, int J, int nI, int K,
-                              hipStream_t s);
+                              int flush, hipStream_t s);
 hipError_t launch_potrf_mx(const Lay& lay, double* dscratch, float* W32, double* logdet,
                            int32_t* info, int J, int K, hipStream_t s);
 hipError_t launch_trsm_mx(const Lay& lay, float* m32, const float* W32, const int32_t* info, int J,

@@ -87,6 +87,10 @@ def test_profile_argument_errors():
     o = _lib.PlOpts()
     o.precision = 7
     assert _call(opts=o) == -12
+    o = _lib.PlOpts()
+    o.precision = 1
+    o.flush = 3
+    assert _call(opts=o) == -12
     assert _call(work=0) == -13
     assert _call(wb=16) == -14
 
@@ -103,6 +107,45 @@ def test_matern_and_chol_argument_errors():
     assert lib.pl_chol_batched(P(1), 10, 1, 9, P(1), P(1), P(1), 1 << 30, None) == -4
     assert lib.pl_chol_batched(P(1), 10, 1, 10, P(1), None, P(1), 1 << 30, None) == -6
     assert lib.pl_chol_batched(P(1), 10, 1, 10, P(1), P(1), P(1), 8, None) == -8
+
+
+def test_opts_struct_layout():
+    # precision, refine, chunk, flags, flush, reserved[2]: 32 bytes
+    assert ctypes.sizeof(_lib.PlOpts) == 32
+    assert _lib.PlOpts.chunk.offset == 8 and _lib.PlOpts.flush.offset == 20
+
+
+def test_autotune_argument_errors_and_workspace():
+    lib = pl.load()
+    P = ctypes.c_void_p
+    om = np.array([[1.0, 1.0, 0.1, 1.0, 0.0]] * 100)
+    lm = np.zeros(4)
+    o = _lib.PlOpts()
+
+    def call(locs=1, tol=1e-3, opts=True, work=1, wb=1 << 40, n=500, sample=0):
+        return lib.pl_autotune(P(locs) if locs else None, P(1), P(1), n, 3,
+                               om.ctypes.data_as(P), 100, lm.ctypes.data_as(P), 4, sample, tol,
+                               ctypes.byref(o) if opts else None, None,
+                               P(work) if work else None, wb, None)
+    assert call(locs=0) == -1
+    assert call(n=1) == -4
+    assert call(sample=-1) == -10
+    assert call(tol=-1.0) == -11 and call(tol=float("nan")) == -11
+    assert call(opts=False) == -12
+    assert call(work=0) == -14
+    assert call(wb=1024) == -15
+    b = ctypes.c_size_t(0)
+    assert lib.pl_autotune_workspace_size(500, 3, 100, 4, 0, ctypes.byref(b)) == 0
+    # holds the 64-point sample in the larger (mixed) layout plus two record sets
+    o2 = _lib.PlOpts()
+    o2.precision = 1
+    rc, mixed64 = _ws(500, 3, 64, 4, o2)
+    assert rc == 0 and b.value >= mixed64 + 2 * 64 * 4 * 80
+    assert lib.pl_autotune_workspace_size(500, 3, 0, 4, 0, ctypes.byref(b)) == -3
+    assert lib.pl_autotune_workspace_size(500, 3, 100, 4, -2, ctypes.byref(b)) == -5
+    b100 = ctypes.c_size_t(0)
+    assert lib.pl_autotune_workspace_size(500, 3, 100, 4, 100, ctypes.byref(b100)) == 0
+    assert b100.value > b.value
 
 
 def test_missing_library_fails_loudly(tmp_path):

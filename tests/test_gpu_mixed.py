@@ -83,3 +83,37 @@ def test_fallback_redoes_fp32_breakdowns_in_fp64(plprof_lib):
     scale = np.maximum(np.abs(ref["loglik"][1]), pr.n)
     assert np.max(np.abs(ll[1] - ref["loglik"][1]) / scale) <= 1e-8
     assert np.max(np.abs(ll[[0, 2]] - ref["loglik"][[0, 2]])) <= TOL_LL
+
+
+@pytest.mark.parametrize("flush", [1, 2, 4])
+def test_mixed_parity_each_flush(plprof_lib, flush):
+    """Every FP32 partial-sum depth the autotuner may pick stays within the
+    mixed tolerance of the oracle; shorter partial sums are not less accurate
+    here than the longest."""
+    pl = plprof_lib
+    pr = synth.small_problem(1000, p=3, K=3, M=4, seed=31)
+    ref = oracle.profile_loglik(pr.locs, pr.y, pr.X, pr.omega, pr.lam)
+    got = _run(pl, pr, precision="mixed", flush=flush)
+    d = np.abs(got["loglik"] - ref["loglik"]).max()
+    print(f"flush {flush}: max |dl| = {d:.2e}")
+    assert d <= TOL_LL
+
+
+def test_autotune_respects_error_budget(plprof_lib):
+    pl = plprof_lib
+    pr = synth.small_problem(900, p=3, K=10, M=4, seed=41)
+    # a zero budget admits only the FP64 form
+    choice, rep = pl.autotune(pr.locs, pr.y, pr.X, pr.omega, pr.lam, tol=0.0)
+    assert choice == {"precision": "fp64", "flush": 0}
+    assert rep["fp64"]["max_abs_dl"] == 0.0 and rep["fp64"]["ms_per_omega"] > 0
+    for key in ("mixed/flush4", "mixed/flush2", "mixed/flush1"):
+        assert rep[key]["ms_per_omega"] > 0 and 0 < rep[key]["max_abs_dl"] < TOL_LL
+    # a loose budget picks the fastest candidate, and the chosen form meets it
+    choice, rep = pl.autotune(pr.locs, pr.y, pr.X, pr.omega, pr.lam, tol=1e-2)
+    key = "fp64" if choice["precision"] == "fp64" else f"mixed/flush{choice['flush']}"
+    assert rep[key]["ms_per_omega"] == min(v["ms_per_omega"] for v in rep.values())
+    ref = oracle.profile_loglik(pr.locs, pr.y, pr.X, pr.omega[:3], pr.lam)
+    got = pl.profile_loglik(pr.locs, pr.y, pr.X, pr.omega[:3], pr.lam, **choice)
+    torch.cuda.synchronize()
+    assert np.abs(got["loglik"].cpu().numpy() - ref["loglik"]).max() <= 1e-2
+    print("autotune report", rep, "->", choice)
