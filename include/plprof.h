@@ -154,12 +154,17 @@ int pl_chol_batched(double* V, int64_t n, int64_t K, int64_t ld, double* logdet,
  *   out      device, K*M pl_result records, record k*M + m
  *   beta_hat device, K*M*p doubles (GLS estimate for record k*M+m at
  *            beta_hat + (k*M+m)*p), or NULL
+ *   xvx_inv  device, K*p*p doubles: (X^T V_k^-1 X)^-1 row-major at
+ *            xvx_inv + k*p*p (NaN where it does not exist), or NULL.  With
+ *            the records it gives the profiles of single coefficients and of
+ *            sigma (Section 3.3, "Profile likelihood for beta_p" and "for
+ *            sigma"); see pl_profile_curves.
  *   opts     NULL for defaults
  *   work     device workspace, see pl_workspace_size
  * Errors: -1 locs, -2 y, -3 X NULL; -4 n < 2; -5 p < 1, p >= n or p > PL_MAX_P;
  * -6 omega NULL or out of domain (as pl_matern_cov); -7 K < 1;
  * -8 lambda NULL or not finite; -9 M < 1 or M > PL_MAX_M; -10 out NULL;
- * -12 bad option; -13/-14 workspace NULL or too small; PL_E_UNSUPPORTED for
+ * -13 bad option; -14/-15 workspace NULL or too small; PL_E_UNSUPPORTED for
  * PL_MIXED with M + p > 32.
  * y <= 0 is detected on the device: every record then carries PL_INFO_BAD_Y.
  *
@@ -176,8 +181,45 @@ int pl_chol_batched(double* V, int64_t n, int64_t K, int64_t ld, double* logdet,
 int pl_profile_loglik(const double* locs, const double* y, const double* X,
                       int64_t n, int64_t p, const double* omega, int64_t K,
                       const double* lambda, int64_t M, pl_result* out,
-                      double* beta_hat, const pl_opts* opts, void* work,
+                      double* beta_hat, double* xvx_inv, const pl_opts* opts, void* work,
                       size_t work_bytes, void* stream);
+
+/*
+ * Profile curves of sigma and of single regression coefficients from the
+ * output of pl_profile_loglik (Section 3.3, the subsections "Profile
+ * likelihood for beta_p" and "Profile likelihood for sigma", maximised over
+ * the evaluated points as in Step 6).  For every grid value the curve is the
+ * maximum over the usable records (info 0 or PL_INFO_FALLBACK) of
+ *   sigma:   -1/2 [SSR/sigma^2 + n log sigma^2 + log|V| + n log 2 pi]
+ *            + (lambda - 1) J                    (equation "profileSigma");
+ *   beta_j:  the likelihood with beta_j fixed at b and the other coefficients
+ *            and sigma at their constrained maximum-likelihood values,
+ *            -1/2 [n log(SSR_b/n) + log|V| + n log 2 pi + n] + (lambda - 1) J
+ *            with SSR_b = SSR + (b - betahat_j)^2 / [(X^T V^-1 X)^-1]_jj, the
+ *            closed form of the cross-product identities of equation
+ *            "profilebetai".
+ *   rec, beta_hat, xvx_inv  device, as written by one pl_profile_loglik call
+ *            (K*M records; beta_hat and xvx_inv may be NULL when Gb = 0)
+ *   n, p, K, lambda (host, M values), M        as in that call
+ *   sigma_grid  host, Gs values > 0          beta_grid  host, p x Gb row-major
+ *   prof_sigma  device, Gs doubles           arg_sigma  device, Gs int64 or NULL
+ *   prof_beta   device, p*Gb doubles         arg_beta   device, p*Gb int64 or NULL
+ *   (arg: record index k*M + m attaining the maximum, the smallest on ties;
+ *   -1 and a curve value of -inf when no record is usable)
+ *   work     device, pl_curves_workspace_size(p, M, Gs, Gb) bytes.
+ * Asynchronous on `stream`.  Errors: -1 rec NULL, -2/-3 beta_hat/xvx_inv NULL
+ * with Gb > 0, -4 n < 2, -5 p out of range, -6 K < 1, -7 lambda NULL or not
+ * finite, -8 M out of range, -9 a sigma value <= 0 or not finite, -10 Gs out
+ * of range or sigma_grid NULL, -11 a beta value not finite, -12 Gb out of
+ * range or beta_grid NULL, -13 prof_sigma NULL, -15 prof_beta NULL, -17/-18
+ * workspace NULL or too small.
+ */
+int pl_curves_workspace_size(int64_t p, int64_t M, int64_t Gs, int64_t Gb, size_t* bytes);
+int pl_profile_curves(const pl_result* rec, const double* beta_hat, const double* xvx_inv,
+                      int64_t n, int64_t p, int64_t K, const double* lambda, int64_t M,
+                      const double* sigma_grid, int64_t Gs, const double* beta_grid, int64_t Gb,
+                      double* prof_sigma, int64_t* arg_sigma, double* prof_beta,
+                      int64_t* arg_beta, void* work, size_t work_bytes, void* stream);
 
 /*
  * Autotuner for the form of pl_profile_loglik on one workload.  Candidates:

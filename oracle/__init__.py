@@ -13,7 +13,9 @@ Every function is written from the paper's statement of the method:
     (the two displays after it) and the profile log-likelihood (equation
     "profile"), plus the sufficient statistics of Table "tab:tocpu" and the
     Step 3 sub-steps (Section 3.3),
-  * the restricted (REML) profile log-likelihood of the Appendix.
+  * the restricted (REML) profile log-likelihood of the Appendix,
+  * the profile curves of sigma and of single regression coefficients
+    (Section 3.3, "Profile likelihood for beta_p" and "for sigma").
 
 Readings of points where the paper is garbled or silent are listed in the
 project's design notes; the ones that change arithmetic are repeated where
@@ -32,10 +34,11 @@ from .bessel import log_kv, kv_quadrature_log, matern_halfint, log_matern
 from .model import boxcox, scaled_distance, matern_corr, build_V, aniso_ranges
 from .likelihood import (profile_loglik, profile_point, full_loglik,
                          profile_loglik_bruteforce, RESULT_FIELDS)
+from .curves import cross_products, curves
 
 __all__ = [
     "log_kv", "kv_quadrature_log", "matern_halfint", "log_matern",
     "boxcox", "scaled_distance", "matern_corr", "build_V", "aniso_ranges",
     "profile_loglik", "profile_point", "full_loglik", "profile_loglik_bruteforce",
-    "RESULT_FIELDS",
+    "RESULT_FIELDS", "cross_products", "curves",
 ]

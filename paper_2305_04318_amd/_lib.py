@@ -13,7 +13,8 @@ PL_MAX_P, PL_MAX_M = 32, 64
 # every symbol the header declares
 EXPORTS = ("pl_version", "pl_error_string", "pl_workspace_size", "pl_matern_workspace_size",
            "pl_matern_cov", "pl_chol_workspace_size", "pl_chol_batched", "pl_profile_loglik",
-           "pl_profiling_enable", "pl_profiling_read", "pl_autotune_workspace_size",
+           "pl_profiling_enable", "pl_profiling_read", "pl_curves_workspace_size",
+           "pl_profile_curves", "pl_autotune_workspace_size",
            "pl_autotune", "pl_batch_create",
            "pl_batch_workspace_size", "pl_batch_stats", "pl_batch_run", "pl_batch_error",
            "pl_batch_destroy")
@@ -79,8 +80,13 @@ def load(path: str = None):
     lib.pl_chol_batched.restype = ctypes.c_int
     lib.pl_chol_batched.argtypes = [_P, _I64, _I64, _I64, _P, _P, _P, _SZ, _P]
     lib.pl_profile_loglik.restype = ctypes.c_int
-    lib.pl_profile_loglik.argtypes = [_P, _P, _P, _I64, _I64, _P, _I64, _P, _I64, _P, _P,
+    lib.pl_profile_loglik.argtypes = [_P, _P, _P, _I64, _I64, _P, _I64, _P, _I64, _P, _P, _P,
                                       ctypes.POINTER(PlOpts), _P, _SZ, _P]
+    lib.pl_curves_workspace_size.restype = ctypes.c_int
+    lib.pl_curves_workspace_size.argtypes = [_I64, _I64, _I64, _I64, ctypes.POINTER(_SZ)]
+    lib.pl_profile_curves.restype = ctypes.c_int
+    lib.pl_profile_curves.argtypes = [_P, _P, _P, _I64, _I64, _I64, _P, _I64, _P, _I64, _P, _I64,
+                                      _P, _P, _P, _P, _P, _SZ, _P]
     lib.pl_profiling_enable.restype = ctypes.c_int
     lib.pl_profiling_enable.argtypes = [ctypes.c_int]
     lib.pl_profiling_read.restype = ctypes.c_int

@@ -120,9 +120,10 @@ class Inputs:
 
 def profile_loglik(locs, y, X, omega, lam, precision="fp64", chunk=0, return_beta=False,
                    out=None, beta=None, work=None, stream=None, device="cuda", inputs=None,
-                   refine=1, fallback=True, flush=0):
+                   refine=1, fallback=True, flush=0, return_xvx_inv=False, xvx_inv=None):
     """Records for every (omega_k, lambda_m): dict of (K, M) tensors on the
-    device, plus "beta" (K, M, p) when return_beta."""
+    device, plus "beta" (K, M, p) when return_beta and "xvx_inv" (K, p, p),
+    (X^T V_k^-1 X)^-1, when return_xvx_inv."""
     lib = load()
     inp = inputs if inputs is not None else Inputs(locs, y, X, device)
     om = _host_f64(omega, 5)
@@ -133,6 +134,8 @@ def profile_loglik(locs, y, X, omega, lam, precision="fp64", chunk=0, return_bet
         out = torch.empty((K, M, 10), dtype=torch.float64, device=dev)
     if return_beta and beta is None:
         beta = torch.empty((K, M, inp.p), dtype=torch.float64, device=dev)
+    if return_xvx_inv and xvx_inv is None:
+        xvx_inv = torch.empty((K, inp.p, inp.p), dtype=torch.float64, device=dev)
     o = _opts(precision, chunk, refine, fallback, flush)
     if work is None:
         work = torch.empty(workspace_size(inp.n, inp.p, K, M, precision, chunk),
@@ -140,13 +143,65 @@ def profile_loglik(locs, y, X, omega, lam, precision="fp64", chunk=0, return_bet
     rc = lib.pl_profile_loglik(_ptr(inp.locs), _ptr(inp.y), _ptr(inp.Xc), inp.n, inp.p,
                                om.ctypes.data_as(ctypes.c_void_p), K,
                                lm.ctypes.data_as(ctypes.c_void_p), M, _ptr(out),
-                               _ptr(beta) if return_beta else None, ctypes.byref(o),
+                               _ptr(beta) if return_beta else None,
+                               _ptr(xvx_inv) if return_xvx_inv else None, ctypes.byref(o),
                                _ptr(work), work.numel(), _stream_ptr(stream))
     check(rc, "pl_profile_loglik")
     res = unpack_records(out)
+    res["records"] = out
     if return_beta:
         res["beta"] = beta
+    if return_xvx_inv:
+        res["xvx_inv"] = xvx_inv
     return res
+
+
+def profile_curves(res, lam, n, sigma_grid=None, beta_grid=None, stream=None):
+    """pl_profile_curves over the output `res` of one profile_loglik call
+    (made with return_beta and return_xvx_inv when beta_grid is given).
+    sigma_grid: (Gs,) values > 0; beta_grid: (p, Gb), row j the values of
+    coefficient j.  Returns a dict with "sigma" (Gs,), "sigma_arg" (Gs,),
+    "beta" (p, Gb), "beta_arg" (p, Gb) device tensors (arg = record index
+    k*M + m of the maximum)."""
+    lib = load()
+    rec = res["records"]
+    K, M = rec.shape[0], rec.shape[1]
+    lm = _host_f64(lam).reshape(-1)
+    if lm.shape[0] != M:
+        raise ValueError("lam must be the lambda values of that call")
+    dev = rec.device
+    sg = _host_f64(sigma_grid).reshape(-1) if sigma_grid is not None else np.zeros(0)
+    Gs = sg.shape[0]
+    beta = res.get("beta")
+    xvi = res.get("xvx_inv")
+    p = beta.shape[2] if beta is not None else (xvi.shape[1] if xvi is not None else 1)
+    if beta_grid is not None:
+        if beta is None or xvi is None:
+            raise ValueError("beta curves need return_beta and return_xvx_inv")
+        bg = _host_f64(beta_grid)
+        if bg.ndim != 2 or bg.shape[0] != p:
+            raise ValueError(f"beta_grid must be (p={p}, Gb)")
+        bg = np.ascontiguousarray(bg)
+    else:
+        bg = np.zeros((p, 0))
+    Gb = bg.shape[1]
+    prof_s = torch.empty(max(Gs, 1), dtype=torch.float64, device=dev)
+    arg_s = torch.empty(max(Gs, 1), dtype=torch.int64, device=dev)
+    prof_b = torch.empty((p, max(Gb, 1)), dtype=torch.float64, device=dev)
+    arg_b = torch.empty((p, max(Gb, 1)), dtype=torch.int64, device=dev)
+    sz = ctypes.c_size_t(0)
+    check(lib.pl_curves_workspace_size(p, M, Gs, Gb, ctypes.byref(sz)), "pl_curves_workspace_size")
+    work = torch.empty(max(1, sz.value), dtype=torch.uint8, device=dev)
+    rc = lib.pl_profile_curves(_ptr(rec), _ptr(beta) if beta is not None else None,
+                               _ptr(xvi) if xvi is not None else None, int(n), p, K,
+                               lm.ctypes.data_as(ctypes.c_void_p), M,
+                               sg.ctypes.data_as(ctypes.c_void_p), Gs,
+                               bg.ctypes.data_as(ctypes.c_void_p), Gb, _ptr(prof_s), _ptr(arg_s),
+                               _ptr(prof_b), _ptr(arg_b), _ptr(work), work.numel(),
+                               _stream_ptr(stream))
+    check(rc, "pl_profile_curves")
+    return {"sigma": prof_s[:Gs], "sigma_arg": arg_s[:Gs], "beta": prof_b[:, :Gb],
+            "beta_arg": arg_b[:, :Gb]}
 
 
 AUTOTUNE_CANDIDATES = (("fp64", 0), ("mixed", 4), ("mixed", 2), ("mixed", 1))

@@ -96,20 +96,6 @@ size_t fixed_bytes(int64_t n, int64_t K, int64_t M, const Lay& lay) {
   return b;
 }
 
-// Host buffer kept alive until the stream has consumed the copy from it.
-void copy_h2d_async(void* dst, const void* src, size_t bytes, hipStream_t s, hipError_t* err) {
-  char* hold = new char[bytes];
-  memcpy(hold, src, bytes);
-  hipError_t e = hipMemcpyAsync(dst, hold, bytes, hipMemcpyHostToDevice, s);
-  if (e != hipSuccess) {
-    delete[] hold;
-    *err = e;
-    return;
-  }
-  e = hipLaunchHostFunc(s, [](void* p) { delete[] static_cast<char*>(p); }, hold);
-  if (e != hipSuccess) *err = e;
-}
-
 #define PL_CHECK(call)                        \
   do {                                        \
     hipError_t _e = (call);                   \
@@ -169,6 +155,21 @@ double gemm_col_flops(const Lay& lay, int J, int nI) {
 
 }  // namespace
 
+// Host-to-device copy of a small host array ordered on the stream: the bytes
+// are copied into a heap buffer that a host callback on the stream frees once
+// the copy has consumed it, so the caller may reuse its array at once.
+hipError_t plk::stage_h2d(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  char* hold = new char[bytes];
+  memcpy(hold, src, bytes);
+  hipError_t e = hipMemcpyAsync(dst, hold, bytes, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) {
+    delete[] hold;
+    return e;
+  }
+  return hipLaunchHostFunc(s, [](void* p) { delete[] static_cast<char*>(p); }, hold);
+}
+
 extern "C" {
 
 const char* pl_version(void) { return "plprof 0.1 (gfx950)"; }
@@ -212,9 +213,7 @@ int pl_matern_cov(const double* locs, int64_t n, const double* omega, int64_t K,
   MaternParams* mp = cv.take<MaternParams>(K * sizeof(MaternParams));
   double* nodes = cv.take<double>((size_t)K * NP * NC * sizeof(double));
   double* tables = cv.take<double>((size_t)K * NP * NC * sizeof(double));
-  hipError_t err = hipSuccess;
-  copy_h2d_async(mp, hp.data(), K * sizeof(MaternParams), s, &err);
-  if (err != hipSuccess) return PL_E_HIP;
+  if (stage_h2d(mp, hp.data(), K * sizeof(MaternParams), s) != hipSuccess) return PL_E_HIP;
   PL_CHECK(timed(PL_KC_TABLES, 0.0, s, [&] { return launch_cheb_tables(mp, nodes, tables, (int)K, s); }));
   PL_CHECK(timed(PL_KC_MATERN, 0.0, s,
                  [&] { return launch_matern_colmajor(V, ld, (int)n, locs, mp, tables, (int)K, s); }));
@@ -283,8 +282,8 @@ int pl_workspace_size(int64_t n, int64_t p, int64_t K, int64_t M, const pl_opts*
 
 int pl_profile_loglik(const double* locs, const double* y, const double* X, int64_t n, int64_t p,
                       const double* omega, int64_t K, const double* lambda, int64_t M,
-                      pl_result* out, double* beta_hat, const pl_opts* opts, void* work,
-                      size_t work_bytes, void* stream) {
+                      pl_result* out, double* beta_hat, double* xvx_inv, const pl_opts* opts,
+                      void* work, size_t work_bytes, void* stream) {
   if (!locs) return -1;
   if (!y) return -2;
   if (!X) return -3;
@@ -307,19 +306,19 @@ int pl_profile_loglik(const double* locs, const double* y, const double* X, int6
     refine = opts->refine;
     flags = opts->flags;
     if (opts->flush != 0) flush = opts->flush;
-    if (precision != PL_FP64 && precision != PL_MIXED) return -12;
-    if (chunk < 0 || refine < 0 || refine > 1) return -12;
-    if (flush != 1 && flush != 2 && flush != 4) return -12;
+    if (precision != PL_FP64 && precision != PL_MIXED) return -13;
+    if (chunk < 0 || refine < 0 || refine > 1) return -13;
+    if (flush != 1 && flush != 2 && flush != 4) return -13;
   }
   const bool mixed = precision == PL_MIXED;
   if (mixed && M + p > 32) return PL_E_UNSUPPORTED;
-  if (!work) return -13;
+  if (!work) return -14;
   hipStream_t s = (hipStream_t)stream;
 
   const Lay lay = packed_layout(n, M + p);
   const size_t fixed = fixed_bytes(n, K, M, lay);
   const size_t per = mixed ? per_omega_bytes_mixed(lay) : per_omega_bytes(lay);
-  if (work_bytes < fixed + per) return -14;
+  if (work_bytes < fixed + per) return -15;
   int64_t kc = (int64_t)((work_bytes - fixed) / per);
   kc = std::min<int64_t>(kc, K);
   if (chunk > 0) kc = std::min<int64_t>(kc, chunk);
@@ -358,10 +357,9 @@ int pl_profile_loglik(const double* locs, const double* y, const double* X, int6
 
   std::vector<MaternParams> hp(K);
   for (int64_t k = 0; k < K; ++k) hp[k] = make_params(omega + 5 * k);
-  hipError_t err = hipSuccess;
-  copy_h2d_async(mp, hp.data(), K * sizeof(MaternParams), s, &err);
-  copy_h2d_async(lam_d, lambda, M * sizeof(double), s, &err);
-  if (err != hipSuccess) return PL_E_HIP;
+  if (stage_h2d(mp, hp.data(), K * sizeof(MaternParams), s) != hipSuccess ||
+      stage_h2d(lam_d, lambda, M * sizeof(double), s) != hipSuccess)
+    return PL_E_HIP;
 
   PL_CHECK(timed(PL_KC_TABLES, 0.0, s, [&] { return launch_cheb_tables(mp, nodes, tables, (int)K, s); }));
   PL_CHECK(timed(PL_KC_OTHER, 0.0, s, [&] {
@@ -419,7 +417,8 @@ int pl_profile_loglik(const double* locs, const double* y, const double* X, int6
     PL_CHECK(timed(PL_KC_OTHER, 0.0, s, [&] {
       hipError_t e = launch_finalize(lay, mats, slots, logdet, info, jac, yflags, lam_d, (int)n,
                                      (int)p, (int)M, kk, out + c0 * M,
-                                     beta_hat ? beta_hat + c0 * M * p : nullptr, s);
+                                     beta_hat ? beta_hat + c0 * M * p : nullptr,
+                                     xvx_inv ? xvx_inv + c0 * p * p : nullptr, s);
       if (e == hipSuccess) e = launch_copy_i32(info, info_all + c0, kk, s);
       return e;
     }));
@@ -440,7 +439,8 @@ int pl_profile_loglik(const double* locs, const double* y, const double* X, int6
       if (hinfo[k] > 0) {
         const int rc = pl_profile_loglik(locs, y, X, n, p, omega + 5 * k, 1, lambda, M,
                                          out + k * M, beta_hat ? beta_hat + k * M * p : nullptr,
-                                         &o64, work, work_bytes, stream);
+                                         xvx_inv ? xvx_inv + k * p * p : nullptr, &o64, work,
+                                         work_bytes, stream);
         if (rc != PL_OK) return rc;
         PL_CHECK(launch_mark_fallback(out + k * M, (int)M, s));
       }
@@ -531,13 +531,13 @@ int pl_autotune(const double* locs, const double* y, const double* X, int64_t n,
     o.flush = kTuneFlush[c];
     pl_result* dst = c == 0 ? rec_ref : rec_c;
     // one untimed call (first use of the kernels), then two timed
-    rc = pl_profile_loglik(locs, y, X, n, p, omega, S, lambda, M, dst, nullptr, &o, work,
-                           call_bytes, stream);
+    rc = pl_profile_loglik(locs, y, X, n, p, omega, S, lambda, M, dst, nullptr, nullptr, &o,
+                           work, call_bytes, stream);
     if (rc != PL_OK) break;
     if (hipEventRecord(e0, s) != hipSuccess) { rc = PL_E_HIP; break; }
     for (int r = 0; r < 2 && rc == PL_OK; ++r)
-      rc = pl_profile_loglik(locs, y, X, n, p, omega, S, lambda, M, dst, nullptr, &o, work,
-                             call_bytes, stream);
+      rc = pl_profile_loglik(locs, y, X, n, p, omega, S, lambda, M, dst, nullptr, nullptr, &o,
+                             work, call_bytes, stream);
     if (rc != PL_OK) break;
     float ms = 0.0f;
     if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||

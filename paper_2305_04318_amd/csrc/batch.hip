@@ -155,7 +155,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_persistent(BatchArgs a) {
         const int64_t rec = (int64_t)u.om * a.M;
         dev_finalize(base + lay.tile_off(u.Nv, u.Nv), a.TB, a.logdet[tk.unit], a.info[tk.unit],
                      a.jac[u.d], a.yflags[u.d] != 0, a.lam, d.n, a.p, a.M, a.out + rec,
-                     a.beta ? a.beta + rec * a.p : nullptr, smem);
+                     a.beta ? a.beta + rec * a.p : nullptr, nullptr, smem);
         break;
       }
     }

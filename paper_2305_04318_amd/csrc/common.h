@@ -77,6 +77,9 @@ __device__ inline int xcd_remap(int wg, int G) {
   return x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
 }
 
+// Stream-ordered copy of a small host array (the caller may reuse it at once).
+hipError_t stage_h2d(void* dst, const void* src, size_t bytes, hipStream_t s);
+
 // ---- launch wrappers (defined in the .hip files) --------------------------
 hipError_t launch_cheb_tables(const MaternParams* mp, double* nodes, double* tables,
                               int K, hipStream_t s);
@@ -102,7 +105,7 @@ hipError_t launch_border_init(const Lay& lay, double* mats, const double* rhs, i
 hipError_t launch_finalize(const Lay& lay, const double* mats, const double* slots,
                            const double* logdet, const int32_t* info, const double* jac,
                            const int32_t* flags, const double* lam, int n, int p, int M, int K,
-                           pl_result* out, double* beta, hipStream_t s);
+                           pl_result* out, double* beta, double* xvi, hipStream_t s);
 // mixed form
 hipError_t launch_matern_mixed(const Lay& lay, double* m64, int64_t stride64, float* m32,
                                const double* locs, const MaternParams* mp, const double* tables,

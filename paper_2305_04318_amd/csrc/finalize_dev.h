@@ -17,12 +17,17 @@ constexpr int FIN_SMEM_DOUBLES = PL_MAX_P * PL_MAX_P + PL_MAX_M * PL_MAX_P + 2;
 //   c_m = Q^-1 X^T V^-1 y'_m          (Step 6)
 //   ssqBetahat_m = c_m^T c_m          (Step 7)
 //   ssqResidual_m = ssqY_m - ssqBetahat_m (Step 8); beta-hat = Q^-T c_m.
+//   (X^T V^-1 X)^-1 = Q^-T Q^-1     (the sampling covariance of beta-hat up to
+//                                    sigma^2; the profile of a single
+//                                    coefficient follows from its diagonal)
 // All threads of the workgroup take part; records go to out[0..M), beta-hat
-// (if not NULL) to beta[0..M*p).
+// (if not NULL) to beta[0..M*p), (X^T V^-1 X)^-1 (if not NULL, row-major p x p,
+// NaN when it does not exist) to xvi[0..p*p).
 __device__ __forceinline__ void dev_finalize(const double* S, int TB, double ldv, int inf,
                                              double J, bool bady, const double* __restrict__ lam,
                                              int n, int p, int M, pl_result* __restrict__ out,
-                                             double* __restrict__ beta, double* smem) {
+                                             double* __restrict__ beta, double* __restrict__ xvi,
+                                             double* smem) {
   double* Q = smem;
   double* cm = smem + PL_MAX_P * PL_MAX_P;
   double* shared_ldx = cm + PL_MAX_M * PL_MAX_P;
@@ -63,6 +68,36 @@ __device__ __forceinline__ void dev_finalize(const double* S, int TB, double ldv
   }
   const double ldx = *shared_ldx;
   const int rbad = *rank_bad;
+  if (xvi) {
+    // Q^-1 by forward substitution, one column per thread, in the c buffer
+    // (free until the record loop below)
+    double* Qi = cm;
+    const bool ok = !bady && inf == 0 && !rbad;
+    if (ok) {
+      for (int j = tid; j < p; j += nt) {
+        for (int i = 0; i < p; ++i) {
+          double v = 0.0;
+          if (i >= j) {
+            v = (i == j) ? 1.0 : 0.0;
+            for (int k = j; k < i; ++k) v -= Q[i * PL_MAX_P + k] * Qi[k * PL_MAX_P + j];
+            v /= Q[i * PL_MAX_P + i];
+          }
+          Qi[i * PL_MAX_P + j] = v;
+        }
+      }
+      __syncthreads();
+    }
+    for (int idx = tid; idx < p * p; idx += nt) {
+      const int i = idx / p, j = idx % p;
+      double v = NAN;
+      if (ok) {
+        v = 0.0;
+        for (int k = (i > j ? i : j); k < p; ++k) v += Qi[k * PL_MAX_P + i] * Qi[k * PL_MAX_P + j];
+      }
+      xvi[idx] = v;
+    }
+    __syncthreads();
+  }
   for (int m = tid; m < M; m += nt) {
     pl_result rec;
     rec.jacobian = J;

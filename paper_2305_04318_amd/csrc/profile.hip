@@ -312,7 +312,8 @@ __global__ __launch_bounds__(64) void k_finalize(Lay lay, const double* __restri
                                                  const int32_t* __restrict__ flags,
                                                  const double* __restrict__ lam, int n, int p,
                                                  int M, pl_result* __restrict__ out,
-                                                 double* __restrict__ beta) {
+                                                 double* __restrict__ beta,
+                                                 double* __restrict__ xvi) {
   __shared__ double smem[FIN_SMEM_DOUBLES];
   __shared__ double Sr[32 * 32];
   const int k = blockIdx.x;
@@ -333,15 +334,16 @@ __global__ __launch_bounds__(64) void k_finalize(Lay lay, const double* __restri
     S = Sr;
   }
   dev_finalize(S, TB, logdet[k], info[k], jac[0], flags[0] != 0, lam, n, p, M,
-               out + (int64_t)k * M, beta ? beta + (int64_t)k * M * p : nullptr, smem);
+               out + (int64_t)k * M, beta ? beta + (int64_t)k * M * p : nullptr,
+               xvi ? xvi + (int64_t)k * p * p : nullptr, smem);
 }
 
 hipError_t launch_finalize(const Lay& lay, const double* mats, const double* slots,
                            const double* logdet, const int32_t* info, const double* jac,
                            const int32_t* flags, const double* lam, int n, int p, int M, int K,
-                           pl_result* out, double* beta, hipStream_t s) {
+                           pl_result* out, double* beta, double* xvi, hipStream_t s) {
   hipLaunchKernelGGL(k_finalize, dim3(K), dim3(64), 0, s, lay, mats, slots, logdet, info, jac,
-                     flags, lam, n, p, M, out, beta);
+                     flags, lam, n, p, M, out, beta, xvi);
   return hipGetLastError();
 }
 

@@ -65,7 +65,7 @@ def _call(locs=1, y=1, X=1, n=100, p=2, omega=None, K=1, lam=None, M=1, out=1, o
     vp = lambda v: ctypes.c_void_p(v) if v else None
     return lib.pl_profile_loglik(vp(locs), vp(y), vp(X), n, p,
                                  om.ctypes.data_as(ctypes.c_void_p), K,
-                                 lm.ctypes.data_as(ctypes.c_void_p), M, vp(out), None,
+                                 lm.ctypes.data_as(ctypes.c_void_p), M, vp(out), None, None,
                                  ctypes.byref(opts) if opts else None, vp(work), wb, None)
 
 
@@ -86,13 +86,13 @@ def test_profile_argument_errors():
     assert _call(out=0) == -10
     o = _lib.PlOpts()
     o.precision = 7
-    assert _call(opts=o) == -12
+    assert _call(opts=o) == -13
     o = _lib.PlOpts()
     o.precision = 1
     o.flush = 3
-    assert _call(opts=o) == -12
-    assert _call(work=0) == -13
-    assert _call(wb=16) == -14
+    assert _call(opts=o) == -13
+    assert _call(work=0) == -14
+    assert _call(wb=16) == -15
 
 
 def test_matern_and_chol_argument_errors():
@@ -146,6 +146,37 @@ def test_autotune_argument_errors_and_workspace():
     b100 = ctypes.c_size_t(0)
     assert lib.pl_autotune_workspace_size(500, 3, 100, 4, 100, ctypes.byref(b100)) == 0
     assert b100.value > b.value
+
+
+def test_curves_argument_errors():
+    lib = pl.load()
+    P = ctypes.c_void_p
+    lm = np.zeros(3)
+    sg = np.array([0.5, 1.0])
+    bg = np.zeros((2, 4))
+
+    def call(rec=1, beta=1, xvi=1, n=100, p=2, K=5, M=3, sgrid=sg, Gs=2, bgrid=bg, Gb=4,
+             ps=1, pb=1, work=1, wb=1 << 30):
+        vp = lambda v: P(v) if v else None
+        arr = lambda a: a.ctypes.data_as(P) if a is not None else None
+        return lib.pl_profile_curves(vp(rec), vp(beta), vp(xvi), n, p, K, lm.ctypes.data_as(P), M,
+                                     arr(sgrid), Gs, arr(bgrid), Gb, vp(ps), None, vp(pb), None,
+                                     vp(work), wb, None)
+    assert call(rec=0) == -1
+    assert call(beta=0) == -2 and call(xvi=0) == -3
+    assert call(beta=0, xvi=0, Gb=0) != -2
+    assert call(n=1) == -4
+    assert call(p=0) == -5
+    assert call(K=0) == -6
+    assert call(M=0) == -8
+    assert call(sgrid=np.array([0.5, -1.0])) == -9
+    assert call(sgrid=None) == -10
+    assert call(bgrid=np.array([[0.0, np.nan, 0, 0], [0, 0, 0, 0]])) == -11
+    assert call(bgrid=None) == -12
+    assert call(ps=0) == -13 and call(pb=0) == -15
+    assert call(work=0) == -17 and call(wb=8) == -18
+    b = ctypes.c_size_t(0)
+    assert lib.pl_curves_workspace_size(2, 3, 2, 4, ctypes.byref(b)) == 0 and b.value >= 8 * 13
 
 
 def test_missing_library_fails_loudly(tmp_path):
