@@ -141,7 +141,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_persistent(BatchArgs a) {
                            base + lay.tile_off(tk.I, tk.J), lay.tile_ld(tk.I), nullptr, smem);
         break;
       case TK_GEMM:
-        if (!failed) dev_gemm_col<true>(lay, base, tk.J, tk.I, smem);
+        if (!failed) dev_gemm_col<true, 1>(lay, base, tk.J, tk.I, smem);
         break;
       case TK_POTRF:
         if (!failed)
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_persistent(BatchArgs a) {
                        a.logdet + tk.unit, a.info + tk.unit, tk.J, smem);
         break;
       case TK_TRSM:
-        if (!failed) dev_trsm<double, true, 1>(lay, base, W, tk.J, tk.I, smem);
+        if (!failed) dev_trsm<double, true, 1, 1>(lay, base, W, tk.J, tk.I, smem);
         break;
       default: {  // TK_FINAL
         const int64_t rec = (int64_t)u.om * a.M;

@@ -4,6 +4,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace plk {
@@ -80,7 +82,7 @@ __device__ __forceinline__ typename Piece<TS>::type fetch_piece(const TS* __rest
 constexpr int LROW = T + 4;         // LDS stride per k column (elements)
 constexpr int GEMM_LDS_BYTES = 2 * 2 * 16 * LROW * 8;
 
-template <typename TS, typename TC, bool VEC, int NJ = 4>
+template <typename TS, typename TC, bool VEC, int NJ = 4, int DEPTH = 2>
 __device__ __forceinline__ void wg_gemm_nt(typename MF<TC>::acc (&acc)[4][4], TS* lds,
                                            const TS* __restrict__ A, int64_t lda, int arows,
                                            const TS* __restrict__ B, int64_t ldb, int brows,
@@ -97,37 +99,102 @@ __device__ __forceinline__ void wg_gemm_nt(typename MF<TC>::acc (&acc)[4][4], TS
   // guards below are scalar branches, not exec masks
   ni = __builtin_amdgcn_readfirstlane(ni);
   do_mfma = __builtin_amdgcn_readfirstlane((int)do_mfma) != 0;
-  V ra[4], rb[4];
-  auto fetch = [&](int k0) {
+  if constexpr (DEPTH == 1) {
+    // one register set: chunk c + 1 is fetched while chunk c is multiplied
+    V ra[4], rb[4];
+    auto fetch = [&](int k0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int idx = tid + 256 * q;
+        const int col = idx / PPC, row = (idx % PPC) * N;
+        ra[q] = fetch_piece<TS, VEC>(A, lda, arows, k0 + col, kmax, row);
+        rb[q] = fetch_piece<TS, VEC>(B, ldb, brows, k0 + col, kmax, row);
+      }
+    };
+    auto stash = [&](int stage) {
+      TS* sa = lds + (stage * 2 + 0) * KC * LROW;
+      TS* sb = lds + (stage * 2 + 1) * KC * LROW;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int idx = tid + 256 * q;
+        const int col = idx / PPC, row = (idx % PPC) * N;
+        *reinterpret_cast<V*>(sa + col * LROW + row) = ra[q];
+        *reinterpret_cast<V*>(sb + col * LROW + row) = rb[q];
+      }
+    };
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    const int lr = lane & 15, lk = lane >> 4;
+    for (int c = 0; c < nchunks; ++c) {
+      const bool more = c + 1 < nchunks;
+      if (more) fetch((c + 1) * KC);
+      if (do_mfma) {
+        const TS* sa = lds + ((c & 1) * 2 + 0) * KC * LROW + 64 * wr + lr;
+        const TS* sb = lds + ((c & 1) * 2 + 1) * KC * LROW + 64 * wc + lr;
+#pragma unroll
+        for (int s4 = 0; s4 < KC / 4; ++s4) {
+          const int kk = 4 * s4 + lk;
+          TC a[4], b[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            a[i] = (TC)sa[kk * LROW + 16 * i];
+            b[i] = (TC)sb[kk * LROW + 16 * i];
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            if (i < ni) {
+#pragma unroll
+              for (int j = 0; j < NJ; ++j) acc[i][j] = MF<TC>::op(b[j], a[i], acc[i][j]);
+            }
+          }
+        }
+      }
+      if (more) stash((c + 1) & 1);
+      __syncthreads();
+    }
+    return;
+  }
+  // two register sets: chunk c + 2 is fetched while chunk c is multiplied and
+  // chunk c + 1 (fetched a chunk earlier) waits in registers for its LDS stage
+  V ra[2][4], rb[2][4];
+  auto fetch = [&](int k0, auto setc) {
+    constexpr int S = decltype(setc)::value;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int idx = tid + 256 * q;
       const int col = idx / PPC, row = (idx % PPC) * N;
-      ra[q] = fetch_piece<TS, VEC>(A, lda, arows, k0 + col, kmax, row);
-      rb[q] = fetch_piece<TS, VEC>(B, ldb, brows, k0 + col, kmax, row);
+      ra[S][q] = fetch_piece<TS, VEC>(A, lda, arows, k0 + col, kmax, row);
+      rb[S][q] = fetch_piece<TS, VEC>(B, ldb, brows, k0 + col, kmax, row);
     }
   };
-  auto stash = [&](int stage) {
-    TS* sa = lds + (stage * 2 + 0) * KC * LROW;
-    TS* sb = lds + (stage * 2 + 1) * KC * LROW;
+  auto stash = [&](auto setc) {
+    constexpr int S = decltype(setc)::value;  // register set = LDS stage
+    TS* sa = lds + (S * 2 + 0) * KC * LROW;
+    TS* sb = lds + (S * 2 + 1) * KC * LROW;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int idx = tid + 256 * q;
       const int col = idx / PPC, row = (idx % PPC) * N;
-      *reinterpret_cast<V*>(sa + col * LROW + row) = ra[q];
-      *reinterpret_cast<V*>(sb + col * LROW + row) = rb[q];
+      *reinterpret_cast<V*>(sa + col * LROW + row) = ra[S][q];
+      *reinterpret_cast<V*>(sb + col * LROW + row) = rb[S][q];
     }
   };
-  fetch(0);
-  stash(0);
+  using S0 = std::integral_constant<int, 0>;
+  using S1 = std::integral_constant<int, 1>;
+  fetch(0, S0{});
+  if (nchunks > 1) fetch(KC, S1{});
+  stash(S0{});
   __syncthreads();
   const int lr = lane & 15, lk = lane >> 4;
-  for (int c = 0; c < nchunks; ++c) {
-    const bool more = c + 1 < nchunks;
-    if (more) fetch((c + 1) * KC);
+  // chunk c (even: set/stage 0, odd: 1): fetch c + 2 into its own set, run
+  // its MFMAs from LDS stage c & 1, then move chunk c + 1 to the other stage
+  auto step = [&](int c, auto setc, auto other) {
+    constexpr int S = decltype(setc)::value;
+    if (c + 2 < nchunks) fetch((c + 2) * KC, setc);
     if (do_mfma) {
-      const TS* sa = lds + ((c & 1) * 2 + 0) * KC * LROW + 64 * wr + lr;
-      const TS* sb = lds + ((c & 1) * 2 + 1) * KC * LROW + 64 * wc + lr;
+      const TS* sa = lds + (S * 2 + 0) * KC * LROW + 64 * wr + lr;
+      const TS* sb = lds + (S * 2 + 1) * KC * LROW + 64 * wc + lr;
 #pragma unroll
       for (int s4 = 0; s4 < KC / 4; ++s4) {
         const int kk = 4 * s4 + lk;
@@ -146,8 +213,12 @@ __device__ __forceinline__ void wg_gemm_nt(typename MF<TC>::acc (&acc)[4][4], TS
         }
       }
     }
-    if (more) stash((c + 1) & 1);
+    if (c + 1 < nchunks) stash(other);
     __syncthreads();
+  };
+  for (int c = 0; c < nchunks; c += 2) {
+    step(c, S0{}, S1{});
+    if (c + 1 < nchunks) step(c + 1, S1{}, S0{});
   }
 }
 
@@ -320,7 +391,9 @@ __device__ __forceinline__ int nblk(int rows) { return rows <= 0 ? 0 : min(4, (r
 // ---- tile tasks -------------------------------------------------------------------
 
 // Left-looking update of tile (I, J), I >= J: C_IJ -= L_I,0:J L_J,0:J^T (FP64 MFMA).
-template <bool VEC>
+// DEPTH: chunks of the k range prefetched into registers (2 for the step
+// kernels; 1 where the caller is register-bound, the persistent batch kernel).
+template <bool VEC, int DEPTH = 2>
 __device__ __forceinline__ void dev_gemm_col(const Lay& lay, double* base, int J, int I, double* lds) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wr = wave >> 1, wc = wave & 1;
@@ -331,7 +404,7 @@ __device__ __forceinline__ void dev_gemm_col(const Lay& lay, double* base, int J
   const int kmax = min(J * T, lay.n);
   d4 acc[4][4];
   zero_acc<double>(acc);
-  wg_gemm_nt<double, double, VEC>(acc, lds, base + lay.tile_off(I, 0), lay.tile_ld(I), arows,
+  wg_gemm_nt<double, double, VEC, 4, DEPTH>(acc, lds, base + lay.tile_off(I, 0), lay.tile_ld(I), arows,
                                   base + lay.tile_off(J, 0), lay.tile_ld(J), brows, kmax, act, ni);
   if (act) {
     const int64_t ldc = lay.tile_ld(I);
@@ -341,7 +414,7 @@ __device__ __forceinline__ void dev_gemm_col(const Lay& lay, double* base, int J
 }
 
 // Panel solve of tile (I, J), I > J: L_IJ = C_IJ W^T with W = L_JJ^-1 (ld T).
-template <typename TS, bool VEC, int FLUSH>
+template <typename TS, bool VEC, int FLUSH, int DEPTH = 2>
 __device__ __forceinline__ void dev_trsm(const Lay& lay, TS* base, const TS* W, int J, int I, TS* lds) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wr = wave >> 1, wc = wave & 1;
@@ -356,7 +429,7 @@ __device__ __forceinline__ void dev_trsm(const Lay& lay, TS* base, const TS* W, 
   zero_acc<double>(acc);
   // the core's final barrier orders every read of C_IJ before the overwrite
   if constexpr (sizeof(TS) == 8) {
-    wg_gemm_nt<TS, TS, VEC>(acc, lds, Ct, ldc, arows, W, T, brows, brows, act, ni);
+    wg_gemm_nt<TS, TS, VEC, 4, DEPTH>(acc, lds, Ct, ldc, arows, W, T, brows, brows, act, ni);
     if (act) store64<double, false>(Co, ldc, Co, ldc, acc, war, wbr, lane);
   } else {
     wg_gemm_nt_f32x64<FLUSH>(acc, lds, Ct, ldc, arows, W, T, brows, brows, act, ni);
