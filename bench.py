@@ -210,6 +210,27 @@ def bench_uneven(pl, runs):
     b.close()
     del b
     torch.cuda.empty_cache()
+    # the same datasets as independent calls on four streams (the serving
+    # executor with every request present at the start), in both forms
+    from paper_2305_04318_amd import serve as sv
+    for prec in ("fp64", "mixed"):
+        reqs = [sv.Request(i, 0.0, p.locs, p.y, p.X, p.omega, p.lam, prec)
+                for i, p in enumerate(probs)]
+        ex = sv.GpuExecutor(64 << 30, slots=4)
+        sv.Server(ex).run(reqs[:8])  # untimed: first use of this form's kernels
+        reqs = [sv.Request(i, 0.0, p.locs, p.y, p.X, p.omega, p.lam, prec)
+                for i, p in enumerate(probs)]
+        t0 = time.perf_counter()
+        done = sv.Server(ex).run(reqs)
+        dt = time.perf_counter() - t0
+        ex.close()
+        del ex
+        torch.cuda.empty_cache()
+        bad = int(sum(np.sum((r.result["info"] != 0) & (r.result["info"] != pl.PL_INFO_FALLBACK))
+                      for r in done))
+        st[f"per_dataset_calls_{prec}"] = {"ms": dt * 1e3, "points_per_s": pts / dt,
+                                           "failed_points": bad}
+        log(f"uneven as {len(done)} calls on 4 streams, {prec}: {dt * 1e3:.0f} ms")
     return st
 
 

@@ -33,30 +33,6 @@ bool omega_ok(const double* om) {
          om[3] > 0.0;
 }
 
-// Constants for one omega = (phi_X, kappa, nu^2, phi_R, phi_A); phi_Y = phi_X / phi_R.
-MaternParams make_params(const double* om) {
-  MaternParams P{};
-  const double phix = om[0], kappa = om[1], nug = om[2], ratio = om[3], ang = om[4];
-  P.inv_phix = 1.0 / phix;
-  P.inv_phiy = ratio / phix;
-  P.cosA = cos(ang);
-  P.sinA = sin(ang);
-  P.sqrt8k = sqrt(8.0 * kappa);
-  P.nugget = nug;
-  P.kappa = kappa;
-  P.log_norm = (1.0 - kappa) * M_LN2 - lgamma(kappa);
-  // x_hi: beyond it rho < exp(-745) (below the smallest double).  From the
-  // large-argument form log rho ~ log_norm + 0.5 log(pi/2) + (kappa-1/2) log x - x,
-  // solved by fixed-point iteration, then widened for the neglected terms.
-  const double C = P.log_norm + 0.5 * log(M_PI / 2.0) + 760.0;
-  double x = std::max(C, 10.0);
-  for (int i = 0; i < 60; ++i) x = std::max(10.0, C + (kappa - 0.5) * log(x));
-  P.x_hi = 1.1 * x + 50.0;
-  P.u_a = log(X_LO);
-  P.inv_w = NP / (log(P.x_hi) - P.u_a);
-  return P;
-}
-
 Lay packed_layout(int64_t n, int64_t q) {
   Lay lay{};
   lay.kind = 0;
@@ -88,7 +64,7 @@ size_t per_omega_bytes_mixed(const Lay& lay) {
 size_t fixed_bytes(int64_t n, int64_t K, int64_t M, const Lay& lay) {
   size_t b = 0;
   b += align_up(K * sizeof(MaternParams));
-  b += 2 * align_up((size_t)K * NP * NC * sizeof(double));
+  b += 2 * align_up((size_t)K * TABLE * sizeof(double));
   b += align_up(M * sizeof(double));
   b += align_up((size_t)n * lay.TB * sizeof(double));
   b += align_up(sizeof(double)) + align_up(sizeof(int32_t));
@@ -155,6 +131,31 @@ double gemm_col_flops(const Lay& lay, int J, int nI) {
 
 }  // namespace
 
+// Constants for one omega = (phi_X, kappa, nu^2, phi_R, phi_A); phi_Y = phi_X / phi_R.
+MaternParams plk::make_matern_params(const double* om) {
+  MaternParams P{};
+  const double phix = om[0], kappa = om[1], nug = om[2], ratio = om[3], ang = om[4];
+  P.inv_phix = 1.0 / phix;
+  P.inv_phiy = ratio / phix;
+  P.cosA = cos(ang);
+  P.sinA = sin(ang);
+  P.k8 = 8.0 * kappa;
+  P.nugget = nug;
+  P.kappa = kappa;
+  P.log_norm = (1.0 - kappa) * M_LN2 - lgamma(kappa);
+  // x_hi: beyond it rho < exp(-745) (below the smallest double).  From the
+  // large-argument form log rho ~ log_norm + 0.5 log(pi/2) + (kappa-1/2) log x - x,
+  // solved by fixed-point iteration, then widened for the neglected terms;
+  // capped at the table's end (rho there is far below exp(-745) for every
+  // admissible shape).
+  const double C = P.log_norm + 0.5 * log(M_PI / 2.0) + 760.0;
+  double x = std::max(C, 10.0);
+  for (int i = 0; i < 60; ++i) x = std::max(10.0, C + (kappa - 0.5) * log(x));
+  const double x_hi = 1.1 * x + 50.0;
+  P.w_hi = std::min(x_hi * x_hi, ldexp(1.0, W_E_LO + NBIN));
+  return P;
+}
+
 // Host-to-device copy of a small host array ordered on the stream: the bytes
 // are copied into a heap buffer that a host callback on the stream frees once
 // the copy has consumed it, so the caller may reuse its array at once.
@@ -188,7 +189,7 @@ const char* pl_error_string(int code) {
 int pl_matern_workspace_size(int64_t K, size_t* bytes) {
   if (K < 1) return -1;
   if (!bytes) return -2;
-  *bytes = align_up(K * sizeof(MaternParams)) + 2 * align_up((size_t)K * NP * NC * sizeof(double));
+  *bytes = align_up(K * sizeof(MaternParams)) + 2 * align_up((size_t)K * TABLE * sizeof(double));
   return PL_OK;
 }
 
@@ -208,11 +209,11 @@ int pl_matern_cov(const double* locs, int64_t n, const double* omega, int64_t K,
   if (work_bytes < need) return -8;
   hipStream_t s = (hipStream_t)stream;
   std::vector<MaternParams> hp(K);
-  for (int64_t k = 0; k < K; ++k) hp[k] = make_params(omega + 5 * k);
+  for (int64_t k = 0; k < K; ++k) hp[k] = make_matern_params(omega + 5 * k);
   Carve cv{(char*)work};
   MaternParams* mp = cv.take<MaternParams>(K * sizeof(MaternParams));
-  double* nodes = cv.take<double>((size_t)K * NP * NC * sizeof(double));
-  double* tables = cv.take<double>((size_t)K * NP * NC * sizeof(double));
+  double* nodes = cv.take<double>((size_t)K * TABLE * sizeof(double));
+  double* tables = cv.take<double>((size_t)K * TABLE * sizeof(double));
   if (stage_h2d(mp, hp.data(), K * sizeof(MaternParams), s) != hipSuccess) return PL_E_HIP;
   PL_CHECK(timed(PL_KC_TABLES, 0.0, s, [&] { return launch_cheb_tables(mp, nodes, tables, (int)K, s); }));
   PL_CHECK(timed(PL_KC_MATERN, 0.0, s,
@@ -325,8 +326,8 @@ int pl_profile_loglik(const double* locs, const double* y, const double* X, int6
 
   Carve cv{(char*)work};
   MaternParams* mp = cv.take<MaternParams>(K * sizeof(MaternParams));
-  double* nodes = cv.take<double>((size_t)K * NP * NC * sizeof(double));
-  double* tables = cv.take<double>((size_t)K * NP * NC * sizeof(double));
+  double* nodes = cv.take<double>((size_t)K * TABLE * sizeof(double));
+  double* tables = cv.take<double>((size_t)K * TABLE * sizeof(double));
   double* lam_d = cv.take<double>(M * sizeof(double));
   double* rhs = cv.take<double>((size_t)n * lay.TB * sizeof(double));
   double* jac = cv.take<double>(sizeof(double));
@@ -356,7 +357,7 @@ int pl_profile_loglik(const double* locs, const double* y, const double* X, int6
   int32_t* info = cv.take<int32_t>((size_t)kc * sizeof(int32_t));
 
   std::vector<MaternParams> hp(K);
-  for (int64_t k = 0; k < K; ++k) hp[k] = make_params(omega + 5 * k);
+  for (int64_t k = 0; k < K; ++k) hp[k] = make_matern_params(omega + 5 * k);
   if (stage_h2d(mp, hp.data(), K * sizeof(MaternParams), s) != hipSuccess ||
       stage_h2d(lam_d, lambda, M * sizeof(double), s) != hipSuccess)
     return PL_E_HIP;
@@ -377,8 +378,8 @@ int pl_profile_loglik(const double* locs, const double* y, const double* X, int6
     }));
     PL_CHECK(timed(PL_KC_MATERN, 0.0, s, [&] {
       return mixed ? launch_matern_mixed(lay, m64, v_stride64(lay), m32, locs, mp + c0,
-                                         tables + c0 * NP * NC, kk, s)
-                   : launch_matern_packed(lay, mats, locs, mp + c0, tables + c0 * NP * NC, kk, s);
+                                         tables + c0 * TABLE, kk, s)
+                   : launch_matern_packed(lay, mats, locs, mp + c0, tables + c0 * TABLE, kk, s);
     }));
     if (!mixed) {
       for (int J = 0; J <= lay.Nv; ++J) {

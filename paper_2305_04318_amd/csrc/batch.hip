@@ -106,6 +106,9 @@ __device__ __forceinline__ Lay unit_lay(const BDataset& d, int Nv, int q, int TB
 
 __global__ __launch_bounds__(256, 2) void k_batch_persistent(BatchArgs a) {
   __shared__ __attribute__((aligned(16))) char smem_raw[GEMM_LDS_BYTES];
+  static_assert((TABLE + 2 * T) * 8 <= GEMM_LDS_BYTES, "covariance task staging");
+  static_assert(POTRF_SMEM_DOUBLES * 8 <= GEMM_LDS_BYTES, "factorisation task staging");
+  static_assert(FIN_SMEM_DOUBLES * 8 <= GEMM_LDS_BYTES, "finalize task staging");
   __shared__ int32_t s_task;
   double* smem = reinterpret_cast<double*>(smem_raw);
   for (;;) {
@@ -137,7 +140,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_persistent(BatchArgs a) {
         break;
       }
       case TK_MATERN:
-        dev_matern_tile<0>(lay, a.mp[u.om], a.tables + (int64_t)u.om * NP * NC, d.locs, tk.I, tk.J,
+        dev_matern_tile<0>(lay, a.mp[u.om], a.tables + (int64_t)u.om * TABLE, d.locs, tk.I, tk.J,
                            base + lay.tile_off(tk.I, tk.J), lay.tile_ld(tk.I), nullptr, smem);
         break;
       case TK_GEMM:
@@ -255,25 +258,6 @@ bool omega_ok_b(const double* om) {
          om[3] > 0.0;
 }
 
-MaternParams make_params_b(const double* om) {
-  MaternParams P{};
-  const double phix = om[0], kappa = om[1], nug = om[2], ratio = om[3], ang = om[4];
-  P.inv_phix = 1.0 / phix;
-  P.inv_phiy = ratio / phix;
-  P.cosA = cos(ang);
-  P.sinA = sin(ang);
-  P.sqrt8k = sqrt(8.0 * kappa);
-  P.nugget = nug;
-  P.kappa = kappa;
-  P.log_norm = (1.0 - kappa) * M_LN2 - lgamma(kappa);
-  const double C = P.log_norm + 0.5 * log(M_PI / 2.0) + 760.0;
-  double x = std::max(C, 10.0);
-  for (int i = 0; i < 60; ++i) x = std::max(10.0, C + (kappa - 0.5) * log(x));
-  P.x_hi = 1.1 * x + 50.0;
-  P.u_a = log(X_LO);
-  P.inv_w = NP / (log(P.x_hi) - P.u_a);
-  return P;
-}
 
 // Tasks of one unit, phase by phase.
 void unit_phases(int Nv, std::vector<std::vector<BTask>>& ph) {
@@ -357,7 +341,7 @@ int pl_batch_create(const pl_dataset* datasets, int64_t D, int64_t p, const doub
     const int Nv = (int)((s.n + T - 1) / T);
     maxNv = std::max(maxNv, Nv);
     for (int64_t k = 0; k < s.K; ++k) {
-      b->params.push_back(make_params_b(s.omega + 5 * k));
+      b->params.push_back(make_matern_params(s.omega + 5 * k));
       b->units.push_back({(int32_t)d, (int32_t)(om + k), Nv, 0, -1, 0});
     }
     om += s.K;
@@ -438,8 +422,8 @@ int pl_batch_create(const pl_dataset* datasets, int64_t D, int64_t p, const doub
   b->off_units = take(U * sizeof(BUnit));
   b->off_ds = take(D * sizeof(BDataset));
   b->off_mp = take(om * sizeof(MaternParams));
-  b->off_nodes = take((size_t)om * NP * NC * sizeof(double));
-  b->off_tables = take((size_t)om * NP * NC * sizeof(double));
+  b->off_nodes = take((size_t)om * TABLE * sizeof(double));
+  b->off_tables = take((size_t)om * TABLE * sizeof(double));
   b->off_lam = take(M * sizeof(double));
   b->off_rhs = take((size_t)rhs_off * sizeof(double));
   b->off_jac = take(D * sizeof(double));

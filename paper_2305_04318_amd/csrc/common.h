@@ -10,26 +10,30 @@ namespace plk {
 
 // Tile edge of the blocked factorisation and of the covariance builder.
 constexpr int T = 128;
-// Chebyshev table for h(u) = log rho(e^u) + e^u, u = log x: NP pieces of NC
-// coefficients each, over [log X_LO, log x_hi(omega)].
-constexpr int NP = 48;
-constexpr int NC = 16;
-constexpr double X_LO = 1.0e-3;     // below: direct quadrature per element
-constexpr double X_ZERO = 1.0e-200; // below: rho = 1 to double precision
+// Chebyshev tables of g(w) = log rho(sqrt w), w = x^2 = 8 kappa d^2, per
+// omega: pieces uniform in the mantissa of w, PB per binade [2^e, 2^(e+1)),
+// for the NBIN binades from 2^W_E_LO up, NC coefficients per piece.
+constexpr int W_E_LO = -20;        // w < 2^-20 (x < ~1e-3): direct quadrature
+constexpr int NBIN = 44;           // binades tabulated: w < 2^24 (x < 4096)
+constexpr int PB = 2;              // pieces per binade
+constexpr int NC = 14;             // coefficients per piece
+constexpr int NPIECE = NBIN * PB;
+constexpr int TABLE = NPIECE * NC; // doubles per omega
 
 // Per-omega constants, computed on the host once per call.
 struct MaternParams {
   double inv_phix, inv_phiy;   // 1/phi_X, 1/phi_Y
   double cosA, sinA;           // rotation by phi_A
-  double sqrt8k;               // sqrt(8 kappa)
+  double k8;                   // 8 kappa (w = 8 kappa d^2)
   double nugget;               // nu^2
   double kappa;
   double log_norm;             // log(2^(1-kappa) / Gamma(kappa))
-  double u_a;                  // log X_LO
-  double inv_w;                // NP / (log x_hi - log X_LO)
-  double x_hi;                 // rho(x) underflows beyond
-  double pad;
+  double w_hi;                 // rho underflows for w >= w_hi
+  double pad[3];
 };
+
+// Host: the constants of omega = (phi_X, kappa, nu^2, phi_R, phi_A).
+MaternParams make_matern_params(const double* om);
 
 // Addressing of the per-omega matrices.
 //  kind 0: packed lower tiles, each T x T column-major, tile (I,J) of the V

@@ -2,16 +2,19 @@
 // covariance build V = R + nu^2 I (equation (1); Step 1 of Section 3.3).
 //
 // rho depends on a pair of locations only through the scaled distance
-// x = sqrt(8 kappa) d, so per omega the library tabulates the smooth function
-// h(u) = log rho(e^u) + e^u, u = log x, as NP Chebyshev pieces of NC terms on
-// [log X_LO, log x_hi].  h is analytic in the strip |Im u| < pi/2 (K_kappa has
-// no zeros with |arg z| <= pi/2), so pieces of width ~0.29 in u converge far
-// below double precision at 16 terms.  The nodes come from a trapezoid-rule
-// evaluation of K_kappa(x) = int_0^inf exp(-x cosh t) cosh(kappa t) dt
-// (DLMF 10.32.9), which converges geometrically for this analytic, doubly
-// exponentially decaying integrand.  Each matrix element then costs one
-// sqrt, one log, one exp and a 16-term Clenshaw sum; x < X_LO (points far
-// closer than the range) falls back to the quadrature itself.
+// x = sqrt(8 kappa) d, so per omega the library tabulates g(w) = log rho(sqrt w)
+// in w = x^2 = 8 kappa d^2: Chebyshev pieces of NC terms, PB pieces uniform in
+// the mantissa of each binade [2^e, 2^(e+1)) of w.  The only singularity of g
+// on or near the positive axis is at w = 0 (K_kappa has no zeros with
+// |arg z| <= pi/2), which lies at least 2 PB + 1 half-widths from every
+// piece, so the pieces converge geometrically (NC = 14, PB = 2 match the
+// quadrature to its own accuracy).  A matrix element then costs its binary
+// exponent and mantissa, a Clenshaw sum and one exp -- no square root or
+// logarithm.  The node values come from a trapezoid-rule evaluation of
+// K_kappa(x) = int_0^inf exp(-x cosh t) cosh(kappa t) dt (DLMF 10.32.9),
+// which converges geometrically for this analytic, doubly exponentially
+// decaying integrand; w < 2^W_E_LO (points far closer than the range) uses
+// the quadrature itself.
 #include <math.h>
 
 #include "matern_dev.h"
@@ -22,20 +25,21 @@ namespace plk {
 
 __global__ void k_cheb_nodes(const MaternParams* __restrict__ mp, double* __restrict__ nodes, int K) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)K * NP * NC) return;
+  if (idx >= (int64_t)K * TABLE) return;
   const int j = (int)(idx % NC);
-  const int piece = (int)((idx / NC) % NP);
-  const int k = (int)(idx / (NP * NC));
+  const int piece = (int)((idx / NC) % NPIECE);
+  const int k = (int)(idx / TABLE);
   const MaternParams P = mp[k];
-  const double w = 1.0 / P.inv_w;
+  const int bin = piece / PB, sub = piece % PB;
   const double sj = cos(M_PI * (j + 0.5) / NC);
-  const double u = P.u_a + (piece + 0.5 + 0.5 * sj) * w;
-  nodes[idx] = h_direct(P, u);
+  // node j of piece `sub` of binade W_E_LO + bin, in the mantissa of w
+  const double w = ldexp(1.0 + (sub + 0.5 + 0.5 * sj) / PB, W_E_LO + bin);
+  nodes[idx] = g_direct(P, w);
 }
 
 __global__ void k_cheb_coeffs(const double* __restrict__ nodes, double* __restrict__ tables, int K) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)K * NP * NC) return;
+  if (idx >= (int64_t)K * TABLE) return;
   const int mm = (int)(idx % NC);
   const int64_t base = idx - mm;
   double acc = 0.0;
@@ -47,7 +51,7 @@ __global__ void k_cheb_coeffs(const double* __restrict__ nodes, double* __restri
 
 hipError_t launch_cheb_tables(const MaternParams* mp, double* nodes, double* tables, int K,
                               hipStream_t s) {
-  const int64_t total = (int64_t)K * NP * NC;
+  const int64_t total = (int64_t)K * TABLE;
   const int blocks = (int)((total + 255) / 256);
   hipLaunchKernelGGL(k_cheb_nodes, dim3(blocks), dim3(256), 0, s, mp, nodes, K);
   hipLaunchKernelGGL(k_cheb_coeffs, dim3(blocks), dim3(256), 0, s, nodes, tables, K);
@@ -62,7 +66,7 @@ __global__ __launch_bounds__(256) void k_matern(Lay lay, double* __restrict__ ma
                                                 const MaternParams* __restrict__ mp,
                                                 const double* __restrict__ tables, int ntiles,
                                                 int G) {
-  __shared__ double smem[NP * NC + 2 * T];
+  __shared__ double smem[TABLE + 2 * T];
   const int wg = xcd_remap(blockIdx.x, G);
   const int k = wg / ntiles;
   const int t = wg % ntiles;
@@ -73,7 +77,7 @@ __global__ __launch_bounds__(256) void k_matern(Lay lay, double* __restrict__ ma
   const int64_t off = lay.tile_off(I, J);
   double* C = mats + (int64_t)k * stride64 + off;
   float* C32 = (MODE == 2) ? m32 + (int64_t)k * stride32 + off : nullptr;
-  dev_matern_tile<MODE>(lay, mp[k], tables + (int64_t)k * NP * NC, locs, I, J, C, lay.tile_ld(I),
+  dev_matern_tile<MODE>(lay, mp[k], tables + (int64_t)k * TABLE, locs, I, J, C, lay.tile_ld(I),
                         C32, smem);
 }
 

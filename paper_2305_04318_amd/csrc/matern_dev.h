@@ -34,26 +34,32 @@ static __device__ double log_scaled_kv_quad(double nu, double x) {
   return m + log(s * h);
 }
 
-// h(u) = log rho(x) + x at x = e^u, from the quadrature.
-static __device__ double h_direct(const MaternParams& P, double u) {
-  const double x = exp(u);
-  return P.log_norm + P.kappa * u + log_scaled_kv_quad(P.kappa, x);
+// g(w) = log rho(x) at x = sqrt(w) > 0, from the quadrature:
+// log rho = log_norm + kappa log x + log K_kappa(x), K from e^x K by - x.
+static __device__ double g_direct(const MaternParams& P, double w) {
+  const double x = sqrt(w);
+  return P.log_norm + P.kappa * log(x) + (log_scaled_kv_quad(P.kappa, x) - x);
 }
 
-// rho(x) for one element given the omega's table (NP*NC doubles).
+// rho for one element given d^2 (the squared anisotropic distance) and the
+// omega's table (TABLE doubles).  The piece comes from the binary exponent and
+// mantissa of w = 8 kappa d^2 (no logarithm), the value from a Clenshaw sum
+// and one exp.
 __device__ __forceinline__ double rho_eval(const MaternParams& P, const double* tab, double d2) {
-  const double x = P.sqrt8k * sqrt(d2);
-  if (x <= X_ZERO) return 1.0;
-  if (x >= P.x_hi) return 0.0;
-  if (x < X_LO) {
-    const double lr = P.log_norm + P.kappa * log(x) + log_scaled_kv_quad(P.kappa, x) - x;
-    return fmin(exp(lr), 1.0);
-  }
-  const double t = (log(x) - P.u_a) * P.inv_w;
-  // t lies in [0, NP) for finite x in [X_LO, x_hi); the clamp keeps the
+  const double w = P.k8 * d2;
+  if (w == 0.0) return 1.0;
+  if (w >= P.w_hi) return 0.0;
+  if (w < 0x1p-20) return fmin(exp(g_direct(P, w)), 1.0);  // 2^W_E_LO
+  int e;
+  const double m = frexp(w, &e);            // w = m 2^e, m in [0.5, 1)
+  const double t = (2.0 * m - 1.0) * PB;    // position in the binade, [0, PB)
+  int j = (int)t;
+  j = j < 0 ? 0 : (j >= PB ? PB - 1 : j);
+  int piece = (e - 1 - W_E_LO) * PB + j;
+  // in range for every finite w in [2^W_E_LO, w_hi); the clamp keeps the
   // table read in bounds for any input (a NaN coordinate included)
-  int piece = (t >= 0.0 && t < (double)NP) ? (int)t : (t >= (double)NP ? NP - 1 : 0);
-  const double s = 2.0 * (t - (double)piece) - 1.0;
+  piece = piece < 0 ? 0 : (piece >= NPIECE ? NPIECE - 1 : piece);
+  const double s = 2.0 * (t - (double)j) - 1.0;
   const double s2 = s + s;
   const double* c = tab + piece * NC;
   double b1 = 0.0, b2 = 0.0;
@@ -63,8 +69,8 @@ __device__ __forceinline__ double rho_eval(const MaternParams& P, const double* 
     b2 = b1;
     b1 = tmp;
   }
-  const double hv = fma(s, b1, c[0] - b2);
-  return fmin(exp(hv - x), 1.0);
+  const double g = fma(s, b1, c[0] - b2);
+  return fmin(exp(g), 1.0);
 }
 
 // ---- covariance tiles -----------------------------------------------------
@@ -104,7 +110,7 @@ __device__ __forceinline__ void matern_tile(const MaternParams& P, const double*
 }
 
 // One T x T tile (I, J) of V for one omega: the omega's table and the tile's
-// column coordinates are staged in smem (NP*NC + 2T doubles).  C points at the
+// column coordinates are staged in smem (TABLE + 2T doubles).  C points at the
 // tile (leading dimension ldc); MODE 2 also writes C32.
 template <int MODE>
 __device__ __forceinline__ void dev_matern_tile(const Lay& lay, const MaternParams& P,
@@ -112,9 +118,9 @@ __device__ __forceinline__ void dev_matern_tile(const Lay& lay, const MaternPara
                                                 const double* __restrict__ locs, int I, int J,
                                                 double* C, int64_t ldc, float* C32, double* smem) {
   double* tab = smem;
-  double* cx = smem + NP * NC;
+  double* cx = smem + TABLE;
   double* cy = cx + T;
-  for (int i = threadIdx.x; i < NP * NC; i += blockDim.x) tab[i] = tab_g[i];
+  for (int i = threadIdx.x; i < TABLE; i += blockDim.x) tab[i] = tab_g[i];
   for (int i = threadIdx.x; i < T; i += blockDim.x) {
     const int gj = J * T + i;
     cx[i] = gj < lay.n ? locs[2 * gj] : 0.0;
