@@ -222,6 +222,38 @@ int pl_profile_curves(const pl_result* rec, const double* beta_hat, const double
                       int64_t* arg_beta, void* work, size_t work_bytes, void* stream);
 
 /*
+ * Univariate profile likelihood of one correlation parameter or of lambda
+ * from the records of one pl_profile_loglik call, and its likelihood interval
+ * (Step 4 of the method; Section 3.3, "Profile likelihood for correlation
+ * parameters"; the likelihood-based interval of Section 2).  Host arrays,
+ * host computation (a few thousand points).
+ *   which 0..4: column of omega (range, shape, nugget, ratio, angle).  The
+ *           point cloud is (omega_k[which], max over m of l_p(omega_k,
+ *           lambda_m)); its upper convex hull, linear between vertices, is
+ *           the profile curve.
+ *   which 5: lambda.  The curve is the interpolation of (lambda_m, max over
+ *           k of l_p).
+ *   Only usable records (info 0 or PL_INFO_FALLBACK) count; equal abscissae
+ *   keep their largest likelihood.
+ *   rec     host, K*M records; omega host K x 5; lambda host M
+ *   drop    the interval is {theta : curve(theta) >= max - drop}; drop =
+ *           c_{1,alpha}/2 with Pr(chi^2_1 <= c_{1,alpha}) = 1 - alpha (1.92
+ *           for 95%), the reading of the paper's interval display
+ *   curve_x, curve_y  host, room for max(K, M) values: the curve's vertices by
+ *           increasing abscissa; *npts receives their count
+ *   interval host, 3 doubles: the maximising abscissa, the lower and upper
+ *           ends (linear interpolation at the crossing)
+ *   open_ends host or NULL: bit 0 (1) when the curve never falls below the
+ *           threshold on the left (the lower end is then the first vertex),
+ *           bit 1 (2) likewise on the right
+ * Errors: -1 rec NULL, -2 K, -3 M out of range, -4 omega NULL, -5 lambda NULL,
+ * -6 which out of range, -7 drop not > 0, -8..-11 output NULL.
+ */
+int pl_profile_param(const pl_result* rec, int64_t K, int64_t M, const double* omega,
+                     const double* lambda, int which, double drop, double* curve_x,
+                     double* curve_y, int64_t* npts, double* interval, int32_t* open_ends);
+
+/*
  * Autotuner for the form of pl_profile_loglik on one workload.  Candidates:
  * PL_FP64, and PL_MIXED with flush 4, 2 and 1 (the k-depth, 16/8/4 products,
  * of the FP32 partial-sum tiles of the mixed update).  Each is run on the

@@ -14,7 +14,7 @@ PL_MAX_P, PL_MAX_M = 32, 64
 EXPORTS = ("pl_version", "pl_error_string", "pl_workspace_size", "pl_matern_workspace_size",
            "pl_matern_cov", "pl_chol_workspace_size", "pl_chol_batched", "pl_profile_loglik",
            "pl_profiling_enable", "pl_profiling_read", "pl_curves_workspace_size",
-           "pl_profile_curves", "pl_autotune_workspace_size",
+           "pl_profile_curves", "pl_profile_param", "pl_autotune_workspace_size",
            "pl_autotune", "pl_batch_create",
            "pl_batch_workspace_size", "pl_batch_stats", "pl_batch_run", "pl_batch_error",
            "pl_batch_destroy")
@@ -92,6 +92,9 @@ def load(path: str = None):
     lib.pl_profiling_read.restype = ctypes.c_int
     lib.pl_profiling_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+    lib.pl_profile_param.restype = ctypes.c_int
+    lib.pl_profile_param.argtypes = [_P, _I64, _I64, _P, _P, ctypes.c_int, ctypes.c_double, _P, _P,
+                                     ctypes.POINTER(_I64), _P, ctypes.POINTER(ctypes.c_int32)]
     lib.pl_autotune_workspace_size.restype = ctypes.c_int
     lib.pl_autotune_workspace_size.argtypes = [_I64, _I64, _I64, _I64, _I64, ctypes.POINTER(_SZ)]
     lib.pl_autotune.restype = ctypes.c_int

@@ -204,6 +204,43 @@ def profile_curves(res, lam, n, sigma_grid=None, beta_grid=None, stream=None):
             "beta_arg": arg_b[:, :Gb]}
 
 
+PARAMS = ("range", "shape", "nugget", "ratio", "angle", "lambda")
+
+
+def profile_param(res, omega, lam, which, drop=1.92):
+    """pl_profile_param on the records of one profile_loglik call: the
+    profile curve of parameter `which` (an index or a name from PARAMS) and
+    its likelihood interval at level drop (1.92: 95%).  Returns a dict with
+    "x", "y" (curve vertices), "argmax", "lower", "upper" and "open"
+    (open_ends bits)."""
+    lib = load()
+    if isinstance(which, str):
+        which = PARAMS.index(which)
+    rec = res["records"] if isinstance(res, dict) else res
+    K, M = rec.shape[0], rec.shape[1]
+    host = np.ascontiguousarray(rec.detach().to("cpu").numpy())
+    om = _host_f64(omega, 5)
+    lm = _host_f64(lam).reshape(-1)
+    if om.shape[0] != K or lm.shape[0] != M:
+        raise ValueError("omega and lam must be those of the call")
+    cap = max(K, M)
+    cx = np.empty(cap)
+    cy = np.empty(cap)
+    npts = ctypes.c_int64(0)
+    iv = np.empty(3)
+    op = ctypes.c_int32(0)
+    rc = lib.pl_profile_param(host.ctypes.data_as(ctypes.c_void_p), K, M,
+                              om.ctypes.data_as(ctypes.c_void_p),
+                              lm.ctypes.data_as(ctypes.c_void_p), int(which), float(drop),
+                              cx.ctypes.data_as(ctypes.c_void_p),
+                              cy.ctypes.data_as(ctypes.c_void_p), ctypes.byref(npts),
+                              iv.ctypes.data_as(ctypes.c_void_p), ctypes.byref(op))
+    check(rc, "pl_profile_param")
+    k = npts.value
+    return {"x": cx[:k].copy(), "y": cy[:k].copy(), "argmax": iv[0], "lower": iv[1],
+            "upper": iv[2], "open": op.value}
+
+
 AUTOTUNE_CANDIDATES = (("fp64", 0), ("mixed", 4), ("mixed", 2), ("mixed", 1))
 
 

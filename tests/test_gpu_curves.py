@@ -89,3 +89,23 @@ def test_mixed_form_curves_within_mixed_tolerance(plprof_lib):
     pr = synth.small_problem(900, p=3, K=4, M=3, seed=56)
     res, sgrid, bgrid, locs, om = _setup(pl, pr, precision="mixed")
     _check(pl, pr, res, sgrid, bgrid, locs, om, tol_abs=1e-2)
+
+
+def test_step4_profiles_match_oracle(plprof_lib):
+    """Univariate profiles of every correlation parameter and of lambda from
+    GPU records equal those the oracle extracts from its own records."""
+    from oracle.extract import profile as oracle_profile
+    pl = plprof_lib
+    pr = synth.small_problem(240, p=2, K=40, M=5, seed=61)
+    res = pl.profile_loglik(pr.locs, pr.y, pr.X, pr.omega, pr.lam)
+    torch.cuda.synchronize()
+    ref = oracle.profile_loglik(pr.locs, pr.y, pr.X, pr.omega, pr.lam)
+    for which in range(6):
+        got = pl.profile_param(res, pr.omega, pr.lam, which)
+        ox, oy, am, lo, hi, op = oracle_profile(ref["loglik"], ref["info"] == 0, pr.omega, pr.lam,
+                                                which)
+        np.testing.assert_array_equal(got["x"], ox)
+        np.testing.assert_allclose(got["y"], oy, rtol=1e-9)
+        assert got["argmax"] == am and got["open"] == op
+        scale = max(1.0, abs(ox).max())
+        np.testing.assert_allclose([got["lower"], got["upper"]], [lo, hi], rtol=0, atol=1e-6 * scale)
