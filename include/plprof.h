@@ -254,6 +254,78 @@ int pl_profile_param(const pl_result* rec, int64_t K, int64_t M, const double* o
                      double* curve_y, int64_t* npts, double* interval, int32_t* open_ends);
 
 /*
+ * Internal parameters of Step 2 (Section 3.3, "Reparameterization"):
+ *   omega' = (gamma1, kappa~, nu, gamma2, gamma3),
+ *   gamma1 = log phi_X + log phi_Y (exp(gamma1/2) is the combined range),
+ *   gamma2 = sqrt(phi_X/phi_Y - 1) cos(2 phi_A),
+ *   gamma3 = sqrt(phi_X/phi_Y - 1) sin(2 phi_A),
+ *   kappa~ = log kappa (shape_transform 0, for kappa-hat < 4) or
+ *            1/sqrt(kappa) (shape_transform 1, kappa-hat >= 4),
+ *   nu = sqrt(nu^2).
+ * A natural omega with phi_R = phi_X/phi_Y < 1 is first rewritten as the same
+ * model with the axes exchanged (phi_X/phi_R, 1/phi_R, phi_A + pi/2), so
+ * gamma2, gamma3 are real; the inverse returns phi_R >= 1 and phi_A in
+ * (-pi/2, pi/2].  The inverse maps a negative nu to the negative nugget
+ * -nu^2 (points drawn from a quadratic approximation can fall there; Step 2's
+ * nugget repair then applies).  Host arrays, K x 5 row-major, host code.
+ * Errors: -1 omega / internal NULL or a value out of domain (omega: range,
+ * ratio <= 0, shape <= 0, nugget < 0, not finite; internal: not finite, or
+ * kappa~ <= 0 with shape_transform 1), -2 K < 1, -3 shape_transform not 0
+ * or 1, -4 output NULL.
+ */
+int pl_to_internal(const double* omega, int64_t K, int shape_transform, double* internal);
+int pl_from_internal(const double* internal, int64_t K, int shape_transform, double* omega);
+
+/*
+ * Maximum-likelihood estimates of (omega, lambda) (Step 1 of the method,
+ * Section 3.3: numerical maximisation of equation "profile", or with reml = 1
+ * of the restricted profile log-likelihood of Appendix "remlpro").
+ *
+ * Batched compass search in the coordinates (gamma1, log kappa, log nu^2,
+ * gamma2, gamma3) -- the internal parameters above with log nu^2 for the
+ * nugget.  Every iteration evaluates the +-h neighbours along each free
+ * coordinate of every start in one pl_profile_loglik call (10 points per
+ * start), moves each start to its best improving neighbour (doubling that
+ * step, capped at 2) or halves its steps; a start stops when its largest step
+ * is below tol.  Steps start at 0.5.  lambda is maximised over the M values
+ * of every call; after the search, the best start is re-evaluated on a fine
+ * lambda set (its value plus min(64, 32 - p for PL_MIXED) - 1 evenly spaced
+ * values between the neighbouring caller values) and polished by a second
+ * search (initial step min(0.5, 16 tol)) on that set.
+ *   omega0     host, starts x 5 natural starting points (shape in
+ *              [PL_MIN_SHAPE, PL_MAX_SHAPE], nugget > 0)
+ *   lambda     host, M Box-Cox values
+ *   fixed_mask bit i holds search coordinate i at its start value (bit 1:
+ *              kappa, the paper's fits with kappa fixed at 0.5 and 10;
+ *              bits 3|4: the anisotropy, isotropic when the starts are)
+ *   tol        step at which a start stops, in search coordinates (0 < tol < 0.5)
+ *   max_iter   iterations per search (each one call of pl_profile_loglik)
+ *   omega_hat  host, 5 doubles; lambda_hat, loglik_hat host, 1 double each;
+ *   iterations host or NULL: total iterations of both searches
+ *   opts       as pl_profile_loglik (NULL for FP64 defaults)
+ *   work       device, pl_mle_workspace_size bytes (same starts, M, opts)
+ * The shape is kept in [PL_MIN_SHAPE, PL_MAX_SHAPE] (candidates beyond are
+ * evaluated at the bound).  The call synchronises `stream` once per
+ * iteration (it reads the records back).
+ * Errors: -1..-5 as pl_profile_loglik; -6 omega0 NULL or out of domain;
+ * -7 starts < 1 or > PL_MLE_MAX_STARTS; -8 lambda NULL or not finite;
+ * -9 M out of range; -10 fixed_mask outside [0, 31]; -11 reml not 0 or 1;
+ * -12 tol out of range; -13 max_iter < 1; -14..-16 output NULL; -18 bad
+ * option; -19/-20 workspace NULL or too small; PL_E_UNSUPPORTED for PL_MIXED
+ * with M + p > 32 or when no start has a usable record.
+ * pl_mle_workspace_size: -1/-2 as pl_workspace_size, -3 starts out of range,
+ * -4 M out of range, -5 bad option, -6 bytes NULL.
+ */
+#define PL_MLE_MAX_STARTS 256
+int pl_mle_workspace_size(int64_t n, int64_t p, int64_t starts, int64_t M,
+                          const pl_opts* opts, size_t* bytes);
+int pl_mle(const double* locs, const double* y, const double* X, int64_t n, int64_t p,
+           const double* omega0, int64_t starts, const double* lambda, int64_t M,
+           int32_t fixed_mask, int32_t reml, double tol, int32_t max_iter, double* omega_hat,
+           double* lambda_hat, double* loglik_hat, int32_t* iterations, const pl_opts* opts,
+           void* work, size_t work_bytes, void* stream);
+
+/*
  * Autotuner for the form of pl_profile_loglik on one workload.  Candidates:
  * PL_FP64, and PL_MIXED with flush 4, 2 and 1 (the k-depth, 16/8/4 products,
  * of the FP32 partial-sum tiles of the mixed update).  Each is run on the

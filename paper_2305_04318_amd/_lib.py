@@ -15,7 +15,8 @@ EXPORTS = ("pl_version", "pl_error_string", "pl_workspace_size", "pl_matern_work
            "pl_matern_cov", "pl_chol_workspace_size", "pl_chol_batched", "pl_profile_loglik",
            "pl_profiling_enable", "pl_profiling_read", "pl_curves_workspace_size",
            "pl_profile_curves", "pl_profile_param", "pl_autotune_workspace_size",
-           "pl_autotune", "pl_batch_create",
+           "pl_autotune", "pl_to_internal", "pl_from_internal", "pl_mle_workspace_size",
+           "pl_mle", "pl_batch_create",
            "pl_batch_workspace_size", "pl_batch_stats", "pl_batch_run", "pl_batch_error",
            "pl_batch_destroy")
 KERNEL_CLASSES = ("tables", "matern", "gemm", "potrf", "trsm", "other")
@@ -101,6 +102,17 @@ def load(path: str = None):
     lib.pl_autotune.argtypes = [_P, _P, _P, _I64, _I64, _P, _I64, _P, _I64, _I64, ctypes.c_double,
                                 ctypes.POINTER(PlOpts), ctypes.POINTER(ctypes.c_double), _P, _SZ,
                                 _P]
+    lib.pl_to_internal.restype = ctypes.c_int
+    lib.pl_to_internal.argtypes = [_P, _I64, ctypes.c_int, _P]
+    lib.pl_from_internal.restype = ctypes.c_int
+    lib.pl_from_internal.argtypes = [_P, _I64, ctypes.c_int, _P]
+    lib.pl_mle_workspace_size.restype = ctypes.c_int
+    lib.pl_mle_workspace_size.argtypes = [_I64, _I64, _I64, _I64, ctypes.POINTER(PlOpts),
+                                          ctypes.POINTER(_SZ)]
+    lib.pl_mle.restype = ctypes.c_int
+    lib.pl_mle.argtypes = [_P, _P, _P, _I64, _I64, _P, _I64, _P, _I64, ctypes.c_int32,
+                           ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _P, _P, _P,
+                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(PlOpts), _P, _SZ, _P]
     lib.pl_batch_create.restype = ctypes.c_int
     lib.pl_batch_create.argtypes = [ctypes.POINTER(PlDataset), _I64, _I64, _P, _I64,
                                     ctypes.POINTER(PlOpts), ctypes.POINTER(ctypes.c_void_p)]

@@ -273,6 +273,75 @@ def autotune(locs, y, X, omega, lam, tol=1e-3, sample=0, device="cuda", stream=N
     return choice, report
 
 
+PARAM_NAMES_INTERNAL = ("gamma1", "shape~", "nu", "gamma2", "gamma3")
+
+
+def to_internal(omega, shape_transform=0):
+    """pl_to_internal: natural omega (K x 5) -> internal (gamma1, kappa~, nu,
+    gamma2, gamma3); shape_transform 0: log kappa, 1: 1/sqrt(kappa)."""
+    om = _host_f64(omega, 5)
+    out = np.empty_like(om)
+    check(load().pl_to_internal(om.ctypes.data_as(ctypes.c_void_p), om.shape[0],
+                                int(shape_transform), out.ctypes.data_as(ctypes.c_void_p)),
+          "pl_to_internal")
+    return out
+
+
+def from_internal(internal, shape_transform=0):
+    """pl_from_internal: the inverse of to_internal (a negative nu gives a
+    negative nugget -nu^2)."""
+    w = _host_f64(internal, 5)
+    out = np.empty_like(w)
+    check(load().pl_from_internal(w.ctypes.data_as(ctypes.c_void_p), w.shape[0],
+                                  int(shape_transform), out.ctypes.data_as(ctypes.c_void_p)),
+          "pl_from_internal")
+    return out
+
+
+def default_starts(locs, fractions=(0.05, 0.2, 0.5), shapes=(0.5, 2.0), nuggets=(0.1, 0.5)):
+    """Isotropic starting points for mle: ranges at `fractions` of the
+    diagonal of the locations' bounding box, every combination with `shapes`
+    and `nuggets` (ratio 1, angle 0)."""
+    xy = np.asarray(locs.cpu() if isinstance(locs, torch.Tensor) else locs, dtype=np.float64)
+    diag = float(np.hypot(*(xy.max(axis=0) - xy.min(axis=0))))
+    return np.array([[f * diag, k, nu, 1.0, 0.0] for f in fractions for k in shapes
+                     for nu in nuggets])
+
+
+def mle(locs, y, X, lam, omega0=None, fixed=(), reml=False, tol=1e-4, max_iter=200,
+        precision="fp64", flush=0, device="cuda", stream=None, inputs=None):
+    """pl_mle: maximum-likelihood (reml: restricted) estimates of omega and
+    lambda from the starts omega0 (default: default_starts(locs)), searching
+    lambda over the values `lam` and then a fine set around the best one.
+    `fixed` names search coordinates held at their start values: any of
+    "range" (gamma1), "shape", "nugget", "aniso" (gamma2 and gamma3).
+    Returns {"omega", "lambda", "loglik", "iterations"}."""
+    lib = load()
+    inp = inputs if inputs is not None else Inputs(locs, y, X, device)
+    om = _host_f64(default_starts(locs) if omega0 is None else omega0, 5)
+    lm = _host_f64(lam).reshape(-1)
+    bits = {"range": 1, "shape": 2, "nugget": 4, "aniso": 8 | 16}
+    mask = 0
+    for name in fixed:
+        mask |= bits[name]
+    o = _opts(precision, flush=flush)
+    sz = ctypes.c_size_t(0)
+    check(lib.pl_mle_workspace_size(inp.n, inp.p, om.shape[0], lm.shape[0], ctypes.byref(o),
+                                    ctypes.byref(sz)), "pl_mle_workspace_size")
+    work = torch.empty(sz.value, dtype=torch.uint8, device=inp.device)
+    oh = np.empty(5)
+    lh, llh = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    its = ctypes.c_int32(0)
+    rc = lib.pl_mle(_ptr(inp.locs), _ptr(inp.y), _ptr(inp.Xc), inp.n, inp.p,
+                    om.ctypes.data_as(ctypes.c_void_p), om.shape[0],
+                    lm.ctypes.data_as(ctypes.c_void_p), lm.shape[0], mask, 1 if reml else 0,
+                    float(tol), int(max_iter), oh.ctypes.data_as(ctypes.c_void_p),
+                    ctypes.byref(lh), ctypes.byref(llh), ctypes.byref(its), ctypes.byref(o),
+                    _ptr(work), work.numel(), _stream_ptr(stream))
+    check(rc, "pl_mle")
+    return {"omega": oh, "lambda": lh.value, "loglik": llh.value, "iterations": its.value}
+
+
 def profiling_enable(on: bool = True):
     """Start (clearing counters) or stop HIP-event timing of the library's kernels."""
     check(load().pl_profiling_enable(1 if on else 0), "pl_profiling_enable")
