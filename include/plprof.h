@@ -326,6 +326,95 @@ int pl_mle(const double* locs, const double* y, const double* X, int64_t n, int6
            void* work, size_t work_bytes, void* stream);
 
 /*
+ * Representative parameter points (Step 2 of the method, Section 3.3,
+ * "Hessian matrix" and "Obtaining representative points").
+ *
+ * pl_hessian: the Hessian H of l_p(omega', lambda_hat) in the internal
+ * parameters omega' (see pl_to_internal; d = 5, or d = 4 without kappa~ when
+ * fix_shape = 1 -- the fits with the shape held fixed) at omega_hat, by
+ * central differences with step delta:
+ *   H_ii = [f(w + delta e_i) - 2 f(w) + f(w - delta e_i)] / delta^2,
+ *   H_ij = [f(++) - f(+-) - f(-+) + f(--)] / (4 delta^2),
+ * on 1 + 2d + 2d(d - 1) points (51 for d = 5, 33 for d = 4), each at lambda
+ * in {lambda_hat - delta, lambda_hat, lambda_hat + delta}: one
+ * pl_profile_loglik call of PL_HESS_POINTS x 3 records at most.  A point's
+ * nugget is nu^2 (so nu - delta < 0 is the nugget (nu - delta)^2).
+ *   omega_hat  host, 5 natural values (e.g. from pl_mle); lambda_hat
+ *   shape_transform  0: kappa~ = log kappa, 1: 1/sqrt(kappa) (the paper uses
+ *              1 when kappa_hat >= 4)
+ *   hess       host, d x d row-major; lambda_curv (host or NULL): the second
+ *              derivative of l_p in lambda at (omega_hat, lambda_hat) from the
+ *              same records; loglik_center (host or NULL): l_p there
+ *   work       device, pl_hessian_workspace_size bytes
+ * Synchronises `stream` once.  Errors: -1..-5 as pl_profile_loglik; -6
+ * omega_hat NULL or out of domain; -7 lambda_hat not finite; -8/-9 flags not
+ * 0 or 1; -10 delta not in (0, 1]; -11 hess NULL; -14 bad option; -15/-16
+ * workspace NULL or too small; PL_E_UNSUPPORTED when a stencil point has a
+ * shape outside [PL_MIN_SHAPE, PL_MAX_SHAPE] or no usable record.
+ * pl_hessian_workspace_size: -1/-2 as pl_workspace_size, -3 bad option, -4
+ * bytes NULL.
+ */
+#define PL_HESS_POINTS 51
+int pl_hessian_workspace_size(int64_t n, int64_t p, const pl_opts* opts, size_t* bytes);
+int pl_hessian(const double* locs, const double* y, const double* X, int64_t n, int64_t p,
+               const double* omega_hat, double lambda_hat, int shape_transform, int fix_shape,
+               double delta, double* hess, double* lambda_curv, double* loglik_center,
+               const pl_opts* opts, void* work, size_t work_bytes, void* stream);
+
+/*
+ * pl_config_points: configuration points around omega_hat from a Hessian of
+ * pl_hessian (same shape_transform and fix_shape).  -H = E D E^T
+ * (eigenvalues ascending, each eigenvector with its largest entry positive);
+ * negative eigenvalues are replaced by their absolute values and, when the
+ * largest exceeds 100, every eigenvalue below 0.1 by 0.1.  For every level l
+ * and sphere point x_t (unit vectors, npts x d):
+ *   omega' = omega_hat' + sqrt(q_l) E D^(-1/2) x_t,
+ * q_l the chi-square (d degrees of freedom) quantile of upper-tail
+ * probability alpha[l], so that (omega' - omega_hat')^T (-H) (omega' -
+ * omega_hat') = q_l with the repaired -H; then natural values (phi_R >= 1,
+ * shape clamped to [PL_MIN_SHAPE, PL_MAX_SHAPE], 1/sqrt(kappa) <= 0 read as
+ * the largest shape, the held shape when fix_shape).  A point with nu < 0 has
+ * a negative nugget: the first, third, ... such point (in output order) gets
+ * nugget 0, the second, fourth, ... 2 u with u = uniforms[its index].
+ *   alpha    host, nlev values in (0, 1); sphere host npts x d
+ *   uniforms host, nlev*npts values in [0, 1) (only those of repaired points
+ *            are read)
+ *   omega_out host, nlev*npts x 5, level-major
+ *   eigvals  host, d repaired eigenvalues ascending, or NULL
+ *   nugget_repaired host or NULL: the number of repaired nuggets
+ * Host code.  Errors: -1 omega_hat NULL or out of domain, -2/-3 flags, -4
+ * hess NULL or not finite, -5 alpha NULL or out of (0, 1), -6 nlev out of
+ * range, -7 sphere NULL, -8 npts out of range, -9 uniforms NULL, -10
+ * omega_out NULL; PL_E_UNSUPPORTED when a repaired eigenvalue is 0.
+ *
+ * pl_sphere_points: npts well-spread unit vectors in R^d, starting from the
+ * directions of `init` (npts x d, nonzero rows; e.g. normal draws): `iters`
+ * steps of a repulsion (the gradient of the Riesz 8-energy, tangential part,
+ * step 0.3 x the current closest distance, shrinking linearly), keeping the
+ * arrangement with the largest closest distance, which *min_dist (or NULL)
+ * receives.  The paper maximises the closest distance with an unspecified
+ * stochastic optimiser.  Host code.  Errors: -1 d not in [2, 16], -2 npts
+ * not in [2, 100000], -3 init NULL or a zero row, -4 iters < 0, -5 out NULL.
+ *
+ * pl_lambda_grid: m values evenly spaced between the tail and 1 - tail
+ * quantiles of the normal approximation N(lambda_hat, 1/|lambda_curv|) of
+ * the likelihood in lambda (the paper: 30 values, tail 0.01).  Host code.
+ * Errors: -1 lambda_hat, -2 lambda_curv (0 or not finite), -3 tail not in
+ * (0, 0.5), -4 m not in [2, PL_MAX_M], -5 out NULL.
+ *
+ * pl_chisq_quantile: *q with Pr(chi^2_dof > q) = upper.  Host code.
+ * Errors: -1 dof not in [1, 1000], -2 upper not in (0, 1), -3 q NULL.
+ */
+int pl_config_points(const double* omega_hat, int shape_transform, int fix_shape,
+                     const double* hess, const double* alpha, int64_t nlev, const double* sphere,
+                     int64_t npts, const double* uniforms, double* omega_out, double* eigvals,
+                     int64_t* nugget_repaired);
+int pl_sphere_points(int d, int64_t npts, const double* init, int iters, double* out,
+                     double* min_dist);
+int pl_lambda_grid(double lambda_hat, double lambda_curv, double tail, int64_t m, double* out);
+int pl_chisq_quantile(int dof, double upper, double* q);
+
+/*
  * Autotuner for the form of pl_profile_loglik on one workload.  Candidates:
  * PL_FP64, and PL_MIXED with flush 4, 2 and 1 (the k-depth, 16/8/4 products,
  * of the FP32 partial-sum tiles of the mixed update).  Each is run on the

@@ -16,7 +16,8 @@ EXPORTS = ("pl_version", "pl_error_string", "pl_workspace_size", "pl_matern_work
            "pl_profiling_enable", "pl_profiling_read", "pl_curves_workspace_size",
            "pl_profile_curves", "pl_profile_param", "pl_autotune_workspace_size",
            "pl_autotune", "pl_to_internal", "pl_from_internal", "pl_mle_workspace_size",
-           "pl_mle", "pl_batch_create",
+           "pl_mle", "pl_hessian_workspace_size", "pl_hessian", "pl_config_points",
+           "pl_sphere_points", "pl_lambda_grid", "pl_chisq_quantile", "pl_batch_create",
            "pl_batch_workspace_size", "pl_batch_stats", "pl_batch_run", "pl_batch_error",
            "pl_batch_destroy")
 KERNEL_CLASSES = ("tables", "matern", "gemm", "potrf", "trsm", "other")
@@ -113,6 +114,24 @@ def load(path: str = None):
     lib.pl_mle.argtypes = [_P, _P, _P, _I64, _I64, _P, _I64, _P, _I64, ctypes.c_int32,
                            ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _P, _P, _P,
                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(PlOpts), _P, _SZ, _P]
+    lib.pl_hessian_workspace_size.restype = ctypes.c_int
+    lib.pl_hessian_workspace_size.argtypes = [_I64, _I64, ctypes.POINTER(PlOpts),
+                                              ctypes.POINTER(_SZ)]
+    lib.pl_hessian.restype = ctypes.c_int
+    lib.pl_hessian.argtypes = [_P, _P, _P, _I64, _I64, _P, ctypes.c_double, ctypes.c_int,
+                               ctypes.c_int, ctypes.c_double, _P, _P, _P, ctypes.POINTER(PlOpts),
+                               _P, _SZ, _P]
+    lib.pl_config_points.restype = ctypes.c_int
+    lib.pl_config_points.argtypes = [_P, ctypes.c_int, ctypes.c_int, _P, _P, _I64, _P, _I64, _P,
+                                     _P, _P, ctypes.POINTER(_I64)]
+    lib.pl_sphere_points.restype = ctypes.c_int
+    lib.pl_sphere_points.argtypes = [ctypes.c_int, _I64, _P, ctypes.c_int, _P,
+                                     ctypes.POINTER(ctypes.c_double)]
+    lib.pl_lambda_grid.restype = ctypes.c_int
+    lib.pl_lambda_grid.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, _I64, _P]
+    lib.pl_chisq_quantile.restype = ctypes.c_int
+    lib.pl_chisq_quantile.argtypes = [ctypes.c_int, ctypes.c_double,
+                                      ctypes.POINTER(ctypes.c_double)]
     lib.pl_batch_create.restype = ctypes.c_int
     lib.pl_batch_create.argtypes = [ctypes.POINTER(PlDataset), _I64, _I64, _P, _I64,
                                     ctypes.POINTER(PlOpts), ctypes.POINTER(ctypes.c_void_p)]

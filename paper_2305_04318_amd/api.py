@@ -342,6 +342,127 @@ def mle(locs, y, X, lam, omega0=None, fixed=(), reml=False, tol=1e-4, max_iter=2
     return {"omega": oh, "lambda": lh.value, "loglik": llh.value, "iterations": its.value}
 
 
+# contour levels (upper-tail probabilities) of the paper's two data examples
+PAPER_ALPHA = (1e-5, 0.01, 0.1, 0.2, 0.25, 0.3, 0.5, 0.8, 0.9, 0.95, 0.99, 0.999)
+
+
+def chisq_quantile(dof, upper):
+    """pl_chisq_quantile: q with Pr(chi^2_dof > q) = upper."""
+    q = ctypes.c_double(0.0)
+    check(load().pl_chisq_quantile(int(dof), float(upper), ctypes.byref(q)), "pl_chisq_quantile")
+    return q.value
+
+
+def sphere_points(d, npts, seed=0, iters=300, init=None):
+    """pl_sphere_points from `init` (npts x d) or from standard normal draws
+    of a PCG64 generator seeded with `seed`.  Returns (points, closest
+    distance)."""
+    if init is None:
+        init = np.random.Generator(np.random.PCG64(seed)).standard_normal((npts, d))
+    x0 = _host_f64(init, d)
+    out = np.empty_like(x0)
+    md = ctypes.c_double(0.0)
+    check(load().pl_sphere_points(int(d), x0.shape[0], x0.ctypes.data_as(ctypes.c_void_p),
+                                  int(iters), out.ctypes.data_as(ctypes.c_void_p),
+                                  ctypes.byref(md)), "pl_sphere_points")
+    return out, md.value
+
+
+def shape_transform_for(kappa_hat):
+    """The paper's choice of shape transform: log below 4, 1/sqrt from 4 on."""
+    return 0 if kappa_hat < 4.0 else 1
+
+
+def hessian(locs, y, X, omega_hat, lambda_hat, shape_transform=None, fix_shape=False,
+            delta=0.05, precision="fp64", device="cuda", stream=None, inputs=None):
+    """pl_hessian: {"H" (d x d), "lambda_curv", "loglik", "shape_transform"}."""
+    lib = load()
+    inp = inputs if inputs is not None else Inputs(locs, y, X, device)
+    om = _host_f64(omega_hat, 5)
+    st = shape_transform_for(om[0, 1]) if shape_transform is None else int(shape_transform)
+    o = _opts(precision)
+    sz = ctypes.c_size_t(0)
+    check(lib.pl_hessian_workspace_size(inp.n, inp.p, ctypes.byref(o), ctypes.byref(sz)),
+          "pl_hessian_workspace_size")
+    work = torch.empty(sz.value, dtype=torch.uint8, device=inp.device)
+    d = 4 if fix_shape else 5
+    H = np.empty((d, d))
+    curv, ll = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    rc = lib.pl_hessian(_ptr(inp.locs), _ptr(inp.y), _ptr(inp.Xc), inp.n, inp.p,
+                        om.ctypes.data_as(ctypes.c_void_p), float(lambda_hat), st,
+                        1 if fix_shape else 0, float(delta), H.ctypes.data_as(ctypes.c_void_p),
+                        ctypes.byref(curv), ctypes.byref(ll), ctypes.byref(o), _ptr(work),
+                        work.numel(), _stream_ptr(stream))
+    check(rc, "pl_hessian")
+    return {"H": H, "lambda_curv": curv.value, "loglik": ll.value, "shape_transform": st}
+
+
+def config_points(omega_hat, H, alpha, sphere, uniforms, shape_transform=0, fix_shape=False):
+    """pl_config_points: (omega rows, level-major; repaired eigenvalues;
+    number of repaired nuggets)."""
+    om = _host_f64(omega_hat, 5)
+    Hh = _host_f64(H)
+    al = _host_f64(alpha).reshape(-1)
+    d = 4 if fix_shape else 5
+    sp = _host_f64(sphere, d)
+    un = _host_f64(uniforms).reshape(-1)
+    if un.shape[0] < al.shape[0] * sp.shape[0]:
+        raise ValueError("need one uniform per output point")
+    out = np.empty((al.shape[0] * sp.shape[0], 5))
+    eig = np.empty(d)
+    nrep = ctypes.c_int64(0)
+    P = ctypes.c_void_p
+    check(load().pl_config_points(om.ctypes.data_as(P), int(shape_transform),
+                                  1 if fix_shape else 0, Hh.ctypes.data_as(P),
+                                  al.ctypes.data_as(P), al.shape[0], sp.ctypes.data_as(P),
+                                  sp.shape[0], un.ctypes.data_as(P), out.ctypes.data_as(P),
+                                  eig.ctypes.data_as(P), ctypes.byref(nrep)), "pl_config_points")
+    return out, eig, nrep.value
+
+
+def lambda_grid(lambda_hat, lambda_curv, m=30, tail=0.01):
+    """pl_lambda_grid: m values between the tail and 1 - tail quantiles of
+    the normal approximation in lambda."""
+    out = np.empty(int(m))
+    check(load().pl_lambda_grid(float(lambda_hat), float(lambda_curv), float(tail), int(m),
+                                out.ctypes.data_as(ctypes.c_void_p)), "pl_lambda_grid")
+    return out
+
+
+def configure(locs, y, X, fits, alpha=PAPER_ALPHA, npts=None, n_lambda=30, delta=0.05,
+              seed=0, sphere_iters=300, device="cuda", stream=None, inputs=None):
+    """Step 2 end to end: for every fit (a dict from mle, with "fixed_shape"
+    True for the fits with the shape held), the Hessian, its repair and the
+    points on every level (726 unit-sphere points in 5-D, 120 in 4-D unless
+    npts is given); the Box-Cox grid from the first fit.  Returns {"omega"
+    (all points), "lambda", "fits" (per fit: H, shape transform, eigenvalues,
+    number of points, repaired nuggets)}."""
+    inp = inputs if inputs is not None else Inputs(locs, y, X, device)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    spheres = {}
+    omegas, info = [], []
+    lam_grid = None
+    for f in fits:
+        fix = bool(f.get("fixed_shape", False))
+        d = 4 if fix else 5
+        npd = npts if npts is not None else (120 if fix else 726)
+        if d not in spheres:
+            spheres[d] = sphere_points(d, npd, init=rng.standard_normal((npd, d)),
+                                       iters=sphere_iters)[0]
+        h = hessian(None, None, None, f["omega"], f["lambda"], fix_shape=fix, delta=delta,
+                    stream=stream, inputs=inp)
+        u = rng.uniform(size=len(alpha) * spheres[d].shape[0])
+        pts, eig, nrep = config_points(f["omega"], h["H"], alpha, spheres[d], u,
+                                       h["shape_transform"], fix)
+        omegas.append(pts)
+        info.append({"H": h["H"], "shape_transform": h["shape_transform"], "eigvals": eig,
+                     "points": pts.shape[0], "nugget_repaired": nrep,
+                     "lambda_curv": h["lambda_curv"]})
+        if lam_grid is None:
+            lam_grid = lambda_grid(f["lambda"], h["lambda_curv"], n_lambda)
+    return {"omega": np.concatenate(omegas), "lambda": lam_grid, "fits": info}
+
+
 def profiling_enable(on: bool = True):
     """Start (clearing counters) or stop HIP-event timing of the library's kernels."""
     check(load().pl_profiling_enable(1 if on else 0), "pl_profiling_enable")
