@@ -35,7 +35,7 @@ GEMM_SOURCES = ("common.h", "tiles.h", "chol.hip")
 
 
 def measured_traffic():
-    """HBM bytes per k_gemm_col launch from the committed FETCH_SIZE/WRITE_SIZE
+    """HBM bytes per block-column update launch from the committed FETCH_SIZE/WRITE_SIZE
     summary, or None when the kernel sources changed since it was taken."""
     import hashlib
     try:
@@ -393,7 +393,8 @@ def main():
     gemm_tflops = g["flops"] / (g["ms"] / 1e3) / 1e12 if g["ms"] > 0 else 0.0
     if prec == "fp64":
         peak = PEAK_FP64_TFLOPS
-        kernel_name = "k_gemm_col (left-looking block-column update, MFMA f64)"
+        kernel_name = ("k_col_update (left-looking block-column update, bordered row folded "
+                       "into the diagonal tile's workgroup, MFMA f64)")
         # counters were taken on this workload's launches only
         default_shape = (n, K, M) == (2000, 1024, 8)
         traffic = measured_traffic() if default_shape else None

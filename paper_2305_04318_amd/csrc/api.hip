@@ -382,17 +382,22 @@ int pl_profile_loglik(const double* locs, const double* y, const double* X, int6
                    : launch_matern_packed(lay, mats, locs, mp + c0, tables + c0 * TABLE, kk, s);
     }));
     if (!mixed) {
+      // per block column: the update of every tile of the column (the
+      // bordered row folded into the diagonal tile's workgroup), the
+      // diagonal tile's factor and inverse, the panel solve; the bordered
+      // row's own block closes the factorisation
       for (int J = 0; J <= lay.Nv; ++J) {
-        if (J > 0) {
-          const int nI = lay.Nv - J + 1;
-          PL_CHECK(timed(PL_KC_GEMM, kk * gemm_col_flops(lay, J, nI), s,
-                         [&] { return launch_gemm_col(lay, mats, info, J, nI, kk, s); }));
-        }
         if (J < lay.Nv) {
+          if (J > 0)
+            PL_CHECK(timed(PL_KC_GEMM, kk * gemm_col_flops(lay, J, lay.Nv - J + 1), s,
+                           [&] { return launch_col_update(lay, mats, info, J, kk, s); }));
           PL_CHECK(timed(PL_KC_POTRF, 0.0, s,
                          [&] { return launch_potrf(lay, mats, W, logdet, info, J, kk, s); }));
           PL_CHECK(timed(PL_KC_TRSM, 0.0, s,
                          [&] { return launch_trsm(lay, mats, W, info, J, lay.Nv - J, kk, s); }));
+        } else {
+          PL_CHECK(timed(PL_KC_GEMM, kk * gemm_col_flops(lay, J, 1), s,
+                         [&] { return launch_gemm_col(lay, mats, info, J, 1, kk, s); }));
         }
       }
     } else {

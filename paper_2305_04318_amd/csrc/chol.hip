@@ -193,6 +193,46 @@ hipError_t launch_potrf_mx(const Lay& lay, double* dscratch, float* W32, double*
                      logdet, info, J);
   return hipGetLastError();
 }
+// ---- FP64 block-column update with the bordered row folded in -------------------
+// Each omega has 1 + nOff workgroups, dispatched omega after omega: first the
+// diagonal tile J, whose update runs on the three waves of its lower
+// quadrants while the fourth (its quadrant lies above the diagonal) updates
+// the bordered row's tile when that is at most 32 rows high, then the
+// off-diagonal tiles of column J.  The 16-row bordered tiles, which would
+// take a whole workgroup for one block row of MFMA work, no longer occupy
+// workgroups of their own.  Consecutive logical workgroups share an XCD
+// (xcd_remap), so an omega's panels are read through one L2.
+template <bool VEC>
+__global__ __launch_bounds__(256, 2) void k_col_update(Lay lay, double* __restrict__ mats,
+                                                       const int32_t* __restrict__ info, int J,
+                                                       int border, int nOff, int G) {
+  __shared__ __attribute__((aligned(16))) char lds_raw[GEMM_LDS_BYTES];
+  double* lds = reinterpret_cast<double*>(lds_raw);
+  const int wg = xcd_remap(blockIdx.x, G);
+  const int k = wg / (nOff + 1), r = wg % (nOff + 1);
+  if (info[k] != 0) return;  // uniform for the workgroup
+  double* base = mats + (int64_t)k * lay.mstride;
+  if (r == 0) dev_gemm_diag_border<VEC>(lay, base, J, border != 0, lds);
+  else dev_gemm_col<VEC>(lay, base, J, J + r, lds);
+}
+
+hipError_t launch_col_update(const Lay& lay, double* mats, const int32_t* info, int J, int K,
+                             hipStream_t s) {
+  if (J <= 0 || J >= lay.Nv) return hipErrorInvalidValue;
+  const bool has_border = lay.kind == 0 && lay.q > 0;
+  const bool border = has_border && lay.TB <= 32;
+  // off-diagonal tile rows J+1 .. Nv-1, and the bordered row unless the
+  // diagonal workgroup takes it
+  const int nOff = (lay.Nv - 1 - J) + ((has_border && !border) ? 1 : 0);
+  const int G = K * (nOff + 1);
+  if (vec_ok(lay, mats))
+    hipLaunchKernelGGL(k_col_update<true>, dim3(G), dim3(256), 0, s, lay, mats, info, J,
+                       border ? 1 : 0, nOff, G);
+  else
+    hipLaunchKernelGGL(k_col_update<false>, dim3(G), dim3(256), 0, s, lay, mats, info, J,
+                       border ? 1 : 0, nOff, G);
+  return hipGetLastError();
+}
 
 // ---- panel solve L_IJ = C_IJ W_J^T for the nI tile rows below J -----------
 // TS double: W from Wbuf[k]; TS float: W from slot J of the omega's table.

@@ -99,6 +99,8 @@ hipError_t launch_trsm(const Lay& lay, double* mats, const double* W, const int3
                        int J, int nI, int K, hipStream_t s);
 hipError_t launch_gemm_col(const Lay& lay, double* mats, const int32_t* info, int J, int nI,
                            int K, hipStream_t s);
+hipError_t launch_col_update(const Lay& lay, double* mats, const int32_t* info, int J, int K,
+                             hipStream_t s);
 hipError_t launch_fill(double* p, double v, int64_t count, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s);
 hipError_t launch_boxcox_rhs(const double* y, const double* X, const double* lam, int n,

@@ -437,6 +437,157 @@ __device__ __forceinline__ void dev_trsm(const Lay& lay, TS* base, const TS* W, 
   }
 }
 
+// ---- diagonal tile and bordered row of block column J in one workgroup -----------
+// The diagonal tile's update is P P^T with P = L_J,0:J, so LDS holds that
+// panel once per chunk.  Waves (0,0), (1,0) and (1,1) compute the lower
+// quadrants as in wg_gemm_nt.  Wave (0,1), whose quadrant lies above the
+// diagonal, computes the bordered row's tile instead: Q P^T with Q the
+// bordered rows' panel (NBR = TB / 16 <= 2 block rows) against all 8 block
+// columns of P -- 8 NBR MFMA blocks, at most the 16 of a quadrant.  Border
+// block (ib, jb) lives in acc[2 ib + jb / 4][jb % 4].  Both roles run one
+// MFMA stream, acc[i][j] += B-fragment (i & 1, j) x A-fragment i, with
+// per-wave LDS offsets (two separate MFMA streams over the same accumulators
+// make the register allocator spill): a quadrant wave reads the same four
+// B fragments twice, the border wave two halves of P.  Rows at or beyond
+// prows / qrows and columns at or beyond kmax read as zero.
+constexpr int LQ = 32 + 4;  // LDS stride per k column of the bordered panel
+constexpr int DIAG_LDS_BYTES = 2 * 16 * (LROW + LQ) * 8;
+static_assert(DIAG_LDS_BYTES <= GEMM_LDS_BYTES, "the diagonal core shares the GEMM LDS");
+
+template <bool VEC>
+__device__ __forceinline__ void wg_gemm_diag_border(d4 (&acc)[4][4], double* lds,
+                                                    const double* __restrict__ P, int prows,
+                                                    const double* __restrict__ Q, int64_t ldq,
+                                                    int qrows, int nbr, int kmax) {
+  constexpr int N = 2, KC = 16, PPC = T / N;
+  constexpr int STAGE = KC * (LROW + LQ);
+  typedef dbl2 V;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = wave >> 1, wc = wave & 1;
+  const int nchunks = (kmax + KC - 1) / KC;
+  if (nchunks <= 0) return;
+  nbr = __builtin_amdgcn_readfirstlane(nbr);
+  const bool border_wave = wr == 0 && wc == 1;
+  // per-wave MFMA plan (uniform): block rows run, LDS offsets of the A
+  // fragments (with their k stride) and of the two B fragment sets
+  const int nie = __builtin_amdgcn_readfirstlane(border_wave ? 2 * nbr : nblk(prows - 64 * wr));
+  const int astr = border_wave ? LQ : LROW;
+  // A fragment i at abase + 16 (i >> ash); B fragment set h at bb0 + h * bdh
+  const int abase = border_wave ? KC * LROW : 64 * wr;
+  const int ash = border_wave ? 1 : 0;
+  const int bb0 = border_wave ? 0 : 64 * wc;
+  const int bdh = border_wave ? 64 : 0;
+  const int qppc = nbr * 16 / N;  // pieces per column of Q: 0, 8 or 16
+  const int qpieces = KC * qppc;  // 0, 128 or 256: at most one per thread
+  V rp[2][4], rq[2];
+  auto fetch = [&](int k0, auto setc) {
+    constexpr int S = decltype(setc)::value;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q;
+      const int col = idx / PPC, row = (idx % PPC) * N;
+      rp[S][q] = fetch_piece<double, VEC>(P, T, prows, k0 + col, kmax, row);
+    }
+    if (tid < qpieces) {
+      const int col = tid / qppc, row = (tid % qppc) * N;
+      rq[S] = fetch_piece<double, VEC>(Q, ldq, qrows, k0 + col, kmax, row);
+    }
+  };
+  auto stash = [&](auto setc) {
+    constexpr int S = decltype(setc)::value;
+    double* sp = lds + S * STAGE;
+    double* sq = sp + KC * LROW;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q;
+      const int col = idx / PPC, row = (idx % PPC) * N;
+      *reinterpret_cast<V*>(sp + col * LROW + row) = rp[S][q];
+    }
+    if (tid < qpieces) {
+      const int col = tid / qppc, row = (tid % qppc) * N;
+      *reinterpret_cast<V*>(sq + col * LQ + row) = rq[S];
+    }
+  };
+  using S0 = std::integral_constant<int, 0>;
+  using S1 = std::integral_constant<int, 1>;
+  fetch(0, S0{});
+  if (nchunks > 1) fetch(KC, S1{});
+  stash(S0{});
+  __syncthreads();
+  const int lr = lane & 15, lk = lane >> 4;
+  auto step = [&](int c, auto setc, auto other) {
+    constexpr int S = decltype(setc)::value;
+    if (c + 2 < nchunks) fetch((c + 2) * KC, setc);
+    const double* st = lds + S * STAGE + lr;
+#pragma unroll
+    for (int s4 = 0; s4 < KC / 4; ++s4) {
+      const int kk = 4 * s4 + lk;
+      double a[4], b[2][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = st[kk * astr + abase + 16 * (i >> ash)];
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[h][j] = st[kk * LROW + bb0 + h * bdh + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (i < nie) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = MF<double>::op(b[i & 1][j], a[i], acc[i][j]);
+        }
+      }
+    }
+    if (c + 1 < nchunks) stash(other);
+    __syncthreads();
+  };
+  for (int c = 0; c < nchunks; c += 2) {
+    step(c, S0{}, S1{});
+    if (c + 1 < nchunks) step(c + 1, S1{}, S0{});
+  }
+}
+
+// C_JJ -= L_J,0:J L_J,0:J^T and, when `border` (TB <= 32), the bordered row's
+// tile C_NvJ -= L_Nv,0:J L_J,0:J^T, in one workgroup (wg_gemm_diag_border).
+template <bool VEC>
+__device__ __forceinline__ void dev_gemm_diag_border(const Lay& lay, double* base, int J,
+                                                     bool border, double* lds) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wr = wave >> 1, wc = wave & 1;
+  const int prows = lay.rows(J);
+  const int qrows = border ? lay.q : 0;
+  const int nbr = border ? lay.TB / 16 : 0;
+  const int kmax = min(J * T, lay.n);
+  d4 acc[4][4];
+  zero_acc<double>(acc);
+  wg_gemm_diag_border<VEC>(acc, lds, base + lay.tile_off(J, 0), prows,
+                           base + lay.tile_off(lay.Nv, 0), lay.TB, qrows, nbr, kmax);
+  if (wr == 0 && wc == 1) {
+    if (nbr == 0) return;
+    double* C = base + lay.tile_off(lay.Nv, J);
+    const int64_t ldc = lay.TB;
+    const int lr = lane & 15, lg = lane >> 4;
+#pragma unroll
+    for (int ib = 0; ib < 2; ++ib) {
+      const int r = 16 * ib + lr;
+      if (ib >= nbr || r >= qrows) continue;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int c = 16 * j + MF<double>::col(lg, e);
+          if (c < prows) C[(int64_t)c * ldc + r] -= acc[2 * ib + j / 4][j % 4][e];
+        }
+    }
+    return;
+  }
+  const int war = prows - 64 * wr, wbr = prows - 64 * wc;
+  if (wc > wr || nblk(war) == 0 || nblk(wbr) == 0) return;
+  double* C = base + lay.tile_off(J, J) + 64 * wr + 64 * wc * T;
+  store64<double, true>(C, T, C, T, acc, war, wbr, lane);
+}
+
 // Diagonal tile J: factor and invert, register-blocked.
 // Thread t owns the 8x8 block (rows 8*(t/16).., columns 8*(t%16)..) of the
 // unit-padded tile; LDS only broadcasts one column (and one row) per step, with
