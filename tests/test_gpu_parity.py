@@ -7,6 +7,7 @@ Bessel route is good to ~1e-13); log|V| and l_p within
 import math
 
 import numpy as np
+from scipy.linalg import lapack
 import pytest
 import torch
 
@@ -136,10 +137,14 @@ def test_chunking_is_bitwise_invariant(plprof_lib):
 def test_non_pd_point_isolated(plprof_lib):
     pl = plprof_lib
     pr = synth.small_problem(150, p=2, K=3, M=2, seed=9)
-    locs = pr.locs.copy()
-    locs[7] = locs[3]
+    locs = pr.locs
     om = pr.omega.copy()
-    om[1, 2] = 0.0          # nugget 0 with a duplicate location: singular V
+    # range 50, shape 50, no nugget on a domain of side 5: numerical rank ~16,
+    # so any FP64 factorisation meets a non-positive pivot (a singular V that
+    # is only singular in exact arithmetic, e.g. a duplicate location without
+    # nugget, can factor with a tiny positive pivot in either implementation)
+    om[1] = [50.0, 50.0, 0.0, 1.0, 0.0]
+    assert lapack.dpotrf(oracle.build_V(locs, om[1]), lower=1)[1] > 0
     got = pl.profile_loglik(locs, pr.y, pr.X, om, pr.lam)
     torch.cuda.synchronize()
     info = got["info"].cpu().numpy()
