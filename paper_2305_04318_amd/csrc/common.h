@@ -15,8 +15,8 @@ constexpr int T = 128;
 // for the NBIN binades from 2^W_E_LO up, NC coefficients per piece.
 constexpr int W_E_LO = -20;        // w < 2^-20 (x < ~1e-3): direct quadrature
 constexpr int NBIN = 44;           // binades tabulated: w < 2^24 (x < 4096)
-constexpr int PB = 2;              // pieces per binade
-constexpr int NC = 14;             // coefficients per piece
+constexpr int PB = 4;              // pieces per binade
+constexpr int NC = 10;             // coefficients per piece
 constexpr int NPIECE = NBIN * PB;
 constexpr int TABLE = NPIECE * NC; // doubles per omega
 

@@ -7,8 +7,9 @@
 // the mantissa of each binade [2^e, 2^(e+1)) of w.  The only singularity of g
 // on or near the positive axis is at w = 0 (K_kappa has no zeros with
 // |arg z| <= pi/2), which lies at least 2 PB + 1 half-widths from every
-// piece, so the pieces converge geometrically (NC = 14, PB = 2 match the
-// quadrature to its own accuracy).  A matrix element then costs its binary
+// piece, so the pieces converge geometrically (NC = 10 terms on PB = 4
+// pieces match the quadrature to its own accuracy, ~2e-13 in rho, as do 14
+// terms on 2 pieces; the shorter sums are the cheaper evaluation).  A matrix element then costs its binary
 // exponent and mantissa, a Clenshaw sum and one exp -- no square root or
 // logarithm.  The node values come from a trapezoid-rule evaluation of
 // K_kappa(x) = int_0^inf exp(-x cosh t) cosh(kappa t) dt (DLMF 10.32.9),
