@@ -30,7 +30,7 @@ METRIC = ("profile-loglik points/sec at n=2000 (FP64 vs mixed, |Δℓ|≤1e-2); 
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 matrix peak
 PEAK_FP32_TFLOPS = 157.3    # MI355X dense FP32 matrix peak
 EXTRAS = ("mixed", "n4000", "n8000", "batch", "serve")
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "gemm_col_hbm_traffic_aniso_n2000_K1024.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "block_column_update_hbm_traffic_aniso_n2000_K1024.md")
 GEMM_SOURCES = ("common.h", "tiles.h", "chol.hip")
 
 
