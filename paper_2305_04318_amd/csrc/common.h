@@ -10,7 +10,7 @@ namespace plk {
 
 // Tile edge of the blocked factorisation and of the covariance builder.
 constexpr int T = 128;
-// Chebyshev tables of g(w) = log rho(sqrt w), w = x^2 = 8 kappa d^2, per
+// Chebyshev tables of rho(sqrt w), w = x^2 = 8 kappa d^2, per
 // omega: pieces uniform in the mantissa of w, PB per binade [2^e, 2^(e+1)),
 // for the NBIN binades from 2^W_E_LO up, NC coefficients per piece.
 constexpr int W_E_LO = -20;        // w < 2^-20 (x < ~1e-3): direct quadrature

@@ -2,16 +2,17 @@
 // covariance build V = R + nu^2 I (equation (1); Step 1 of Section 3.3).
 //
 // rho depends on a pair of locations only through the scaled distance
-// x = sqrt(8 kappa) d, so per omega the library tabulates g(w) = log rho(sqrt w)
-// in w = x^2 = 8 kappa d^2: Chebyshev pieces of NC terms, PB pieces uniform in
-// the mantissa of each binade [2^e, 2^(e+1)) of w.  The only singularity of g
-// on or near the positive axis is at w = 0 (K_kappa has no zeros with
+// x = sqrt(8 kappa) d, so per omega the library tabulates rho(sqrt w) in
+// w = x^2 = 8 kappa d^2: Chebyshev pieces of NC terms, PB pieces uniform in
+// the mantissa of each binade [2^e, 2^(e+1)) of w.  The only singularity on
+// or near the positive axis is at w = 0 (K_kappa has no zeros with
 // |arg z| <= pi/2), which lies at least 2 PB + 1 half-widths from every
 // piece, so the pieces converge geometrically (NC = 10 terms on PB = 4
-// pieces match the quadrature to its own accuracy, ~2e-13 in rho, as do 14
-// terms on 2 pieces; the shorter sums are the cheaper evaluation).  A matrix element then costs its binary
-// exponent and mantissa, a Clenshaw sum and one exp -- no square root or
-// logarithm.  The node values come from a trapezoid-rule evaluation of
+// pieces match the quadrature to its own accuracy, ~2.6e-13 absolute in rho).
+// V needs absolute accuracy, so rho itself is tabulated rather than log rho
+// (which would cost an exp per element): a matrix element costs its binary
+// exponent and mantissa and a Clenshaw sum -- no square root, logarithm or
+// exponential.  The node values come from a trapezoid-rule evaluation of
 // K_kappa(x) = int_0^inf exp(-x cosh t) cosh(kappa t) dt (DLMF 10.32.9),
 // which converges geometrically for this analytic, doubly exponentially
 // decaying integrand; w < 2^W_E_LO (points far closer than the range) uses
@@ -35,7 +36,7 @@ __global__ void k_cheb_nodes(const MaternParams* __restrict__ mp, double* __rest
   const double sj = cos(M_PI * (j + 0.5) / NC);
   // node j of piece `sub` of binade W_E_LO + bin, in the mantissa of w
   const double w = ldexp(1.0 + (sub + 0.5 + 0.5 * sj) / PB, W_E_LO + bin);
-  nodes[idx] = g_direct(P, w);
+  nodes[idx] = exp(g_direct(P, w));
 }
 
 __global__ void k_cheb_coeffs(const double* __restrict__ nodes, double* __restrict__ tables, int K) {

@@ -42,9 +42,9 @@ static __device__ double g_direct(const MaternParams& P, double w) {
 }
 
 // rho for one element given d^2 (the squared anisotropic distance) and the
-// omega's table (TABLE doubles).  The piece comes from the binary exponent and
-// mantissa of w = 8 kappa d^2 (no logarithm), the value from a Clenshaw sum
-// and one exp.
+// omega's table (TABLE doubles, Chebyshev coefficients of rho itself).  The
+// piece comes from the binary exponent and mantissa of w = 8 kappa d^2 (no
+// logarithm), the value from a Clenshaw sum clamped to [0, 1] (no exp).
 __device__ __forceinline__ double rho_eval(const MaternParams& P, const double* tab, double d2) {
   const double w = P.k8 * d2;
   if (w == 0.0) return 1.0;
@@ -69,8 +69,8 @@ __device__ __forceinline__ double rho_eval(const MaternParams& P, const double* 
     b2 = b1;
     b1 = tmp;
   }
-  const double g = fma(s, b1, c[0] - b2);
-  return fmin(exp(g), 1.0);
+  const double r = fma(s, b1, c[0] - b2);
+  return fmin(fmax(r, 0.0), 1.0);
 }
 
 // ---- covariance tiles -----------------------------------------------------
