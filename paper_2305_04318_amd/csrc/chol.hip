@@ -87,9 +87,12 @@ __global__ __launch_bounds__(256, 2) void k_gemm_col_mx(Lay lay, float* __restri
 }
 
 // Mixed form, diagonal tile J: FP64 MFMA on the FP32 panel, subtracted from V's
-// FP64 tile, written to the FP64 scratch tile that k_potrf reads.
-template <bool VEC>
-__global__ __launch_bounds__(256, 2) void k_gemm_diag_mx(Lay lay, const float* __restrict__ m32,
+// FP64 tile, written to the FP64 scratch tile that k_potrf reads.  BORDER:
+// the wave whose quadrant lies above the diagonal also updates the bordered
+// row's FP32 tile (FP64 MFMA on the FP32 panels, one rounding to FP32), so
+// k_gemm_col_mx does not give that 16- or 32-row tile a workgroup of its own.
+template <bool VEC, bool BORDER>
+__global__ __launch_bounds__(256, 2) void k_gemm_diag_mx(Lay lay, float* __restrict__ m32,
                                                          const double* __restrict__ m64,
                                                          int64_t m64stride,
                                                          double* __restrict__ dscratch,
@@ -104,12 +107,39 @@ __global__ __launch_bounds__(256, 2) void k_gemm_diag_mx(Lay lay, const float* _
   const int war = rows - 64 * wr, wbr = rows - 64 * wc;
   const int ni = nblk(war), nj = nblk(wbr);
   const bool act = ni > 0 && nj > 0 && wc <= wr;
-  const float* P = m32 + (int64_t)k * lay.mstride + lay.tile_off(J, 0);
+  float* base = m32 + (int64_t)k * lay.mstride;
+  const float* P = base + lay.tile_off(J, 0);
   const int kmax = min(J * T, lay.n);
   d4 acc[4][4];
   zero_acc<double>(acc);
-  wg_gemm_nt<float, double, VEC>(acc, lds, P, lay.tile_ld(J), rows, P, lay.tile_ld(J), rows, kmax,
-                                 act, ni);
+  if constexpr (BORDER) {
+    wg_gemm_diag_border<VEC, float>(acc, lds, P, rows, base + lay.tile_off(lay.Nv, 0), lay.TB,
+                                    lay.q, lay.TB / 16, kmax);
+    if (wr == 0 && wc == 1) {
+      if (kmax == 0) return;  // nothing to subtract
+      float* C = base + lay.tile_off(lay.Nv, J);
+      const int64_t ldc = lay.TB;
+      const int lr = lane & 15, lg = lane >> 4, nbr = lay.TB / 16;
+#pragma unroll
+      for (int ib = 0; ib < 2; ++ib) {
+        const int r = 16 * ib + lr;
+        if (ib >= nbr || r >= lay.q) continue;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int c = 16 * j + MF<double>::col(lg, e);
+            if (c < rows)
+              C[(int64_t)c * ldc + r] =
+                  (float)((double)C[(int64_t)c * ldc + r] - acc[2 * ib + j / 4][j % 4][e]);
+          }
+      }
+      return;
+    }
+  } else {
+    wg_gemm_nt<float, double, VEC>(acc, lds, P, lay.tile_ld(J), rows, P, lay.tile_ld(J), rows,
+                                   kmax, act, ni);
+  }
   if (act) {
     const double* Cin = m64 + (int64_t)k * m64stride + lay.tile_off(J, J) + 64 * wr + 64 * wc * T;
     double* Cout = dscratch + (int64_t)k * T * T + 64 * wr + 64 * wc * T;
@@ -134,9 +164,17 @@ hipError_t launch_gemm_col(const Lay& lay, double* mats, const int32_t* info, in
 hipError_t launch_gemm_col_mx(const Lay& lay, float* m32, const double* m64, int64_t m64stride,
                               double* dscratch, const int32_t* info, int J, int nI, int K,
                               int flush, hipStream_t s) {
-  // nI counts the tile rows from J down (the diagonal tile included)
-  hipLaunchKernelGGL(k_gemm_diag_mx<true>, dim3(K), dim3(256), 0, s, lay, m32, m64, m64stride,
-                     dscratch, info, J);
+  // nI counts the tile rows from J down (the diagonal tile included); the
+  // bordered row (the last of them, when J > 0) is folded into the diagonal
+  // kernel when it is at most 32 rows high
+  const bool border = lay.kind == 0 && lay.q > 0 && lay.TB <= 32;
+  if (border)
+    hipLaunchKernelGGL((k_gemm_diag_mx<true, true>), dim3(K), dim3(256), 0, s, lay, m32, m64,
+                       m64stride, dscratch, info, J);
+  else
+    hipLaunchKernelGGL((k_gemm_diag_mx<true, false>), dim3(K), dim3(256), 0, s, lay, m32, m64,
+                       m64stride, dscratch, info, J);
+  if (border && J > 0) --nI;
   if (nI > 1) {
     const int G = K * (nI - 1);
     switch (flush) {

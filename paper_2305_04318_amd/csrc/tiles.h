@@ -466,14 +466,15 @@ constexpr int LQ = 32 + 4;  // LDS stride per k column of the bordered panel
 constexpr int DIAG_LDS_BYTES = 2 * 16 * (LROW + LQ) * 8;
 static_assert(DIAG_LDS_BYTES <= GEMM_LDS_BYTES, "the diagonal core shares the GEMM LDS");
 
-template <bool VEC>
-__device__ __forceinline__ void wg_gemm_diag_border(d4 (&acc)[4][4], double* lds,
-                                                    const double* __restrict__ P, int prows,
-                                                    const double* __restrict__ Q, int64_t ldq,
+template <bool VEC, typename TS = double>
+__device__ __forceinline__ void wg_gemm_diag_border(d4 (&acc)[4][4], TS* lds,
+                                                    const TS* __restrict__ P, int prows,
+                                                    const TS* __restrict__ Q, int64_t ldq,
                                                     int qrows, int nbr, int kmax) {
-  constexpr int N = 2, KC = 16, PPC = T / N;
+  // TS: storage of the panels (FP64, or FP32 in the mixed form); the MFMA is FP64
+  constexpr int N = Piece<TS>::N, KC = 128 / (int)sizeof(TS), PPC = T / N;
   constexpr int STAGE = KC * (LROW + LQ);
-  typedef dbl2 V;
+  typedef typename Piece<TS>::type V;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave >> 1, wc = wave & 1;
@@ -490,8 +491,8 @@ __device__ __forceinline__ void wg_gemm_diag_border(d4 (&acc)[4][4], double* lds
   const int ash = border_wave ? 1 : 0;
   const int bb0 = border_wave ? 0 : 64 * wc;
   const int bdh = border_wave ? 64 : 0;
-  const int qppc = nbr * 16 / N;  // pieces per column of Q: 0, 8 or 16
-  const int qpieces = KC * qppc;  // 0, 128 or 256: at most one per thread
+  const int qppc = nbr * 16 / N;  // pieces per column of Q
+  const int qpieces = KC * qppc;  // at most 256: at most one per thread
   V rp[2][4], rq[2];
   const bool whole_rows = __builtin_amdgcn_readfirstlane((int)(prows == T)) != 0;
   auto fetch = [&](int k0, auto setc) {
@@ -508,18 +509,18 @@ __device__ __forceinline__ void wg_gemm_diag_border(d4 (&acc)[4][4], double* lds
       for (int q = 0; q < 4; ++q) {
         const int idx = tid + 256 * q;
         const int col = idx / PPC, row = (idx % PPC) * N;
-        rp[S][q] = fetch_piece<double, VEC>(P, T, prows, k0 + col, kmax, row);
+        rp[S][q] = fetch_piece<TS, VEC>(P, T, prows, k0 + col, kmax, row);
       }
     }
     if (tid < qpieces) {
       const int col = tid / qppc, row = (tid % qppc) * N;
-      rq[S] = fetch_piece<double, VEC>(Q, ldq, qrows, k0 + col, kmax, row);
+      rq[S] = fetch_piece<TS, VEC>(Q, ldq, qrows, k0 + col, kmax, row);
     }
   };
   auto stash = [&](auto setc) {
     constexpr int S = decltype(setc)::value;
-    double* sp = lds + S * STAGE;
-    double* sq = sp + KC * LROW;
+    TS* sp = lds + S * STAGE;
+    TS* sq = sp + KC * LROW;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int idx = tid + 256 * q;
@@ -541,17 +542,17 @@ __device__ __forceinline__ void wg_gemm_diag_border(d4 (&acc)[4][4], double* lds
   auto step = [&](int c, auto setc, auto other) {
     constexpr int S = decltype(setc)::value;
     if (c + 2 < nchunks) fetch((c + 2) * KC, setc);
-    const double* st = lds + S * STAGE + lr;
+    const TS* st = lds + S * STAGE + lr;
 #pragma unroll
     for (int s4 = 0; s4 < KC / 4; ++s4) {
       const int kk = 4 * s4 + lk;
       double a[4], b[2][4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = st[kk * astr + abase + 16 * (i >> ash)];
+      for (int i = 0; i < 4; ++i) a[i] = (double)st[kk * astr + abase + 16 * (i >> ash)];
 #pragma unroll
       for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) b[h][j] = st[kk * LROW + bb0 + h * bdh + 16 * j];
+        for (int j = 0; j < 4; ++j) b[h][j] = (double)st[kk * LROW + bb0 + h * bdh + 16 * j];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         if (i < nie) {
