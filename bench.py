@@ -400,8 +400,8 @@ def main():
         traffic = measured_traffic() if default_shape else None
     else:
         peak = PEAK_FP32_TFLOPS
-        kernel_name = ("k_gemm_col_mx + k_gemm_diag_mx (block-column update: FP32 MFMA with "
-                       "FP64 flushes off the diagonal, FP64 MFMA on diagonal tiles)")
+        kernel_name = ("k_col_update_mx (block-column update: FP32 MFMA with FP64 flushes off "
+                       "the diagonal, FP64 MFMA on the diagonal tile and the bordered row)")
         traffic = None
     rec64 = {k: v.cpu().numpy() for k, v in pl.unpack_records(out).items()}
     rec64["beta"] = beta.cpu().numpy()

@@ -50,17 +50,9 @@ __global__ __launch_bounds__(256, 2) void k_gemm_col(Lay lay, double* __restrict
 // FP64 fold): 1, 2 or 4, chosen by the caller (default MX_FLUSH; pl_autotune
 // measures the speed/accuracy trade-off per workload).
 template <bool VEC, int FLUSH>
-__global__ __launch_bounds__(256, 2) void k_gemm_col_mx(Lay lay, float* __restrict__ m32,
-                                                        const double* __restrict__ m64,
-                                                        int64_t m64stride,
-                                                        const int32_t* __restrict__ info, int J,
-                                                        int nI, int G) {
-  __shared__ __attribute__((aligned(16))) char lds_raw[GEMM_LDS_BYTES];
-  float* lds = reinterpret_cast<float*>(lds_raw);
-  const int wg = xcd_remap(blockIdx.x, G);
-  const int k = wg / nI;
-  const int I = J + 1 + wg % nI;  // tile rows strictly below the diagonal
-  if (info[k] != 0) return;       // uniform for the workgroup
+__device__ __forceinline__ void dev_col_mx(const Lay& lay, float* __restrict__ m32,
+                                           const double* __restrict__ m64, int64_t m64stride,
+                                           int k, int I, int J, float* lds) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wr = wave >> 1, wc = wave & 1;
   const int arows = lay.rows(I), brows = lay.rows(J);
@@ -90,17 +82,13 @@ __global__ __launch_bounds__(256, 2) void k_gemm_col_mx(Lay lay, float* __restri
 // FP64 tile, written to the FP64 scratch tile that k_potrf reads.  BORDER:
 // the wave whose quadrant lies above the diagonal also updates the bordered
 // row's FP32 tile (FP64 MFMA on the FP32 panels, one rounding to FP32), so
-// k_gemm_col_mx does not give that 16- or 32-row tile a workgroup of its own.
+// the off-diagonal work does not give that 16- or 32-row tile a workgroup of
+// its own.
 template <bool VEC, bool BORDER>
-__global__ __launch_bounds__(256, 2) void k_gemm_diag_mx(Lay lay, float* __restrict__ m32,
-                                                         const double* __restrict__ m64,
-                                                         int64_t m64stride,
-                                                         double* __restrict__ dscratch,
-                                                         const int32_t* __restrict__ info, int J) {
-  __shared__ __attribute__((aligned(16))) char lds_raw[GEMM_LDS_BYTES];
-  float* lds = reinterpret_cast<float*>(lds_raw);
-  const int k = blockIdx.x;
-  if (info[k] != 0) return;
+__device__ __forceinline__ void dev_diag_mx(const Lay& lay, float* __restrict__ m32,
+                                            const double* __restrict__ m64, int64_t m64stride,
+                                            double* __restrict__ dscratch, int k, int J,
+                                            float* lds) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wr = wave >> 1, wc = wave & 1;
   const int rows = lay.rows(J);
@@ -147,6 +135,33 @@ __global__ __launch_bounds__(256, 2) void k_gemm_diag_mx(Lay lay, float* __restr
   }
 }
 
+// Mixed-form block-column update in one launch: the K diagonal tiles (FP64
+// MFMA, with the bordered row's tile on the idle wave; about twice as long
+// as an FP32 tile) are dispatched first, the off-diagonal tiles (FP32 MFMA
+// with FP64 folds) after them, so the diagonal work overlaps the bulk of the
+// update instead of running as a launch of K workgroups of its own.
+template <int FLUSH>
+__global__ __launch_bounds__(256, 2) void k_col_update_mx(Lay lay, float* __restrict__ m32,
+                                                          const double* __restrict__ m64,
+                                                          int64_t m64stride,
+                                                          double* __restrict__ dscratch,
+                                                          const int32_t* __restrict__ info, int J,
+                                                          int nOff, int K) {
+  __shared__ __attribute__((aligned(16))) char lds_raw[GEMM_LDS_BYTES];
+  float* lds = reinterpret_cast<float*>(lds_raw);
+  const int b = blockIdx.x;
+  if (b < K) {
+    if (info[b] != 0) return;  // uniform for the workgroup
+    dev_diag_mx<true, true>(lay, m32, m64, m64stride, dscratch, b, J, lds);
+    return;
+  }
+  const int G = K * nOff;
+  const int wg = xcd_remap(b - K, G);
+  const int k = wg / nOff, r = wg % nOff;
+  if (info[k] != 0) return;
+  dev_col_mx<true, FLUSH>(lay, m32, m64, m64stride, k, J + 1 + r, J, lds);
+}
+
 static bool vec_ok(const Lay& lay, const void* p) {
   return (reinterpret_cast<uintptr_t>(p) & 15) == 0 && (lay.kind == 0 || (lay.ld % 2) == 0);
 }
@@ -164,35 +179,27 @@ hipError_t launch_gemm_col(const Lay& lay, double* mats, const int32_t* info, in
 hipError_t launch_gemm_col_mx(const Lay& lay, float* m32, const double* m64, int64_t m64stride,
                               double* dscratch, const int32_t* info, int J, int nI, int K,
                               int flush, hipStream_t s) {
-  // nI counts the tile rows from J down (the diagonal tile included); the
-  // bordered row (the last of them, when J > 0) is folded into the diagonal
-  // kernel when it is at most 32 rows high
-  const bool border = lay.kind == 0 && lay.q > 0 && lay.TB <= 32;
-  if (border)
-    hipLaunchKernelGGL((k_gemm_diag_mx<true, true>), dim3(K), dim3(256), 0, s, lay, m32, m64,
-                       m64stride, dscratch, info, J);
-  else
-    hipLaunchKernelGGL((k_gemm_diag_mx<true, false>), dim3(K), dim3(256), 0, s, lay, m32, m64,
-                       m64stride, dscratch, info, J);
-  if (border && J > 0) --nI;
-  if (nI > 1) {
-    const int G = K * (nI - 1);
-    switch (flush) {
-      case 1:
-        hipLaunchKernelGGL((k_gemm_col_mx<true, 1>), dim3(G), dim3(256), 0, s, lay, m32, m64,
-                           m64stride, info, J, nI - 1, G);
-        break;
-      case 2:
-        hipLaunchKernelGGL((k_gemm_col_mx<true, 2>), dim3(G), dim3(256), 0, s, lay, m32, m64,
-                           m64stride, info, J, nI - 1, G);
-        break;
-      case 4:
-        hipLaunchKernelGGL((k_gemm_col_mx<true, 4>), dim3(G), dim3(256), 0, s, lay, m32, m64,
-                           m64stride, info, J, nI - 1, G);
-        break;
-      default:
-        return hipErrorInvalidValue;
-    }
+  // nI counts the tile rows from J down (the diagonal tile included).  The
+  // mixed form has M + p <= 32, so the bordered row (the last of the nI rows
+  // when J > 0) is always folded into the diagonal tile's workgroup.
+  if (!(lay.kind == 0 && lay.q > 0 && lay.TB <= 32)) return hipErrorInvalidValue;
+  const int nOff = (J > 0) ? nI - 2 : 0;  // V tiles strictly below the diagonal
+  const int G = K * (nOff + 1);
+  switch (flush) {
+    case 1:
+      hipLaunchKernelGGL(k_col_update_mx<1>, dim3(G), dim3(256), 0, s, lay, m32, m64, m64stride,
+                         dscratch, info, J, nOff, K);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_col_update_mx<2>, dim3(G), dim3(256), 0, s, lay, m32, m64, m64stride,
+                         dscratch, info, J, nOff, K);
+      break;
+    case 4:
+      hipLaunchKernelGGL(k_col_update_mx<4>, dim3(G), dim3(256), 0, s, lay, m32, m64, m64stride,
+                         dscratch, info, J, nOff, K);
+      break;
+    default:
+      return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
