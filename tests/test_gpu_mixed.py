@@ -19,7 +19,8 @@ def _run(pl, pr, **kw):
     return {k: v.cpu().numpy() for k, v in res.items()}
 
 
-@pytest.mark.parametrize("n,p,K,M,seed", [(300, 2, 4, 3, 11), (700, 4, 4, 8, 12), (1100, 3, 3, 4, 13)])
+@pytest.mark.parametrize("n,p,K,M,seed", [(300, 2, 4, 3, 11), (700, 4, 4, 8, 12), (1100, 3, 3, 4, 13),
+                                          (500, 4, 3, 24, 14)])
 def test_mixed_parity(plprof_lib, n, p, K, M, seed):
     pl = plprof_lib
     pr = synth.small_problem(n, p=p, K=K, M=M, seed=seed)
