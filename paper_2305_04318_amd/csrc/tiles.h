@@ -158,20 +158,8 @@ __device__ __forceinline__ void wg_gemm_nt(typename MF<TC>::acc (&acc)[4][4], TS
   // two register sets: chunk c + 2 is fetched while chunk c is multiplied and
   // chunk c + 1 (fetched a chunk earlier) waits in registers for its LDS stage
   V ra[2][4], rb[2][4];
-  // whole chunks of whole panels (nearly all of them) load without guards
-  const bool whole_rows = __builtin_amdgcn_readfirstlane((int)(arows == T && brows == T)) != 0;
   auto fetch = [&](int k0, auto setc) {
     constexpr int S = decltype(setc)::value;
-    if (VEC && whole_rows && k0 + KC <= kmax) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int idx = tid + 256 * q;
-        const int col = idx / PPC, row = (idx % PPC) * N;
-        ra[S][q] = *reinterpret_cast<const V*>(A + (int64_t)(k0 + col) * lda + row);
-        rb[S][q] = *reinterpret_cast<const V*>(B + (int64_t)(k0 + col) * ldb + row);
-      }
-      return;
-    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int idx = tid + 256 * q;
@@ -494,23 +482,13 @@ __device__ __forceinline__ void wg_gemm_diag_border(d4 (&acc)[4][4], TS* lds,
   const int qppc = nbr * 16 / N;  // pieces per column of Q
   const int qpieces = KC * qppc;  // at most 256: at most one per thread
   V rp[2][4], rq[2];
-  const bool whole_rows = __builtin_amdgcn_readfirstlane((int)(prows == T)) != 0;
   auto fetch = [&](int k0, auto setc) {
     constexpr int S = decltype(setc)::value;
-    if (VEC && whole_rows && k0 + KC <= kmax) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int idx = tid + 256 * q;
-        const int col = idx / PPC, row = (idx % PPC) * N;
-        rp[S][q] = *reinterpret_cast<const V*>(P + (int64_t)(k0 + col) * T + row);
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int idx = tid + 256 * q;
-        const int col = idx / PPC, row = (idx % PPC) * N;
-        rp[S][q] = fetch_piece<TS, VEC>(P, T, prows, k0 + col, kmax, row);
-      }
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q;
+      const int col = idx / PPC, row = (idx % PPC) * N;
+      rp[S][q] = fetch_piece<TS, VEC>(P, T, prows, k0 + col, kmax, row);
     }
     if (tid < qpieces) {
       const int col = tid / qppc, row = (tid % qppc) * N;
