@@ -105,23 +105,8 @@ __device__ __forceinline__ void dev_diag_mx(const Lay& lay, float* __restrict__ 
                                     lay.q, lay.TB / 16, kmax);
     if (wr == 0 && wc == 1) {
       if (kmax == 0) return;  // nothing to subtract
-      float* C = base + lay.tile_off(lay.Nv, J);
-      const int64_t ldc = lay.TB;
-      const int lr = lane & 15, lg = lane >> 4, nbr = lay.TB / 16;
-#pragma unroll
-      for (int ib = 0; ib < 2; ++ib) {
-        const int r = 16 * ib + lr;
-        if (ib >= nbr || r >= lay.q) continue;
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int c = 16 * j + MF<double>::col(lg, e);
-            if (c < rows)
-              C[(int64_t)c * ldc + r] =
-                  (float)((double)C[(int64_t)c * ldc + r] - acc[2 * ib + j / 4][j % 4][e]);
-          }
-      }
+      sub_store_border<float>(base + lay.tile_off(lay.Nv, J), lay.TB, acc, lay.TB / 16, lay.q,
+                              rows, lane);
       return;
     }
   } else {

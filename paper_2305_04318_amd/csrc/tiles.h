@@ -336,51 +336,104 @@ __device__ __forceinline__ void zero_acc(typename MF<TC>::acc (&acc)[4][4]) {
 }
 
 // Cout[r][c] = (SUB ? Cin[r][c] - acc : acc) for the valid part of a wave's
-// 64x64 tile; LAYOUT names the MFMA whose result layout acc follows.
-template <typename LAYOUT, bool SUB, typename TI, typename TO, typename ACC>
+// 64x64 tile; LAYOUT names the MFMA whose result layout acc follows.  With
+// SUB the 16 Cin values of a block row are loaded together, from addresses
+// clamped into the valid part, before any of its stores: element by element,
+// each load would wait behind the store before it (Cin and Cout may alias),
+// 64 dependent HBM round trips per lane instead of 4.  BATCH = false keeps
+// the element-by-element form for register-bound callers (the 16 staged
+// values per lane would spill there).
+template <typename LAYOUT, bool SUB, typename TI, typename TO, typename ACC, bool BATCH = true>
 __device__ __forceinline__ void store64_l(const TI* Cin, int64_t ldin, TO* Cout, int64_t ldout,
                                           const ACC (&acc)[4][4], int arows, int brows, int lane) {
   const int lr = lane & 15, lg = lane >> 4;
+  if constexpr (SUB && BATCH) {
+    arows = __builtin_amdgcn_readfirstlane(arows);  // per-wave values
+    brows = __builtin_amdgcn_readfirstlane(brows);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int r = 16 * i + lr;
-    if (r >= arows) continue;
+    for (int i = 0; i < 4; ++i) {
+      if (16 * i >= arows) break;
+      const int r = 16 * i + lr, rc = min(r, arows - 1);
+      double cin[4][4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int c = 16 * j + MF<LAYOUT>::col(lg, e);
-        if (c < brows) {
-          const double v = (double)acc[i][j][e];
-          TO* po = Cout + (int64_t)c * ldout + r;
-          if (SUB) *po = (TO)((double)Cin[(int64_t)c * ldin + r] - v);
-          else *po = (TO)v;
+        for (int e = 0; e < 4; ++e) {
+          const int cc = min(16 * j + MF<LAYOUT>::col(lg, e), brows - 1);
+          cin[j][e] = (double)Cin[(int64_t)cc * ldin + rc];
+        }
+      if (r >= arows) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int c = 16 * j + MF<LAYOUT>::col(lg, e);
+          if (c < brows) Cout[(int64_t)c * ldout + r] = (TO)(cin[j][e] - (double)acc[i][j][e]);
+        }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = 16 * i + lr;
+      if (r >= arows) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int c = 16 * j + MF<LAYOUT>::col(lg, e);
+          if (c < brows) {
+            const double v = (double)acc[i][j][e];
+            TO* po = Cout + (int64_t)c * ldout + r;
+            if (SUB) *po = (TO)((double)Cin[(int64_t)c * ldin + r] - v);
+            else *po = (TO)v;
+          }
         }
       }
     }
   }
 }
 
-template <typename TC, bool SUB, typename TI, typename TO>
+template <typename TC, bool SUB, typename TI, typename TO, bool BATCH = true>
 __device__ __forceinline__ void store64(const TI* Cin, int64_t ldin, TO* Cout, int64_t ldout,
                                         const typename MF<TC>::acc (&acc)[4][4], int arows,
                                         int brows, int lane) {
+  store64_l<TC, SUB, TI, TO, typename MF<TC>::acc, BATCH>(Cin, ldin, Cout, ldout, acc, arows,
+                                                          brows, lane);
+}
+
+// C -= the bordered row's tile held by the border wave of the diagonal-tile
+// workgroup: block (ib, jb) of the nbr x 8 blocks in acc[2 ib + jb / 4][jb % 4]
+// (FP64 MFMA layout); rows below qrows and columns below prows are valid.
+// The loads of four blocks are issued together, as in store64_l.
+template <typename TO>
+__device__ __forceinline__ void sub_store_border(TO* C, int64_t ldc, const d4 (&acc)[4][4],
+                                                 int nbr, int qrows, int prows, int lane) {
   const int lr = lane & 15, lg = lane >> 4;
+  nbr = __builtin_amdgcn_readfirstlane(nbr);
+  qrows = __builtin_amdgcn_readfirstlane(qrows);
+  prows = __builtin_amdgcn_readfirstlane(prows);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int r = 16 * i + lr;
-    if (r >= arows) continue;
+  for (int ib = 0; ib < 2; ++ib) {
+    if (ib >= nbr || 16 * ib >= qrows) break;
+    const int r = 16 * ib + lr, rc = min(r, qrows - 1);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int h = 0; h < 2; ++h) {
+      double cin[4][4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int c = 16 * j + MF<TC>::col(lg, e);
-        if (c < brows) {
-          const double v = (double)acc[i][j][e];
-          TO* po = Cout + (int64_t)c * ldout + r;
-          if (SUB) *po = (TO)((double)Cin[(int64_t)c * ldin + r] - v);
-          else *po = (TO)v;
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int cc = min(64 * h + 16 * j + MF<double>::col(lg, e), prows - 1);
+          cin[j][e] = (double)C[(int64_t)cc * ldc + rc];
         }
+      if (r < qrows) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int c = 64 * h + 16 * j + MF<double>::col(lg, e);
+            if (c < prows) C[(int64_t)c * ldc + r] = (TO)(cin[j][e] - acc[2 * ib + h][j][e]);
+          }
       }
     }
   }
@@ -409,7 +462,7 @@ __device__ __forceinline__ void dev_gemm_col(const Lay& lay, double* base, int J
   if (act) {
     const int64_t ldc = lay.tile_ld(I);
     double* C = base + lay.tile_off(I, J) + 64 * wr + 64 * wc * ldc;
-    store64<double, true>(C, ldc, C, ldc, acc, war, wbr, lane);
+    store64<double, true, double, double, (DEPTH > 1)>(C, ldc, C, ldc, acc, war, wbr, lane);
   }
 }
 
@@ -566,21 +619,7 @@ __device__ __forceinline__ void dev_gemm_diag_border(const Lay& lay, double* bas
                            base + lay.tile_off(lay.Nv, 0), lay.TB, qrows, nbr, kmax);
   if (wr == 0 && wc == 1) {
     if (nbr == 0) return;
-    double* C = base + lay.tile_off(lay.Nv, J);
-    const int64_t ldc = lay.TB;
-    const int lr = lane & 15, lg = lane >> 4;
-#pragma unroll
-    for (int ib = 0; ib < 2; ++ib) {
-      const int r = 16 * ib + lr;
-      if (ib >= nbr || r >= qrows) continue;
-#pragma unroll
-      for (int j = 0; j < 8; ++j)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int c = 16 * j + MF<double>::col(lg, e);
-          if (c < prows) C[(int64_t)c * ldc + r] -= acc[2 * ib + j / 4][j % 4][e];
-        }
-    }
+    sub_store_border<double>(base + lay.tile_off(lay.Nv, J), lay.TB, acc, nbr, qrows, prows, lane);
     return;
   }
   const int war = prows - 64 * wr, wbr = prows - 64 * wc;
