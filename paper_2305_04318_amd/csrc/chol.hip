@@ -25,6 +25,8 @@
 #include <math.h>
 #include <stdlib.h>
 
+#include <algorithm>
+
 #include "tiles.h"
 
 namespace plk {
@@ -312,15 +314,111 @@ hipError_t launch_trsm_mx(const Lay& lay, float* m32, const float* W32, const in
 //   Y = V_IJ x0_J on MFMA f64 (the GEMM core, x0 as a TB x T column-major panel),
 //   M = x0_I^T Y;  slot = -(M + M^T) for I > J,  2 B_I^T x0_I - M for I = J.
 // The slots are summed in a fixed order by k_finalize (deterministic).
+// acc[i][0:NB] += A[0:128, 0:kmax] B[0:16 NB, 0:kmax]^T: the GEMM core for a
+// B of at most 16 NB rows (x0_J), with an LDS stage sized for those rows
+// instead of 128, so that more workgroups fit a compute unit.  The quadratic
+// forms stream V once with little arithmetic per byte, so resident
+// workgroups (loads in flight) bound them, not the MFMAs.  Same two-set
+// register pipeline and guarded loads as wg_gemm_nt; only the waves of the
+// first wave column (B rows 0 .. 16 NB - 1) multiply.
+template <int NB>
+__device__ __forceinline__ void wg_gemm_rhs(d4 (&acc)[4][4], double* lds,
+                                            const double* __restrict__ A, int64_t lda, int arows,
+                                            const double* __restrict__ B, int64_t ldb, int brows,
+                                            int kmax, bool do_mfma, int ni) {
+  constexpr int N = 2, KC = 16, PPC = T / N;
+  constexpr int BR = 16 * NB, LB = BR + 4, BPPC = BR / N, BPIECES = KC * BPPC;
+  constexpr int STAGE = KC * (LROW + LB);
+  static_assert(BPIECES <= 256, "one B piece per thread");
+  typedef dbl2 V;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1;
+  const int nchunks = (kmax + KC - 1) / KC;
+  if (nchunks <= 0) return;
+  ni = __builtin_amdgcn_readfirstlane(ni);
+  do_mfma = __builtin_amdgcn_readfirstlane((int)do_mfma) != 0;
+  V ra[2][4], rb[2];
+  auto fetch = [&](int k0, auto setc) {
+    constexpr int S = decltype(setc)::value;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q;
+      const int col = idx / PPC, row = (idx % PPC) * N;
+      ra[S][q] = fetch_piece<double, true>(A, lda, arows, k0 + col, kmax, row);
+    }
+    if (tid < BPIECES) {
+      const int col = tid / BPPC, row = (tid % BPPC) * N;
+      rb[S] = fetch_piece<double, true>(B, ldb, brows, k0 + col, kmax, row);
+    }
+  };
+  auto stash = [&](auto setc) {
+    constexpr int S = decltype(setc)::value;
+    double* sa = lds + S * STAGE;
+    double* sb = sa + KC * LROW;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q;
+      const int col = idx / PPC, row = (idx % PPC) * N;
+      *reinterpret_cast<V*>(sa + col * LROW + row) = ra[S][q];
+    }
+    if (tid < BPIECES) {
+      const int col = tid / BPPC, row = (tid % BPPC) * N;
+      *reinterpret_cast<V*>(sb + col * LB + row) = rb[S];
+    }
+  };
+  using S0 = std::integral_constant<int, 0>;
+  using S1 = std::integral_constant<int, 1>;
+  fetch(0, S0{});
+  if (nchunks > 1) fetch(KC, S1{});
+  stash(S0{});
+  __syncthreads();
+  const int lr = lane & 15, lk = lane >> 4;
+  auto step = [&](int c, auto setc, auto other) {
+    constexpr int S = decltype(setc)::value;
+    if (c + 2 < nchunks) fetch((c + 2) * KC, setc);
+    if (do_mfma) {
+      const double* sa = lds + S * STAGE + 64 * wr + lr;
+      const double* sb = lds + S * STAGE + KC * LROW + lr;
+#pragma unroll
+      for (int s4 = 0; s4 < KC / 4; ++s4) {
+        const int kk = 4 * s4 + lk;
+        double a[4], b[NB];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = sa[kk * LROW + 16 * i];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) b[j] = sb[kk * LB + 16 * j];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (i < ni) {
+#pragma unroll
+            for (int j = 0; j < NB; ++j) acc[i][j] = MF<double>::op(b[j], a[i], acc[i][j]);
+          }
+        }
+      }
+    }
+    if (c + 1 < nchunks) stash(other);
+    __syncthreads();
+  };
+  for (int c = 0; c < nchunks; c += 2) {
+    step(c, S0{}, S1{});
+    if (c + 1 < nchunks) step(c + 1, S1{}, S0{});
+  }
+}
+
+// LDS of k_qform: the core's two stages, then Y ((T + 1) TB) and x0_I (T TB)
 template <int TB>
-__global__ __launch_bounds__(256, 2) void k_qform(Lay lay, const double* __restrict__ m64,
+constexpr int qform_lds_doubles() {
+  return std::max(2 * 16 * (LROW + TB + 4), (2 * T + 1) * TB);
+}
+
+template <int TB>
+__global__ __launch_bounds__(256, TB == 16 ? 3 : 2) void k_qform(Lay lay, const double* __restrict__ m64,
                                                   int64_t stride64, const double* __restrict__ X,
                                                   const double* __restrict__ rhs,
                                                   const int32_t* __restrict__ info,
                                                   double* __restrict__ slots, int refine,
                                                   int ntile, int G) {
-  __shared__ __attribute__((aligned(16))) char lds_raw[GEMM_LDS_BYTES];
-  double* lds = reinterpret_cast<double*>(lds_raw);
+  __shared__ __attribute__((aligned(16))) double lds[qform_lds_doubles<TB>()];
   const int wg = xcd_remap(blockIdx.x, G);
   const int k = wg / ntile;
   const int t = wg % ntile;
@@ -350,9 +448,8 @@ __global__ __launch_bounds__(256, 2) void k_qform(Lay lay, const double* __restr
     d4 acc[4][4];
     zero_acc<double>(acc);
     // B = x0_J has q <= TB rows: TB / 16 block columns
-    wg_gemm_nt<double, double, true, TB / 16>(acc, lds,
-                                              m64 + (int64_t)k * stride64 + lay.tile_off(I, J), T,
-                                              ri, Xk + (int64_t)J * T * TB, TB, q, rj, act, ni);
+    wg_gemm_rhs<TB / 16>(acc, lds, m64 + (int64_t)k * stride64 + lay.tile_off(I, J), T, ri,
+                         Xk + (int64_t)J * T * TB, TB, q, rj, act, ni);
     // the core ends with a barrier: the LDS stages are free for Y
     if (act) store64<double, false>(Ys + 64 * wr + 64 * wc * LY, LY, Ys + 64 * wr + 64 * wc * LY, LY,
                                     acc, war, wbr, lane);
@@ -411,8 +508,6 @@ __global__ __launch_bounds__(256, 2) void k_qform(Lay lay, const double* __restr
 hipError_t launch_qform(const Lay& lay, const double* m64, int64_t stride64, const double* X,
                         const double* rhs, const int32_t* info, double* slots, int refine, int K,
                         hipStream_t s) {
-  // Y and x0_I share the core's LDS block: (T + 1) TB + T TB doubles
-  static_assert((2 * T + 1) * 32 * (int)sizeof(double) <= GEMM_LDS_BYTES, "qform LDS");
   const int ntile = lay.Nv * (lay.Nv + 1) / 2;
   const int G = K * ntile;
   if (lay.TB == 16)
