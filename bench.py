@@ -326,8 +326,9 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(omega points shard across GPUs by design only)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(omega points would shard across GPUs; only the single-GPU share is built)",
+              file=sys.stderr)
         sys.exit(2)
     extras = [] if args.extras == "none" else [e for e in args.extras.split(",") if e]
     for e in extras:
