@@ -421,7 +421,11 @@ int pl_profile_loglik(const double* locs, const double* y, const double* X, int6
       }));
     }
     PL_CHECK(timed(PL_KC_OTHER, 0.0, s, [&] {
-      hipError_t e = launch_finalize(lay, mats, slots, logdet, info, jac, yflags, lam_d, (int)n,
+      hipError_t e = hipSuccess;
+      if (mixed) e = launch_slot_reduce(lay, slots, dscr, (int64_t)T * T, kk, s);
+      if (e == hipSuccess)
+        e = launch_finalize(lay, mats, mixed ? dscr : nullptr, (int64_t)T * T, logdet, info, jac,
+                            yflags, lam_d, (int)n,
                                      (int)p, (int)M, kk, out + c0 * M,
                                      beta_hat ? beta_hat + c0 * M * p : nullptr,
                                      xvx_inv ? xvx_inv + c0 * p * p : nullptr, s);

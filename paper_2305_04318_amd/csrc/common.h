@@ -108,8 +108,13 @@ hipError_t launch_boxcox_rhs(const double* y, const double* X, const double* lam
                              hipStream_t s);
 hipError_t launch_border_init(const Lay& lay, double* mats, const double* rhs, int K,
                               hipStream_t s);
-hipError_t launch_finalize(const Lay& lay, const double* mats, const double* slots,
-                           const double* logdet, const int32_t* info, const double* jac,
+// mixed form: red[k red_stride + b TB + a] = -(1/2) sum over the omega's lower
+// tiles of the refined slots (a, b) + (b, a)
+hipError_t launch_slot_reduce(const Lay& lay, const double* slots, double* red,
+                              int64_t red_stride, int K, hipStream_t s);
+// sred: null (FP64: the Schur tile of the factor) or the reduced slots
+hipError_t launch_finalize(const Lay& lay, const double* mats, const double* sred,
+                           int64_t sred_stride, const double* logdet, const int32_t* info, const double* jac,
                            const int32_t* flags, const double* lam, int n, int p, int M, int K,
                            pl_result* out, double* beta, double* xvi, hipStream_t s);
 // mixed form

@@ -301,11 +301,40 @@ hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int n, hipStream_t 
   return hipGetLastError();
 }
 
+// ---- mixed form: the cross products from the refined slots ----------------------
+// red[b TB + a] = -(1/2) sum_t (slot_t[a][b] + slot_t[b][a]) over the omega's
+// lower tiles t, in tile order.  One workgroup per omega, one thread per
+// (a, b) pair: the tile loop is unrolled so that many loads are in flight
+// (one wave summing every pair in turn was bound by load latency).
+__global__ __launch_bounds__(256) void k_slot_reduce(const double* __restrict__ slots, int ntile,
+                                                     int TB, double* __restrict__ red,
+                                                     int64_t red_stride) {
+  const int k = blockIdx.x;
+  const int64_t tile = (int64_t)TB * TB;
+  const double* sk = slots + (int64_t)k * ntile * tile;
+  for (int pr = threadIdx.x; pr < TB * TB; pr += 256) {
+    const int a = pr / TB, b = pr % TB;
+    double v = 0.0;
+#pragma unroll 8
+    for (int t = 0; t < ntile; ++t) v += sk[t * tile + a * TB + b] + sk[t * tile + b * TB + a];
+    red[(int64_t)k * red_stride + b * TB + a] = -0.5 * v;
+  }
+}
+
+hipError_t launch_slot_reduce(const Lay& lay, const double* slots, double* red,
+                              int64_t red_stride, int K, hipStream_t s) {
+  const int ntile = lay.Nv * (lay.Nv + 1) / 2;
+  hipLaunchKernelGGL(k_slot_reduce, dim3(K), dim3(256), 0, s, slots, ntile, lay.TB, red,
+                     red_stride);
+  return hipGetLastError();
+}
+
 // ---- p x p stage (dev_finalize) -----------------------------------------------------
 // One wave per omega.  S: the Schur tile of the bordered FP64 factorisation, or
-// (mixed form) minus the symmetrised sum of the refined cross-product slots.
+// (mixed form, sred non-null) the reduced cross products of k_slot_reduce.
 __global__ __launch_bounds__(64) void k_finalize(Lay lay, const double* __restrict__ mats,
-                                                 const double* __restrict__ slots,
+                                                 const double* __restrict__ sred,
+                                                 int64_t sred_stride,
                                                  const double* __restrict__ logdet,
                                                  const int32_t* __restrict__ info,
                                                  const double* __restrict__ jac,
@@ -315,34 +344,22 @@ __global__ __launch_bounds__(64) void k_finalize(Lay lay, const double* __restri
                                                  double* __restrict__ beta,
                                                  double* __restrict__ xvi) {
   __shared__ double smem[FIN_SMEM_DOUBLES];
-  __shared__ double Sr[32 * 32];
   const int k = blockIdx.x;
-  const int tid = threadIdx.x;
   const int TB = lay.TB;
-  const double* S = mats + (int64_t)k * lay.mstride + lay.tile_off(lay.Nv, lay.Nv);
-  if (slots) {
-    const int ntile = lay.Nv * (lay.Nv + 1) / 2;
-    const double* sk = slots + (int64_t)k * ntile * TB * TB;
-    for (int pr = tid; pr < TB * TB; pr += 64) {
-      const int a = pr / TB, b = pr % TB;
-      double v = 0.0;
-      for (int t = 0; t < ntile; ++t)
-        v += sk[(int64_t)t * TB * TB + a * TB + b] + sk[(int64_t)t * TB * TB + b * TB + a];
-      Sr[b * TB + a] = -0.5 * v;
-    }
-    __syncthreads();
-    S = Sr;
-  }
+  const double* S = sred ? sred + (int64_t)k * sred_stride
+                         : mats + (int64_t)k * lay.mstride + lay.tile_off(lay.Nv, lay.Nv);
   dev_finalize(S, TB, logdet[k], info[k], jac[0], flags[0] != 0, lam, n, p, M,
                out + (int64_t)k * M, beta ? beta + (int64_t)k * M * p : nullptr,
                xvi ? xvi + (int64_t)k * p * p : nullptr, smem);
 }
 
-hipError_t launch_finalize(const Lay& lay, const double* mats, const double* slots,
+hipError_t launch_finalize(const Lay& lay, const double* mats, const double* sred,
+                           int64_t sred_stride,
                            const double* logdet, const int32_t* info, const double* jac,
                            const int32_t* flags, const double* lam, int n, int p, int M, int K,
                            pl_result* out, double* beta, double* xvi, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(K), dim3(64), 0, s, lay, mats, slots, logdet, info, jac,
+  hipLaunchKernelGGL(k_finalize, dim3(K), dim3(64), 0, s, lay, mats, sred, sred_stride, logdet,
+                     info, jac,
                      flags, lam, n, p, M, out, beta, xvi);
   return hipGetLastError();
 }
