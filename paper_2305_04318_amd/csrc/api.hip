@@ -396,8 +396,10 @@ int pl_profile_loglik(const double* locs, const double* y, const double* X, int6
           PL_CHECK(timed(PL_KC_TRSM, 0.0, s,
                          [&] { return launch_trsm(lay, mats, W, info, J, lay.Nv - J, kk, s); }));
         } else {
-          PL_CHECK(timed(PL_KC_GEMM, kk * gemm_col_flops(lay, J, 1), s,
-                         [&] { return launch_gemm_col(lay, mats, info, J, 1, kk, s); }));
+          PL_CHECK(timed(PL_KC_GEMM, kk * gemm_col_flops(lay, J, 1), s, [&] {
+            return lay.TB <= 32 ? launch_border_block(lay, mats, info, kk, s)
+                                : launch_gemm_col(lay, mats, info, J, 1, kk, s);
+          }));
         }
       }
     } else {

@@ -266,6 +266,86 @@ hipError_t launch_col_update(const Lay& lay, double* mats, const int32_t* info, 
   return hipGetLastError();
 }
 
+// ---- the bordered row's own block after the last block column ------------------
+// C_B -= Q Q^T: Q is the bordered rows' panel (q rows; the packed tiles
+// (Nv, 0..Nv-1) form one TB x Nv T column-major block, leading dimension TB)
+// over its n valid columns, C_B the final TB x TB tile (Step 4's cross
+// products).  A 16- or 32-row product with k = n gives one wave of a GEMM
+// workgroup almost all the MFMA work and a long, latency-bound chunk loop.
+// Here the four waves of a workgroup take interleaved groups of 4 U columns,
+// load their fragments straight from global memory (16 lanes read 16
+// consecutive rows of one column), use each fragment as both MFMA operands,
+// and sum their partial blocks through LDS in wave order.
+template <int NB>
+__global__ __launch_bounds__(256) void k_border_block(Lay lay, double* __restrict__ mats,
+                                                      const int32_t* __restrict__ info) {
+  constexpr int TBC = 16 * NB, U = NB == 1 ? 8 : 4;
+  __shared__ double part[4][TBC * TBC];
+  const int k = blockIdx.x;
+  if (info[k] != 0) return;  // uniform for the workgroup
+  double* base = mats + (int64_t)k * lay.mstride;
+  const double* Q = base + lay.tile_off(lay.Nv, 0);
+  double* C = base + lay.tile_off(lay.Nv, lay.Nv);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int n = lay.n, q = lay.q;
+  const int64_t ld = lay.TB;
+  d4 acc[NB][NB];
+#pragma unroll
+  for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < NB; ++jb) acc[ib][jb] = d4{0.0, 0.0, 0.0, 0.0};
+  const int ngroups = (n + 4 * U - 1) / (4 * U);
+  for (int g = wave; g < ngroups; g += 4) {
+    double v[U][NB];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int col = g * 4 * U + 4 * u + lk;
+      const int cc = col < n ? col : n - 1;
+#pragma unroll
+      for (int ib = 0; ib < NB; ++ib) {
+        const int row = 16 * ib + lr;
+        const int rc = row < q ? row : q - 1;  // clamped: always a valid element
+        v[u][ib] = Q[(int64_t)cc * ld + rc];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int col = g * 4 * U + 4 * u + lk;
+#pragma unroll
+      for (int ib = 0; ib < NB; ++ib)
+        if (col >= n || 16 * ib + lr >= q) v[u][ib] = 0.0;
+#pragma unroll
+      for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) acc[ib][jb] = MF<double>::op(v[u][jb], v[u][ib], acc[ib][jb]);
+    }
+  }
+#pragma unroll
+  for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        part[wave][(16 * jb + MF<double>::col(lk, e)) * TBC + 16 * ib + lr] = acc[ib][jb][e];
+  __syncthreads();
+  for (int idx = tid; idx < TBC * TBC; idx += 256) {
+    const int r = idx % TBC, c = idx / TBC;
+    if (r < q && c < q)
+      C[(int64_t)c * ld + r] -= ((part[0][idx] + part[1][idx]) + part[2][idx]) + part[3][idx];
+  }
+}
+
+hipError_t launch_border_block(const Lay& lay, double* mats, const int32_t* info, int K,
+                               hipStream_t s) {
+  if (lay.kind != 0 || lay.q <= 0 || lay.q > 32 || lay.n <= 0) return hipErrorInvalidValue;
+  if (lay.TB == 16)
+    hipLaunchKernelGGL(k_border_block<1>, dim3(K), dim3(256), 0, s, lay, mats, info);
+  else
+    hipLaunchKernelGGL(k_border_block<2>, dim3(K), dim3(256), 0, s, lay, mats, info);
+  return hipGetLastError();
+}
+
 // ---- panel solve L_IJ = C_IJ W_J^T for the nI tile rows below J -----------
 // TS double: W from Wbuf[k]; TS float: W from slot J of the omega's table.
 template <typename TS, bool VEC>

@@ -101,6 +101,9 @@ hipError_t launch_gemm_col(const Lay& lay, double* mats, const int32_t* info, in
                            int K, hipStream_t s);
 hipError_t launch_col_update(const Lay& lay, double* mats, const int32_t* info, int J, int K,
                              hipStream_t s);
+// the bordered row's own TB x TB block (TB <= 32) after the last block column
+hipError_t launch_border_block(const Lay& lay, double* mats, const int32_t* info, int K,
+                               hipStream_t s);
 hipError_t launch_fill(double* p, double v, int64_t count, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s);
 hipError_t launch_boxcox_rhs(const double* y, const double* X, const double* lam, int n,
