@@ -2,10 +2,15 @@
 // left-looking over block columns of width T, batched over omega.
 //
 // Step J of the factorisation:
-//   k_gemm_col : C_IJ -= L_I,0:J L_J,0:J^T for every tile row I >= J (MFMA)
-//   k_potrf    : C_JJ = L_JJ L_JJ^T, log|V| += 2 sum log L_jj,
-//                W_J = L_JJ^{-1} (triangular inverse), register-blocked, FP64
-//   k_trsm     : L_IJ = C_IJ W_J^T for I > J (MFMA)
+//   k_col_update : C_IJ -= L_I,0:J L_J,0:J^T for every tile row I >= J (MFMA);
+//                  the diagonal tile's workgroup also updates the bordered
+//                  row's tile (k_col_update_mx in the mixed form; k_gemm_col
+//                  for the plain layout and bordered heights above 32)
+//   k_potrf      : C_JJ = L_JJ L_JJ^T, log|V| += 2 sum log L_jj,
+//                  W_J = L_JJ^{-1} (triangular inverse), register-blocked, FP64
+//   k_trsm       : L_IJ = C_IJ W_J^T for I > J (MFMA)
+// and after the last block column k_border_block updates the bordered row's
+// own block.
 // With the packed bordered layout the right-hand sides are extra tile rows
 // under V, so the same steps produce Z = L^{-1}[Y'|X] (Step 3) and, in the
 // final tile, minus the cross products (y,X)^T V^{-1} (y,X) (Step 4).
