@@ -205,6 +205,51 @@ __device__ __forceinline__ void bs_rowdot(const float* Ls, const float* Xs, int 
   }
 }
 
+// Half of a tile (its 64 columns from col0) transposed into Ls (64 x (T+1));
+// rows c >= valid_rows read as zero.  G points at the tile.
+constexpr int HALF_PER = 64 * T / 4 / 256;
+__device__ __forceinline__ void stage_half_t(float* Ls, const float* __restrict__ G, int col0,
+                                             int valid_rows) {
+  float4 v[HALF_PER];
+#pragma unroll
+  for (int u = 0; u < HALF_PER; ++u)
+    v[u] = *reinterpret_cast<const float4*>(G + (int64_t)col0 * T + 4 * (threadIdx.x + 256 * u));
+#pragma unroll
+  for (int u = 0; u < HALF_PER; ++u) {
+    const int idx = 4 * (threadIdx.x + 256 * u), col = idx / T, row = idx % T;
+    float* dst = Ls + col * (T + 1) + row;
+    dst[0] = (row + 0 < valid_rows) ? v[u].x : 0.0f;
+    dst[1] = (row + 1 < valid_rows) ? v[u].y : 0.0f;
+    dst[2] = (row + 2 < valid_rows) ? v[u].z : 0.0f;
+    dst[3] = (row + 3 < valid_rows) ? v[u].w : 0.0f;
+  }
+}
+
+// out[m] = sum_c Ls[r][c] Xs[c][q NC + m] over c < rows (NC = TB / 4): the
+// quarter-width form of bs_rowdot for a half-tile stage, same order of sums
+template <int TB>
+__device__ __forceinline__ void bs_rowdot4(const float* Ls, const float* Xs, int r, int q,
+                                           int rows, float (&out)[TB / 4]) {
+  constexpr int NC = TB / 4;
+  const float* lrow = Ls + r * (T + 1);
+  const float* xcol = Xs + q * NC;
+#pragma unroll
+  for (int m = 0; m < NC; ++m) out[m] = 0.0f;
+#pragma unroll 4
+  for (int c = 0; c < rows; ++c) {
+    const float l = lrow[c];
+    const float4* xv = reinterpret_cast<const float4*>(xcol + c * TB);
+#pragma unroll
+    for (int m4 = 0; m4 < NC / 4; ++m4) {
+      const float4 x = xv[m4];
+      out[4 * m4 + 0] += l * x.x;
+      out[4 * m4 + 1] += l * x.y;
+      out[4 * m4 + 2] += l * x.z;
+      out[4 * m4 + 3] += l * x.w;
+    }
+  }
+}
+
 template <int TB>
 __global__ __launch_bounds__(256) void k_bs_diag(Lay lay, const float* __restrict__ W32,
                                                  const int32_t* __restrict__ info,
@@ -230,44 +275,55 @@ __global__ __launch_bounds__(256) void k_bs_diag(Lay lay, const float* __restric
   }
 }
 
+// x_J -= L_IJ^T x_I for one (omega, J < I).  The tile is staged one half
+// (64 of its columns) at a time, so that the LDS block (64 (T+1) + T TB floats)
+// lets three workgroups share a compute unit; thread (r, q) produces row
+// 64 half + r of x_J for a quarter of the right-hand sides.
 template <int TB>
 __global__ __launch_bounds__(256) void k_bs_update(Lay lay, const float* __restrict__ m32,
                                                    const int32_t* __restrict__ info,
                                                    double* __restrict__ X, int I) {
   extern __shared__ __attribute__((aligned(16))) float bsm[];
   float* Ls = bsm;
-  float* Xs = bsm + T * (T + 1);
-  constexpr int NC = TB / 2;
+  float* Xs = bsm + 64 * (T + 1);  // 64 (T + 1) = 8256 floats: 16-byte aligned
+  constexpr int NC = TB / 4;
   const int k = blockIdx.x / I;
   const int J = blockIdx.x % I;
   if (info[k] != 0) return;
-  const int tid = threadIdx.x, r = tid & (T - 1), h = tid >> 7;
+  const int tid = threadIdx.x, r = tid & 63, q = tid >> 6;
   const int ri = lay.rows(I);
   const double* Xi = X + (int64_t)k * lay.n * TB + (int64_t)I * T * TB;
   double* Xj = X + (int64_t)k * lay.n * TB + (int64_t)J * T * TB;
   // tile (I, J): rows in block I (the contraction index), columns in block J
-  stage_tile_t(Ls, m32 + (int64_t)k * lay.mstride + lay.tile_off(I, J), ri);
+  const float* G = m32 + (int64_t)k * lay.mstride + lay.tile_off(I, J);
   stage_rhs<TB>(Xs, Xi, ri);
-  __syncthreads();
-  float out[NC];
-  bs_rowdot<TB>(Ls, Xs, r, h, ri, out);
-  // tile row J < I is complete (T rows)
-  double* dst = Xj + r * TB + h * NC;
-  double cur[NC];
+#pragma unroll 1
+  for (int half = 0; half < 2; ++half) {
+    stage_half_t(Ls, G, 64 * half, ri);
+    __syncthreads();
+    float out[NC];
+    bs_rowdot4<TB>(Ls, Xs, r, q, ri, out);
+    // tile row J < I is complete (T rows)
+    double* dst = Xj + (64 * half + r) * TB + q * NC;
+    double cur[NC];
 #pragma unroll
-  for (int m = 0; m < NC; ++m) cur[m] = dst[m];
+    for (int m = 0; m < NC; ++m) cur[m] = dst[m];
 #pragma unroll
-  for (int m = 0; m < NC; ++m) dst[m] = cur[m] - (double)out[m];
+    for (int m = 0; m < NC; ++m) dst[m] = cur[m] - (double)out[m];
+    __syncthreads();  // Ls is restaged for the second half
+  }
 }
 
 template <int TB>
 static void backsolve_sweep(const Lay& lay, const float* m32, const float* W32, const int32_t* info,
                             double* X, int K, hipStream_t s) {
   const size_t lds = (size_t)(T * (T + 1) + T * TB) * sizeof(float);
+  const size_t lds_half = (size_t)(64 * (T + 1) + T * TB) * sizeof(float);
   for (int I = lay.Nv - 1; I >= 0; --I) {
     hipLaunchKernelGGL(k_bs_diag<TB>, dim3(K), dim3(256), lds, s, lay, W32, info, X, I);
     if (I > 0)
-      hipLaunchKernelGGL(k_bs_update<TB>, dim3(K * I), dim3(256), lds, s, lay, m32, info, X, I);
+      hipLaunchKernelGGL(k_bs_update<TB>, dim3(K * I), dim3(256), lds_half, s, lay, m32, info, X,
+                         I);
   }
 }
 
