@@ -10,8 +10,12 @@
 // piece, so the pieces converge geometrically (NC = 10 terms on PB = 4
 // pieces match the quadrature to its own accuracy, ~2.6e-13 absolute in rho).
 // V needs absolute accuracy, so rho itself is tabulated rather than log rho
-// (which would cost an exp per element): a matrix element costs its binary
-// exponent and mantissa and a Clenshaw sum -- no square root, logarithm or
+// (which would cost an exp per element).  Each piece's Chebyshev interpolant
+// is stored as power-basis coefficients in the piece's local variable
+// s in [-1, 1] (its coefficients decay geometrically, so the conversion adds
+// only rounding of the order of the leading terms): a matrix element costs
+// its binary exponent and mantissa and a 10-term Horner sum (9 FMAs, against
+// 18 operations for a Clenshaw sum) -- no square root, logarithm or
 // exponential.  The node values come from a trapezoid-rule evaluation of
 // K_kappa(x) = int_0^inf exp(-x cosh t) cosh(kappa t) dt (DLMF 10.32.9),
 // which converges geometrically for this analytic, doubly exponentially
@@ -51,12 +55,49 @@ __global__ void k_cheb_coeffs(const double* __restrict__ nodes, double* __restri
   tables[idx] = acc;
 }
 
+// Chebyshev coefficients c_0 .. c_{NC-1} of one piece (c_0 already halved)
+// -> power-basis coefficients a_j of sum_m c_m T_m(s), in place, through the
+// integer coefficients of T_m (T_{m+1} = 2 s T_m - T_{m-1}).
+__global__ void k_cheb_mono(double* __restrict__ tables, int K) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)K * NPIECE) return;
+  double* c = tables + idx * NC;
+  double cm[NC], a[NC], t0[NC], t1[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    cm[j] = c[j];
+    t0[j] = t1[j] = 0.0;
+  }
+  t0[0] = 1.0;  // T_0
+  t1[1] = 1.0;  // T_1
+#pragma unroll
+  for (int j = 0; j < NC; ++j) a[j] = cm[0] * t0[j] + cm[1] * t1[j];
+#pragma unroll
+  for (int m = 2; m < NC; ++m) {
+    double t2[NC];
+    t2[0] = -t0[0];
+#pragma unroll
+    for (int j = 1; j < NC; ++j) t2[j] = 2.0 * t1[j - 1] - t0[j];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      a[j] = fma(cm[m], t2[j], a[j]);
+      t0[j] = t1[j];
+      t1[j] = t2[j];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NC; ++j) c[j] = a[j];
+}
+
 hipError_t launch_cheb_tables(const MaternParams* mp, double* nodes, double* tables, int K,
                               hipStream_t s) {
   const int64_t total = (int64_t)K * TABLE;
   const int blocks = (int)((total + 255) / 256);
   hipLaunchKernelGGL(k_cheb_nodes, dim3(blocks), dim3(256), 0, s, mp, nodes, K);
   hipLaunchKernelGGL(k_cheb_coeffs, dim3(blocks), dim3(256), 0, s, nodes, tables, K);
+  const int64_t pieces = (int64_t)K * NPIECE;
+  hipLaunchKernelGGL(k_cheb_mono, dim3((unsigned)((pieces + 255) / 256)), dim3(256), 0, s, tables,
+                     K);
   return hipGetLastError();
 }
 

@@ -42,9 +42,10 @@ static __device__ double g_direct(const MaternParams& P, double w) {
 }
 
 // rho for one element given d^2 (the squared anisotropic distance) and the
-// omega's table (TABLE doubles, Chebyshev coefficients of rho itself).  The
-// piece comes from the binary exponent and mantissa of w = 8 kappa d^2 (no
-// logarithm), the value from a Clenshaw sum clamped to [0, 1] (no exp).
+// omega's table (TABLE doubles: per piece, the power-basis coefficients of the
+// Chebyshev interpolant of rho itself in the local variable s).  The piece
+// comes from the binary exponent and mantissa of w = 8 kappa d^2 (no
+// logarithm), the value from a Horner sum clamped to [0, 1] (no exp).
 __device__ __forceinline__ double rho_eval(const MaternParams& P, const double* tab, double d2) {
   const double w = P.k8 * d2;
   if (w == 0.0) return 1.0;
@@ -60,16 +61,10 @@ __device__ __forceinline__ double rho_eval(const MaternParams& P, const double* 
   // table read in bounds for any input (a NaN coordinate included)
   piece = piece < 0 ? 0 : (piece >= NPIECE ? NPIECE - 1 : piece);
   const double s = 2.0 * (t - (double)j) - 1.0;
-  const double s2 = s + s;
-  const double* c = tab + piece * NC;
-  double b1 = 0.0, b2 = 0.0;
+  const double* a = tab + piece * NC;  // power-basis coefficients in s
+  double r = a[NC - 1];
 #pragma unroll
-  for (int mm = NC - 1; mm >= 1; --mm) {
-    const double tmp = fma(s2, b1, c[mm] - b2);
-    b2 = b1;
-    b1 = tmp;
-  }
-  const double r = fma(s, b1, c[0] - b2);
+  for (int mm = NC - 2; mm >= 0; --mm) r = fma(r, s, a[mm]);
   return fmin(fmax(r, 0.0), 1.0);
 }
 
