@@ -82,11 +82,14 @@ __device__ __forceinline__ typename Piece<TS>::type fetch_piece(const TS* __rest
 constexpr int LROW = T + 4;         // LDS stride per k column (elements)
 constexpr int GEMM_LDS_BYTES = 2 * 2 * 16 * LROW * 8;
 
-template <typename TS, typename TC, bool VEC, int NJ = 4, int DEPTH = 2>
+// KSTOP: a wave multiplies only the chunks below kstop (it still loads and
+// stages every chunk for the others); the panel solve's first wave column
+// needs no products past its columns, where W^T is zero.
+template <typename TS, typename TC, bool VEC, int NJ = 4, int DEPTH = 2, bool KSTOP = false>
 __device__ __forceinline__ void wg_gemm_nt(typename MF<TC>::acc (&acc)[4][4], TS* lds,
                                            const TS* __restrict__ A, int64_t lda, int arows,
                                            const TS* __restrict__ B, int64_t ldb, int brows,
-                                           int kmax, bool do_mfma, int ni) {
+                                           int kmax, bool do_mfma, int ni, int kstop = 0) {
   constexpr int N = Piece<TS>::N;
   constexpr int KC = 128 / (int)sizeof(TS);
   constexpr int PPC = T / N;  // pieces per column
@@ -189,10 +192,11 @@ __device__ __forceinline__ void wg_gemm_nt(typename MF<TC>::acc (&acc)[4][4], TS
   const int lr = lane & 15, lk = lane >> 4;
   // chunk c (even: set/stage 0, odd: 1): fetch c + 2 into its own set, run
   // its MFMAs from LDS stage c & 1, then move chunk c + 1 to the other stage
+  if constexpr (KSTOP) kstop = __builtin_amdgcn_readfirstlane(kstop);
   auto step = [&](int c, auto setc, auto other) {
     constexpr int S = decltype(setc)::value;
     if (c + 2 < nchunks) fetch((c + 2) * KC, setc);
-    if (do_mfma) {
+    if (do_mfma && (!KSTOP || c * KC < kstop)) {
       const TS* sa = lds + (S * 2 + 0) * KC * LROW + 64 * wr + lr;
       const TS* sb = lds + (S * 2 + 1) * KC * LROW + 64 * wc + lr;
 #pragma unroll
@@ -482,7 +486,10 @@ __device__ __forceinline__ void dev_trsm(const Lay& lay, TS* base, const TS* W, 
   zero_acc<double>(acc);
   // the core's final barrier orders every read of C_IJ before the overwrite
   if constexpr (sizeof(TS) == 8) {
-    wg_gemm_nt<TS, TS, VEC, 4, DEPTH>(acc, lds, Ct, ldc, arows, W, T, brows, brows, act, ni);
+    // W is lower triangular: output columns 64 wc .. 64 wc + 63 need k < 64 (wc + 1)
+    // (two-set pipeline only: the persistent batch kernel keeps its code)
+    wg_gemm_nt<TS, TS, VEC, 4, DEPTH, (DEPTH > 1)>(acc, lds, Ct, ldc, arows, W, T, brows, brows,
+                                                   act, ni, DEPTH > 1 ? 64 * (wc + 1) : 0);
     if (act) store64<double, false>(Co, ldc, Co, ldc, acc, war, wbr, lane);
   } else {
     wg_gemm_nt_f32x64<FLUSH>(acc, lds, Ct, ldc, arows, W, T, brows, brows, act, ni);
