@@ -229,13 +229,15 @@ __device__ __forceinline__ void wg_gemm_nt(typename MF<TC>::acc (&acc)[4][4], TS
 // FP32 MFMA whose partial sums are flushed into FP64 accumulators every
 // FLUSH k-steps (FLUSH * 4 products): the FP32 rounding then only touches short
 // partial sums instead of the long running sums that cancel in the Schur
-// complements of an ill-conditioned V.  Same LDS pipeline as wg_gemm_nt.
-template <int FLUSH>
+// complements of an ill-conditioned V.  Same LDS pipeline as wg_gemm_nt,
+// and the same KSTOP (skipped chunks leave the pending partials untouched; the
+// final fold adds them).
+template <int FLUSH, bool KSTOP = false>
 __device__ __forceinline__ void wg_gemm_nt_f32x64(d4 (&acc)[4][4], float* lds,
                                                   const float* __restrict__ A, int64_t lda,
                                                   int arows, const float* __restrict__ B,
                                                   int64_t ldb, int brows, int kmax, bool do_mfma,
-                                                  int ni) {
+                                                  int ni, int kstop = 0) {
   constexpr int N = 4;
   constexpr int KC = 32;
   constexpr int PPC = T / N;
@@ -276,10 +278,11 @@ __device__ __forceinline__ void wg_gemm_nt_f32x64(d4 (&acc)[4][4], float* lds,
   f4 pp[4];  // FP32 partials of the block row that is folded in next
 #pragma unroll
   for (int j = 0; j < 4; ++j) pp[j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  if constexpr (KSTOP) kstop = __builtin_amdgcn_readfirstlane(kstop);
   for (int c = 0; c < nchunks; ++c) {
     const bool more = c + 1 < nchunks;
     if (more) fetch((c + 1) * KC);
-    if (do_mfma) {
+    if (do_mfma && (!KSTOP || c * KC < kstop)) {
       const float* sa = lds + ((c & 1) * 2 + 0) * KC * LROW + 64 * wr + lr;
       const float* sb = lds + ((c & 1) * 2 + 1) * KC * LROW + 64 * wc + lr;
       // rolled: only one group's fragments and partial sums are live at a time
@@ -492,7 +495,8 @@ __device__ __forceinline__ void dev_trsm(const Lay& lay, TS* base, const TS* W, 
                                                    act, ni, DEPTH > 1 ? 64 * (wc + 1) : 0);
     if (act) store64<double, false>(Co, ldc, Co, ldc, acc, war, wbr, lane);
   } else {
-    wg_gemm_nt_f32x64<FLUSH>(acc, lds, Ct, ldc, arows, W, T, brows, brows, act, ni);
+    wg_gemm_nt_f32x64<FLUSH, true>(acc, lds, Ct, ldc, arows, W, T, brows, brows, act, ni,
+                                   64 * (wc + 1));
     if (act) store64_l<float, false>(Co, ldc, Co, ldc, acc, war, wbr, lane);
   }
 }
