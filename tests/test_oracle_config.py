@@ -42,6 +42,66 @@ def test_central_hessian_exact_on_polynomials():
     assert abs(H[1, 2]) < 1e-8
 
 
+def _internal_by_hand(om_row, shape_transform):
+    """The internal parameters written out from the definitions of Section 3.3
+    (independent of oracle.mle): gamma1 = log phi_X + log phi_Y, kappa~, nu =
+    sqrt(nu^2), gamma2/3 = sqrt(phi_X/phi_Y - 1) (cos, sin)(2 phi_A)."""
+    phi_x, kappa, nug, ratio, ang = om_row
+    phi_y = phi_x / ratio
+    r = math.sqrt(max(ratio - 1.0, 0.0))
+    ks = math.log(kappa) if shape_transform == 0 else 1.0 / math.sqrt(kappa)
+    return np.array([math.log(phi_x) + math.log(phi_y), ks, math.sqrt(nug),
+                     r * math.cos(2 * ang), r * math.sin(2 * ang)])
+
+
+@pytest.mark.parametrize("fix_shape,shape_transform,nu_hat",
+                         [(False, 0, 0.6), (True, 1, 0.6), (False, 1, 0.03)])
+def test_hessian_wiring_on_a_known_quadratic(monkeypatch, fix_shape, shape_transform, nu_hat):
+    # hessian_at's wiring -- which internal coordinates it perturbs and in
+    # which order, the |nu| rule of a stencil point, the held shape and the
+    # lambda-hat +- delta columns -- against a likelihood that is an exact
+    # quadratic in the internal parameters and lambda (central differences
+    # are exact on it).  The quadratic depends on nu only through nu^2, so a
+    # stencil point nu - delta < 0 (third case) must give the same value as
+    # |nu - delta|: the rule that the point's nugget is (nu - delta)^2.
+    rng = np.random.default_rng(11)
+    d_all = 5
+    A = rng.standard_normal((d_all, d_all))
+    A = A @ A.T + d_all * np.eye(d_all)
+    A[2, :] = A[:, 2] = 0.0
+    A[2, 2] = 3.0                      # nu enters as a nu^2 term only
+    omega_hat = np.array([1.3, 2.2, nu_hat ** 2, 2.5, 0.4])
+    c = _internal_by_hand(omega_hat, shape_transform) + 0.05 * rng.standard_normal(d_all)
+    c[2] = 0.0
+    b_lam, lam0, cross = 4.0, 0.3, 0.7
+    lam_hat, delta = 0.45, 0.05
+
+    def fake_loglik(locs, y, X, omega, lam):
+        omega = np.atleast_2d(omega)
+        lam = np.asarray(lam, dtype=np.float64)
+        ll = np.empty((omega.shape[0], lam.shape[0]))
+        for k, row in enumerate(omega):
+            assert row[2] >= 0.0                  # a stencil point never has a negative nugget
+            if fix_shape:
+                assert row[1] == omega_hat[1]     # the held shape exactly
+            w = _internal_by_hand(row, shape_transform) - c
+            q = -0.5 * w @ A @ w
+            for m, l in enumerate(lam):
+                ll[k, m] = q - b_lam * (l - lam0) ** 2 + cross * (l - lam0) * w[0]
+        return {"loglik": ll}
+
+    monkeypatch.setattr(oc, "profile_loglik", fake_loglik)
+    H, curv, l0, rows = oc.hessian_at(None, None, None, omega_hat, lam_hat, shape_transform,
+                                      fix_shape, delta)
+    idx = oc.free_coords(fix_shape)
+    np.testing.assert_allclose(H, -A[np.ix_(idx, idx)], rtol=0, atol=1e-7 * np.abs(A).max())
+    assert abs(curv - (-2.0 * b_lam)) < 1e-7
+    w0 = _internal_by_hand(omega_hat, shape_transform) - c
+    assert abs(l0 - (-0.5 * w0 @ A @ w0 - b_lam * (lam_hat - lam0) ** 2
+                     + cross * (lam_hat - lam0) * w0[0])) < 1e-12
+    assert rows.shape[0] == oc.stencil(len(idx)).shape[0]
+
+
 def test_chisq_quantiles_textbook():
     # printed tables: chi^2_5 upper 5% 11.070, 1% 15.086; chi^2_4 upper 5%
     # 9.488; chi^2_1 upper 5% 3.841 (= 1.95996^2); chi^2_2 upper a = -2 log a

@@ -182,7 +182,7 @@ def test_parameter_conventions_from_paper_tables():
     # rounding of the printed ratio: phi_Y = phi_X / phi_R, which aniso_ranges encodes.
     # The printed tau equals sigma * sqrt(nu^2): nu^2 is the nugget relative to sigma^2,
     # as in V = R + nu^2 I.
-    for name, (rng_, comb, ratio, sigma, nug, tau) in _golden().items():
+    for name, (rng_, comb, ratio, sigma, nug, tau, *_angle_gammas) in _golden().items():
         lo = hi = None
         for r in (ratio - 0.005, ratio + 0.005):
             phi_x, phi_y = oracle.aniso_ranges([rng_, 1.0, nug, r, 0.0])

@@ -32,12 +32,66 @@ def _random_omega(rng, K):
 def test_combined_range_matches_paper_table():
     # Section 3.3: exp(gamma1 / 2) is the combined range sqrt(phi_X phi_Y);
     # the paper's tables print range, ratio and combined range side by side
-    for name, (rng_x, combined, ratio, _sigma, nugget, _tau) in _golden().items():
+    for name, (rng_x, combined, ratio, _sigma, nugget, _tau, *_angle_gammas) in _golden().items():
         w = om.to_internal([[rng_x, 1.0, nugget, ratio, 0.3]])[0]
         assert abs(math.exp(w[0] / 2.0) - combined) <= 0.006 * combined, name
         # gamma2^2 + gamma3^2 = phi_X/phi_Y - 1 and nu = sqrt(nu^2)
         assert abs(w[3] ** 2 + w[4] ** 2 - (ratio - 1.0)) < 1e-12 * ratio
         assert abs(w[2] - math.sqrt(nugget)) < 1e-15
+
+
+def _printed_interval(v, digits=2):
+    h = 0.5 * 10.0 ** -digits
+    return v - h, v + h
+
+
+def _gamma_range(ratio, angle, which):
+    """Range of gamma2 (which 3) or gamma3 (which 4) of to_internal over the
+    rounding box of the printed ratio and angle (a fine grid of the box; the
+    functions are smooth there)."""
+    vals = []
+    for r in np.linspace(*_printed_interval(ratio), 21):
+        for a in np.linspace(*_printed_interval(angle), 21):
+            vals.append(om.to_internal([[1.0, 1.0, 0.1, r, a]])[0][which])
+    return min(vals), max(vals)
+
+
+def test_gammas_match_paper_tables():
+    # Section 3.3 "Reparameterization": the Swiss and soil tables print the
+    # anisotropy ratio, the angle and the internal parameters aniso1 (gamma2)
+    # and aniso2 (gamma3) of the same fit.  The printed gammas must lie in the
+    # range that the printed (ratio, angle), within their rounding, give.
+    # Swiss (angle 0.65) has |gamma2| << |gamma3|, soil (angle -0.82) a
+    # negative gamma3: a gamma2/gamma3 swap, a sign slip in the angle or a
+    # missing factor 2 fails one of them.
+    for name, row in _golden().items():
+        ratio, angle, g2, g3 = row[2], row[6], row[7], row[8]
+        for which, printed in ((3, g2), (4, g3)):
+            lo, hi = _gamma_range(ratio, angle, which)
+            plo, phi = _printed_interval(printed)
+            assert lo <= phi and plo <= hi, (name, which, lo, hi, printed)
+
+
+def test_gamma_pin_rejects_plausible_mistakes():
+    # the check above is sharp enough to see the mistakes it is meant to catch:
+    # each variant of the definition misses at least one printed value
+    variants = {
+        "swapped": lambda r, a: (math.sqrt(r - 1) * math.sin(2 * a), math.sqrt(r - 1) * math.cos(2 * a)),
+        "angle sign": lambda r, a: (math.sqrt(r - 1) * math.cos(-2 * a), math.sqrt(r - 1) * math.sin(-2 * a)),
+        "no factor 2": lambda r, a: (math.sqrt(r - 1) * math.cos(a), math.sqrt(r - 1) * math.sin(a)),
+        "ratio not - 1": lambda r, a: (math.sqrt(r) * math.cos(2 * a), math.sqrt(r) * math.sin(2 * a)),
+    }
+    for label, f in variants.items():
+        missed = False
+        for name, row in _golden().items():
+            ratio, angle, g2, g3 = row[2], row[6], row[7], row[8]
+            for idx, printed in ((0, g2), (1, g3)):
+                vals = [f(r, a)[idx] for r in np.linspace(*_printed_interval(ratio), 21)
+                        for a in np.linspace(*_printed_interval(angle), 21)]
+                plo, phi = _printed_interval(printed)
+                if not (min(vals) <= phi and plo <= max(vals)):
+                    missed = True
+        assert missed, label
 
 
 def test_isotropic_model_is_the_origin():
