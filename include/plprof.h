@@ -86,8 +86,14 @@ typedef struct pl_opts {
                            in FP32 before each FP64 fold in the off-diagonal
                            updates: 1, 2 or 4; 0 = default (4).  Longer runs are
                            faster and less accurate; see pl_autotune            */
-  int32_t reserved[2];
+  int32_t wait_us;      /* pl_batch_create: wall-time limit of one task wait of
+                           the persistent launch, microseconds; 0 = default
+                           (PL_BATCH_WAIT_US).  A wait that outlives it makes
+                           the launch drain without results (pl_batch_error)  */
+  int32_t reserved;
 } pl_opts;
+
+#define PL_BATCH_WAIT_US 4000000  /* 4 s: far above any legitimate task wait */
 
 /* pl_opts.flags */
 #define PL_OPT_NO_FALLBACK 1  /* PL_MIXED: do not synchronise to redo FP32
@@ -491,8 +497,10 @@ int pl_batch_stats(const pl_batch* plan, int64_t* units, int64_t* tasks, int64_t
  */
 int pl_batch_run(pl_batch* plan, pl_result* out, double* beta_hat, void* work, size_t work_bytes,
                  void* stream);
-/* After the stream has been synchronised: *err = 1 if a task wait exceeded
- * its bound (the results are then not valid), else 0.  Synchronous. */
+/* After the stream has been synchronised: *err = 1 if a task wait outlived
+ * its wall-time limit (opts->wait_us of pl_batch_create); every later wait
+ * then returned at once and every later task skipped its work, so the launch
+ * ended, but its results are not valid.  Else 0.  Synchronous. */
 int pl_batch_error(const pl_batch* plan, void* work, int32_t* err);
 void pl_batch_destroy(pl_batch* plan);
 

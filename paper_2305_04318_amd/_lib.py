@@ -35,7 +35,8 @@ class PlResult(ctypes.Structure):
 class PlOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("refine", ctypes.c_int32),
                 ("chunk", ctypes.c_int64), ("flags", ctypes.c_int32),
-                ("flush", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("flush", ctypes.c_int32), ("wait_us", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 PL_OPT_NO_FALLBACK = 1

@@ -15,7 +15,7 @@ class Batch:
     """A plan over many datasets; run() evaluates every (dataset, omega, lambda)
     record with one graph launch (a persistent kernel plus small prologue)."""
 
-    def __init__(self, problems, lam, device="cuda", max_slabs=0, inputs=None):
+    def __init__(self, problems, lam, device="cuda", max_slabs=0, inputs=None, wait_us=0):
         lib = load()
         self.device = device
         self.inputs = inputs if inputs is not None else [
@@ -33,6 +33,7 @@ class Batch:
                                om.ctypes.data, om.shape[0])
         self._arr = arr
         o = _opts("fp64", max_slabs)
+        o.wait_us = int(wait_us)  # limit of one task wait (0: the library's default)
         h = ctypes.c_void_p()
         check(lib.pl_batch_create(arr, D, self.p, self.lam.ctypes.data_as(ctypes.c_void_p),
                                   self.lam.shape[0], ctypes.byref(o), ctypes.byref(h)),

@@ -11,9 +11,10 @@
 // runs the task and counts it done.  A task popped earlier is held by a
 // running workgroup whose own dependencies were listed earlier still, so the
 // queue drains.  Units recycle a pool of matrix slabs: a unit's first phase
-// also waits for the previous user of its slab.  Waits are bounded; a wait
-// that exceeds the bound sets an error flag after which every wait returns,
-// so the kernel always terminates.
+// also waits for the previous user of its slab.  Every wait is bounded by wall
+// time (the device's constant-rate counter): a wait that outlives its limit
+// sets an error flag, after which every wait returns at once and every task
+// skips its work, so the kernel always drains and terminates.
 //
 // The launch sequence (counter resets, omega tables, Box-Cox right-hand
 // sides, the persistent kernel) is captured once into a HIP graph and replayed.
@@ -80,17 +81,23 @@ struct BatchArgs {
   int32_t p, M, q, TB;
   pl_result* out;
   double* beta;
+  int64_t wait_ticks;  // limit of one wait, in ticks of the constant-rate counter
 };
 
-constexpr long SPIN_LIMIT = 1L << 26;  // ~ seconds of s_sleep before giving up
-
-__device__ __forceinline__ void wait_ge(int32_t* ctr, int32_t v, int32_t* err) {
-  for (long it = 0; it < SPIN_LIMIT; ++it) {
-    if (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= v) return;
-    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+// Waits until *ctr >= v.  Gives up when the error flag is set, or when the
+// wait has lasted wait_ticks of wall time (it then sets the flag).  Returns
+// whether the count was reached.
+__device__ __forceinline__ bool wait_ge(int32_t* ctr, int32_t v, int32_t* err, int64_t wait_ticks) {
+  const int64_t t0 = wall_clock64();
+  for (;;) {
+    if (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= v) return true;
+    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    if (wall_clock64() - t0 > wait_ticks) {
+      __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
     __builtin_amdgcn_s_sleep(2);
   }
-  __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ Lay unit_lay(const BDataset& d, int Nv, int q, int TB) {
@@ -109,7 +116,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_persistent(BatchArgs a) {
   static_assert((TABLE + 2 * T) * 8 <= GEMM_LDS_BYTES, "covariance task staging");
   static_assert(POTRF_SMEM_DOUBLES * 8 <= GEMM_LDS_BYTES, "factorisation task staging");
   static_assert(FIN_SMEM_DOUBLES * 8 <= GEMM_LDS_BYTES, "finalize task staging");
-  __shared__ int32_t s_task;
+  __shared__ int32_t s_task, s_ok;
   double* smem = reinterpret_cast<double*>(smem_raw);
   for (;;) {
     if (threadIdx.x == 0) s_task = atomicAdd(a.head, 1);
@@ -119,17 +126,20 @@ __global__ __launch_bounds__(256, 2) void k_batch_persistent(BatchArgs a) {
     const BTask tk = a.tasks[t];
     const BUnit u = a.units[tk.unit];
     if (threadIdx.x == 0) {
-      wait_ge(a.done + tk.unit, tk.wait, a.err);
-      if (tk.first && u.pred >= 0) wait_ge(a.done + u.pred, u.pred_total, a.err);
+      bool ok = wait_ge(a.done + tk.unit, tk.wait, a.err, a.wait_ticks);
+      if (ok && tk.first && u.pred >= 0) ok = wait_ge(a.done + u.pred, u.pred_total, a.err, a.wait_ticks);
       __threadfence();  // acquire: the unit's earlier tasks' stores are visible
+      s_ok = ok ? 1 : 0;
     }
     __syncthreads();
+    // after a wait gave up (here or anywhere) the task only counts itself done
+    const bool run = s_ok != 0;
     const BDataset d = a.ds[u.d];
     const Lay lay = unit_lay(d, u.Nv, a.q, a.TB);
     double* base = a.slabs + (int64_t)u.slab * a.slab_stride;
     double* W = base + a.w_off;
     const bool failed = a.info[tk.unit] != 0;
-    switch (tk.type) {
+    if (run) switch (tk.type) {
       case TK_BORDER: {
         const int64_t nrhs = (int64_t)d.n * a.TB;
         const double* rhs = a.rhs + d.rhs_off;
@@ -232,6 +242,7 @@ struct pl_batch {
   std::vector<MaternParams> params;
   std::vector<double> lam;
   int32_t p = 0, M = 0, q = 0, TB = 0;
+  int32_t wait_us = 0;  // limit of one task wait
   int64_t n_omega = 0, nslabs = 0, slab_stride = 0, w_off = 0;
   // workspace layout (bytes)
   size_t off_tasks, off_units, off_ds, off_mp, off_nodes, off_tables, off_lam, off_rhs, off_jac,
@@ -314,7 +325,7 @@ int pl_batch_create(const pl_dataset* datasets, int64_t D, int64_t p, const doub
   if (M < 1 || M > PL_MAX_M) return -5;
   for (int64_t m = 0; m < M; ++m)
     if (!std::isfinite(lambda[m])) return -4;
-  if (opts && (opts->precision != PL_FP64 || opts->chunk < 0)) return -6;
+  if (opts && (opts->precision != PL_FP64 || opts->chunk < 0 || opts->wait_us < 0)) return -6;
   if (!plan) return -7;
   pl_batch* b = new pl_batch();
   b->p = (int32_t)p;
@@ -322,11 +333,13 @@ int pl_batch_create(const pl_dataset* datasets, int64_t D, int64_t p, const doub
   b->q = (int32_t)(M + p);
   b->TB = (int32_t)((b->q + 15) / 16 * 16);
   b->lam.assign(lambda, lambda + M);
+  b->wait_us = (opts && opts->wait_us > 0) ? opts->wait_us : PL_BATCH_WAIT_US;
   int64_t rhs_off = 0, om = 0;
   int maxNv = 0;
   for (int64_t d = 0; d < D; ++d) {
     const pl_dataset& s = datasets[d];
-    if (!s.locs || !s.y || !s.X || s.n < 2 || s.n <= p || s.n > 65535 * T || !s.omega ||
+    // tile indices are int16_t in the task list: at most 32767 tile rows
+    if (!s.locs || !s.y || !s.X || s.n < 2 || s.n <= p || s.n > (int64_t)32767 * T || !s.omega ||
         s.K < 1) {
       delete b;
       return -1;
@@ -481,9 +494,11 @@ int pl_batch_run(pl_batch* b, pl_result* out, double* beta_hat, void* work, size
         up(b->off_lam, b->lam.data(), b->lam.size() * sizeof(double)) != hipSuccess ||
         hipStreamSynchronize(b->cap) != hipSuccess)
       return PL_E_HIP;
-    int dev = 0, cus = 0, per_cu = 0;
+    int dev = 0, cus = 0, per_cu = 0, clock_khz = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+        clock_khz <= 0 ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_persistent, 256, 0) !=
             hipSuccess)
       return PL_E_HIP;
@@ -514,6 +529,7 @@ int pl_batch_run(pl_batch* b, pl_result* out, double* beta_hat, void* work, size
     a.TB = b->TB;
     a.out = out;
     a.beta = beta_hat;
+    a.wait_ticks = (int64_t)b->wait_us * clock_khz / 1000;
     hipGraph_t graph = nullptr;
     if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return PL_E_HIP;

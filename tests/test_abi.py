@@ -110,9 +110,10 @@ def test_matern_and_chol_argument_errors():
 
 
 def test_opts_struct_layout():
-    # precision, refine, chunk, flags, flush, reserved[2]: 32 bytes
+    # precision, refine, chunk, flags, flush, wait_us, reserved: 32 bytes
     assert ctypes.sizeof(_lib.PlOpts) == 32
     assert _lib.PlOpts.chunk.offset == 8 and _lib.PlOpts.flush.offset == 20
+    assert _lib.PlOpts.wait_us.offset == 24
 
 
 def test_autotune_argument_errors_and_workspace():

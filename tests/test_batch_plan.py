@@ -64,3 +64,26 @@ def test_plan_rejects_bad_datasets():
     assert rc == -3
     rc, h, _ = _plan([100], [1], M=0)
     assert rc == -5
+
+
+def test_plan_tile_index_bound():
+    # the task list holds tile indices as int16: a dataset with more than 32767
+    # tile rows is rejected before any task is built
+    rc, h, _ = _plan([32767 * 128 + 1], [1])
+    assert rc == -1
+    rc, h, _ = _plan([100], [1], slabs=0)
+    assert rc == 0
+    pl.load().pl_batch_destroy(h)
+
+
+def test_plan_rejects_negative_wait_limit():
+    lib = pl.load()
+    om = np.array([[1.0, 1.5, 0.1, 1.0, 0.0]])
+    arr = (_lib.PlDataset * 1)()
+    arr[0] = _lib.PlDataset(0x1000, 0x2000, 0x3000, 100, om.ctypes.data, 1)
+    lam = np.array([0.0])
+    o = _lib.PlOpts()
+    o.wait_us = -1
+    h = ctypes.c_void_p()
+    assert lib.pl_batch_create(arr, 1, 2, lam.ctypes.data_as(ctypes.c_void_p), 1, ctypes.byref(o),
+                               ctypes.byref(h)) == -6

@@ -22,8 +22,9 @@ def _problems(D=10, seed=0, n_lo=40, n_hi=700):
 
 
 def _check_close(a, b, n, tol=1e-11):
-    scale = np.maximum(np.abs(b), n)
-    assert np.max(np.abs(a - b) / scale) <= tol
+    d = np.abs(a - b)
+    assert np.max(d / np.maximum(np.abs(b), 1.0)) <= tol
+    assert np.max(d) <= tol * n
 
 
 def test_batch_matches_single_path_and_oracle(plprof_lib):
@@ -82,3 +83,51 @@ def test_batch_isolates_failed_unit(plprof_lib):
         q = probs[i]
         ref = oracle.profile_loglik(q.locs, q.y, q.X, q.omega, lam)
         _check_close(b.records(i)["loglik"].cpu().numpy(), ref["loglik"], q.n, tol=1e-8)
+
+
+def test_batch_large_units_match_oracle(plprof_lib):
+    # units up to n = 1500 (12 block columns, the largest of the uneven
+    # workload) beside small ones, so that deep task chains and slabs reused
+    # across waves of different sizes are covered; every record against the
+    # oracle, FP64 bar
+    pl = plprof_lib
+    ns = [1500, 1217, 1388, 130, 1452, 101, 777]
+    probs = [synth.small_problem(n, p=2, K=2 if n > 1000 else 3, M=2, seed=300 + i,
+                                 aniso=bool(i % 2)) for i, n in enumerate(ns)]
+    lam = probs[0].lam
+    print(f"batch: n = {ns}, slab pool 4", flush=True)
+    b = pl.batch.Batch(probs, lam, max_slabs=4).run()
+    torch.cuda.synchronize()
+    assert b.error() == 0
+    for i, pr in enumerate(probs):
+        rec = {k: v.cpu().numpy() for k, v in b.records(i).items()}
+        ref, refb = oracle.profile_loglik(pr.locs, pr.y, pr.X, pr.omega, lam, return_beta=True)
+        assert np.array_equal(rec["info"], ref["info"])
+        _check_close(rec["loglik"], ref["loglik"], pr.n, tol=1e-8)
+        _check_close(rec["loglik_reml"], ref["loglik_reml"], pr.n, tol=1e-8)
+        np.testing.assert_allclose(rec["beta"], refb, rtol=1e-7, atol=1e-7)
+
+
+def test_batch_wait_limit_drains_and_reports(plprof_lib):
+    # a 1-microsecond limit on every task wait: waits that are not met at once
+    # give up, set the error flag and make every later task skip its work.
+    # The launch must still end (this test returning is the proof) and report
+    # the error; a plan with the default limit on the same data is then exact.
+    pl = plprof_lib
+    probs = _problems(D=6, seed=4, n_lo=600, n_hi=1500)
+    lam = probs[0].lam
+    print("batch: 1 us wait limit", flush=True)
+    tight = pl.batch.Batch(probs, lam, wait_us=1).run()
+    torch.cuda.synchronize()
+    assert tight.error() == 1
+    tight.run()  # the error flag is cleared by every launch and set again
+    torch.cuda.synchronize()
+    assert tight.error() == 1
+    tight.close()
+    print("batch: default wait limit", flush=True)
+    ok = pl.batch.Batch(probs, lam).run()
+    torch.cuda.synchronize()
+    assert ok.error() == 0
+    pr = probs[0]
+    ref = oracle.profile_loglik(pr.locs, pr.y, pr.X, pr.omega, lam)
+    _check_close(ok.records(0)["loglik"].cpu().numpy(), ref["loglik"], pr.n, tol=1e-8)

@@ -27,12 +27,15 @@ def _gpu(pl, pr, **kw):
 
 
 def _check(got, ref, refb, n, tol=1e-8):
-    scale = np.maximum(np.abs(ref["loglik"]), n)
-    err = np.abs(got["loglik"] - ref["loglik"]) / scale
+    # relative to the log-likelihood itself (floored at 1 for values near 0),
+    # and absolute per location
     assert np.all(got["info"] == ref["info"]), (got["info"], ref["info"])
-    assert np.max(err) <= tol, f"max rel loglik err {np.max(err):.3e}"
-    errr = np.abs(got["loglik_reml"] - ref["loglik_reml"]) / scale
-    assert np.max(errr) <= tol
+    for f in ("loglik", "loglik_reml"):
+        d = np.abs(got[f] - ref[f])
+        rel = d / np.maximum(np.abs(ref[f]), 1.0)
+        assert np.max(rel) <= tol, f"max rel {f} err {np.max(rel):.3e}"
+        assert np.max(d) <= tol * n, f"max abs {f} err {np.max(d):.3e}"
+    err = np.abs(got["loglik"] - ref["loglik"]) / np.maximum(np.abs(ref["loglik"]), 1.0)
     np.testing.assert_allclose(got["logdet_v"], ref["logdet_v"], rtol=0, atol=tol * n)
     np.testing.assert_allclose(got["jacobian"], ref["jacobian"], rtol=1e-13, atol=1e-12)
     for f in ("ssq_y", "ssq_resid", "ssq_betahat", "sigma2_hat"):
@@ -111,20 +114,6 @@ def test_config_iso_grid_full(plprof_lib):
     got = _gpu(pl, pr)
     ref, refb = oracle.profile_loglik(pr.locs, pr.y, pr.X, pr.omega, pr.lam, return_beta=True)
     _check(got, ref, refb, pr.n)
-
-
-def test_config_aniso_full_size_sampled(plprof_lib):
-    # n=2000, K=1024, M=8 in one device pass (the benchmark's configuration);
-    # a seeded sample of omega points is recomputed by the oracle
-    pl = plprof_lib
-    pr = synth.config_aniso()
-    got = _gpu(pl, pr)
-    assert np.all(got["info"] == 0)
-    assert np.all(np.isfinite(got["loglik"]))
-    idx = np.random.default_rng(0).choice(pr.K, 6, replace=False)
-    ref, refb = oracle.profile_loglik(pr.locs, pr.y, pr.X, pr.omega[idx], pr.lam, return_beta=True)
-    sub = {k: v[idx] for k, v in got.items()}
-    _check(sub, ref, refb, pr.n)
 
 
 def test_chunking_is_bitwise_invariant(plprof_lib):
