@@ -66,6 +66,14 @@ def load(path: str = None):
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise PlError(f"plprof HIP library not found at {p}; run __graft_entry__.build()")
+    # PyTorch ships its own HIP runtime.  Importing it first makes the
+    # library bind to that runtime, the one that owns torch's device memory
+    # and streams; loaded the other way round, the library's kernel launches
+    # fail in a process that then imports torch.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(p)
     lib.pl_version.restype = ctypes.c_char_p
     lib.pl_version.argtypes = []
