@@ -11,8 +11,9 @@
  *
  * Ownership: the caller allocates and owns every device buffer, including the
  * workspace sized by the matching *_workspace_size call.  The library keeps
- * no device state between calls.  Host arrays (omega, lambda, options) are
- * read during the call only.
+ * no device state between calls, except the fixed scratch array of
+ * pl_profile_loglik_noalloc.  Host arrays (omega, lambda, options) are read
+ * during the call only.
  *
  * Notation and definitions (Xu & Brown, "Profile likelihoods for parameters
  * in trans-Gaussian geostatistical models"):
@@ -47,6 +48,8 @@ extern "C" {
 #define PL_E_HIP         1   /* a HIP runtime call failed                       */
 #define PL_E_WORKSPACE   2   /* workspace too small for even one omega          */
 #define PL_E_UNSUPPORTED 3   /* size outside the compiled limits                */
+#define PL_E_SCRATCH     4   /* pl_profile_loglik_noalloc: one omega needs more
+                                than PL_NOALLOC_SCRATCH_BYTES                   */
 
 /* per-record info codes */
 #define PL_INFO_RANK     (-1)        /* X^T V^-1 X not positive definite        */
@@ -189,6 +192,31 @@ int pl_profile_loglik(const double* locs, const double* y, const double* X,
                       const double* lambda, int64_t M, pl_result* out,
                       double* beta_hat, double* xvx_inv, const pl_opts* opts, void* work,
                       size_t work_bytes, void* stream);
+
+/*
+ * pl_profile_loglik without a caller workspace and without any device
+ * allocation, for callers that cannot allocate: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * Arguments, results, error codes 1-13 and stream semantics are those of
+ * pl_profile_loglik (stream is argument 14).  The workspace is a fixed device
+ * array of PL_NOALLOC_SCRATCH_BYTES inside the library; each GPU holds its
+ * own copy from the first call on it until the process ends.  The omega
+ * points run in as many stream-ordered passes as the array needs.  The call
+ * allocates no device memory and calls no allocating library routine; the
+ * stream must belong to the current device.
+ * Limits: PL_E_SCRATCH when one omega's workspace exceeds the array: FP64
+ * n above about 8,050 (M + p <= 16) or 7,900 (M + p <= 32); PL_MIXED n above
+ * about 6,400 (M + p <= 16) or 6,250 (M + p <= 32).
+ * Calls that overlap on one GPU (different streams or host threads without
+ * ordering between them) share the array and race; serialise them.
+ */
+#define PL_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)   /* 256 MiB per GPU */
+int pl_profile_loglik_noalloc(const double* locs, const double* y, const double* X,
+                              int64_t n, int64_t p, const double* omega, int64_t K,
+                              const double* lambda, int64_t M, pl_result* out,
+                              double* beta_hat, double* xvx_inv, const pl_opts* opts,
+                              void* stream);
 
 /*
  * Profile curves of sigma and of single regression coefficients from the

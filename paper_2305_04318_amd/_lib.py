@@ -19,7 +19,7 @@ EXPORTS = ("pl_version", "pl_error_string", "pl_workspace_size", "pl_matern_work
            "pl_mle", "pl_hessian_workspace_size", "pl_hessian", "pl_config_points",
            "pl_sphere_points", "pl_lambda_grid", "pl_chisq_quantile", "pl_batch_create",
            "pl_batch_workspace_size", "pl_batch_stats", "pl_batch_run", "pl_batch_error",
-           "pl_batch_destroy")
+           "pl_batch_destroy", "pl_profile_loglik_noalloc")
 KERNEL_CLASSES = ("tables", "matern", "gemm", "potrf", "trsm", "other")
 
 
@@ -93,6 +93,9 @@ def load(path: str = None):
     lib.pl_profile_loglik.restype = ctypes.c_int
     lib.pl_profile_loglik.argtypes = [_P, _P, _P, _I64, _I64, _P, _I64, _P, _I64, _P, _P, _P,
                                       ctypes.POINTER(PlOpts), _P, _SZ, _P]
+    lib.pl_profile_loglik_noalloc.restype = ctypes.c_int
+    lib.pl_profile_loglik_noalloc.argtypes = [_P, _P, _P, _I64, _I64, _P, _I64, _P, _I64, _P, _P,
+                                              _P, ctypes.POINTER(PlOpts), _P]
     lib.pl_curves_workspace_size.restype = ctypes.c_int
     lib.pl_curves_workspace_size.argtypes = [_I64, _I64, _I64, _I64, ctypes.POINTER(_SZ)]
     lib.pl_profile_curves.restype = ctypes.c_int

@@ -156,6 +156,36 @@ def profile_loglik(locs, y, X, omega, lam, precision="fp64", chunk=0, return_bet
     return res
 
 
+def profile_loglik_noalloc(locs, y, X, omega, lam, precision="fp64", chunk=0,
+                           return_beta=False, out=None, beta=None, stream=None, device="cuda",
+                           inputs=None, refine=1, fallback=True, flush=0):
+    """profile_loglik with the library's fixed per-GPU scratch array as its
+    workspace (pl_profile_loglik_noalloc): the library allocates nothing.
+    Output tensors are allocated here unless `out` (and `beta`) are given."""
+    lib = load()
+    inp = inputs if inputs is not None else Inputs(locs, y, X, device)
+    om = _host_f64(omega, 5)
+    lm = _host_f64(lam).reshape(-1)
+    K, M = om.shape[0], lm.shape[0]
+    dev = inp.device
+    if out is None:
+        out = torch.empty((K, M, 10), dtype=torch.float64, device=dev)
+    if return_beta and beta is None:
+        beta = torch.empty((K, M, inp.p), dtype=torch.float64, device=dev)
+    o = _opts(precision, chunk, refine, fallback, flush)
+    rc = lib.pl_profile_loglik_noalloc(_ptr(inp.locs), _ptr(inp.y), _ptr(inp.Xc), inp.n, inp.p,
+                                       om.ctypes.data_as(ctypes.c_void_p), K,
+                                       lm.ctypes.data_as(ctypes.c_void_p), M, _ptr(out),
+                                       _ptr(beta) if return_beta else None, None,
+                                       ctypes.byref(o), _stream_ptr(stream))
+    check(rc, "pl_profile_loglik_noalloc")
+    res = unpack_records(out)
+    res["records"] = out
+    if return_beta:
+        res["beta"] = beta
+    return res
+
+
 def profile_curves(res, lam, n, sigma_grid=None, beta_grid=None, stream=None):
     """pl_profile_curves over the output `res` of one profile_loglik call
     (made with return_beta and return_xvx_inv when beta_grid is given).

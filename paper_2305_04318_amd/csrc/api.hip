@@ -182,6 +182,7 @@ const char* pl_error_string(int code) {
     case PL_E_HIP: return "HIP runtime error";
     case PL_E_WORKSPACE: return "workspace too small";
     case PL_E_UNSUPPORTED: return "unsupported size";
+    case PL_E_SCRATCH: return "one omega of this problem does not fit the fixed scratch array";
     default: return "unknown error";
   }
 }

@@ -183,3 +183,27 @@ def test_curves_argument_errors():
 def test_missing_library_fails_loudly(tmp_path):
     with pytest.raises(_lib.PlError):
         _lib.load(str(tmp_path / "nope.so"))
+
+
+def test_noalloc_rejects_problems_beyond_its_scratch():
+    """pl_profile_loglik_noalloc refuses, before any device work, a problem
+    one omega of which needs more than its fixed array; sizes are checked as
+    in pl_profile_loglik."""
+    lib = pl.load()
+    om = np.array([[1.0, 1.0, 0.1, 1.0, 0.0]])
+    lm = np.zeros(4)
+    one = ctypes.c_void_p(1)
+
+    def call(n, p=2, K=1, M=4, precision=_lib.PL_FP64):
+        o = _lib.PlOpts()
+        o.precision = precision
+        return lib.pl_profile_loglik_noalloc(one, one, one, n, p,
+                                             om.ctypes.data_as(ctypes.c_void_p), K,
+                                             lm.ctypes.data_as(ctypes.c_void_p), M, one, None,
+                                             None, ctypes.byref(o), None)
+
+    assert call(9000) == 4 and lib.pl_error_string(4).startswith(b"one omega")
+    assert call(7000, precision=_lib.PL_MIXED) == 4
+    assert call(1) == -4 and call(100, p=0) == -5 and call(100, K=0) == -7
+    assert call(100, M=0) == -9 and call(100, precision=7) == -13
+    assert call(100, p=30, M=8, precision=_lib.PL_MIXED) == 3
