@@ -43,6 +43,10 @@ extern "C" {
                            tiles, log-determinant, p x p stage and residual,
                            one FP64 iterative-refinement step                   */
 
+/* storage types of pl_matern_cov */
+#define PL_F64   0      /* double                                              */
+#define PL_F32   1      /* float: each element computed in FP64, rounded once  */
+
 /* runtime error codes (positive returns) */
 #define PL_OK            0
 #define PL_E_HIP         1   /* a HIP runtime call failed                       */
@@ -120,39 +124,53 @@ int pl_workspace_size(int64_t n, int64_t p, int64_t K, int64_t M,
 
 /*
  * Matern correlation-plus-nugget matrices V_k = R(omega_k) + nu_k^2 I
- * (Section 2.1, equation (1); Step 1 of Section 3.3).
+ * (Section 2.1, equation (1); Step 1 of Section 3.3, the paper's maternBatch,
+ * whose precision is a per-call choice).
  *   locs   device, n x 2 row-major (x_i, y_i)
  *   omega  host, K x 5 row-major natural parameters
+ *   dtype  PL_F64: V holds doubles; PL_F32: V holds floats, each element
+ *          computed in FP64 and rounded once (the input of pl_chol_batched
+ *          with PL_MIXED)
  *   V      device, K matrices, each n x n column-major with leading dimension
- *          ld >= n; matrix k starts at V + k*ld*n.  The lower triangle and the
- *          diagonal are written; the strict upper triangle is not touched.
+ *          ld >= n; matrix k starts at element k*ld*n.  The lower triangle and
+ *          the diagonal are written; the strict upper triangle is not touched.
  *   work   device workspace of pl_matern_workspace_size(K) bytes.
  * Errors: -1 locs NULL, -2 n < 1, -3 omega NULL or a parameter out of domain
  * (range <= 0, shape outside [PL_MIN_SHAPE, PL_MAX_SHAPE], nugget < 0,
- * ratio <= 0, any value not finite), -4 K < 1, -5 V NULL, -6 ld < n,
- * -7/-8 workspace NULL or too small.
+ * ratio <= 0, any value not finite), -4 K < 1, -5 dtype not PL_F64 or
+ * PL_F32, -6 V NULL, -7 ld < n, -8/-9 workspace NULL or too small.
  */
 int pl_matern_workspace_size(int64_t K, size_t* bytes);
-int pl_matern_cov(const double* locs, int64_t n, const double* omega, int64_t K,
-                  double* V, int64_t ld, void* work, size_t work_bytes, void* stream);
+int pl_matern_cov(const double* locs, int64_t n, const double* omega, int64_t K, int dtype,
+                  void* V, int64_t ld, void* work, size_t work_bytes, void* stream);
 
 /*
- * In-place batched Cholesky V_k = L_k L_k^T (Step 2 of Section 3.3; the paper
- * factors L D L^T, whose determinant is the same) with
+ * In-place batched Cholesky V_k = L_k L_k^T (Step 2 of Section 3.3, the
+ * paper's cholBatch; it factors L D L^T, whose determinant is the same) with
  * logdet[k] = log|V_k| = 2 sum_i log L_k,ii.
- *   V      device, K matrices, n x n column-major, leading dimension ld,
- *          matrix k at V + k*ld*n; the lower triangle is read and overwritten
- *          by L, the strict upper triangle is not referenced.
- *   logdet device, K doubles.  info device, K int32: 0, or j > 0 when the
- *          leading minor of order j is not positive definite (that matrix is
- *          left partly factored and logdet[k] is not meaningful).
- *   work   device workspace of pl_chol_workspace_size(K) bytes.
- * Errors: -1 V NULL, -2 n < 1, -3 K < 1, -4 ld < n, -5 logdet NULL,
- * -6 info NULL, -7/-8 workspace NULL or too small.
+ *   V         device, K matrices, n x n column-major, leading dimension ld,
+ *             matrix k at element k*ld*n; the lower triangle is read and
+ *             overwritten by L, the strict upper triangle is not referenced.
+ *   precision PL_FP64: V holds doubles and every step is FP64.
+ *             PL_MIXED: V holds floats (pl_matern_cov with PL_F32) and L is
+ *             stored in FP32; off-diagonal updates and panel solves run on
+ *             FP32 MFMA with their partial sums folded into FP64 every 16
+ *             products, each diagonal tile is updated with FP64 accumulation
+ *             and factored in FP64, so logdet is accumulated in FP64.  V must
+ *             be 16-byte aligned and ld a multiple of 4.
+ *   logdet    device, K doubles.  info device, K int32: 0, or j > 0 when the
+ *             leading minor of order j is not positive definite (that matrix
+ *             is left partly factored and logdet[k] is not meaningful).
+ *   work      device workspace of pl_chol_workspace_size(K, precision) bytes.
+ * Errors: -1 V NULL (or, PL_MIXED, not 16-byte aligned), -2 n < 1, -3 K < 1,
+ * -4 ld < n (or, PL_MIXED, not a multiple of 4), -5 precision not PL_FP64 or
+ * PL_MIXED, -6 logdet NULL, -7 info NULL, -8/-9 workspace NULL or too small.
+ * pl_chol_workspace_size: -1 K < 1, -2 precision, -3 bytes NULL.
  */
-int pl_chol_workspace_size(int64_t K, size_t* bytes);
-int pl_chol_batched(double* V, int64_t n, int64_t K, int64_t ld, double* logdet,
-                    int32_t* info, void* work, size_t work_bytes, void* stream);
+int pl_chol_workspace_size(int64_t K, int precision, size_t* bytes);
+int pl_chol_batched(void* V, int64_t n, int64_t K, int64_t ld, int precision,
+                    double* logdet, int32_t* info, void* work, size_t work_bytes,
+                    void* stream);
 
 /*
  * Profile log-likelihood at every (omega_k, lambda_m) (Section 3.3, Steps 1-8;

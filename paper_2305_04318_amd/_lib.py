@@ -7,6 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libplprof.so")
 
 PL_FP64, PL_MIXED = 0, 1
+PL_F64, PL_F32 = 0, 1
 PL_INFO_RANK, PL_INFO_BAD_Y, PL_INFO_FALLBACK = -1, -2, 1 << 30
 PL_MAX_P, PL_MAX_M = 32, 64
 
@@ -85,11 +86,11 @@ def load(path: str = None):
     lib.pl_matern_workspace_size.restype = ctypes.c_int
     lib.pl_matern_workspace_size.argtypes = [_I64, ctypes.POINTER(_SZ)]
     lib.pl_matern_cov.restype = ctypes.c_int
-    lib.pl_matern_cov.argtypes = [_P, _I64, _P, _I64, _P, _I64, _P, _SZ, _P]
+    lib.pl_matern_cov.argtypes = [_P, _I64, _P, _I64, ctypes.c_int, _P, _I64, _P, _SZ, _P]
     lib.pl_chol_workspace_size.restype = ctypes.c_int
-    lib.pl_chol_workspace_size.argtypes = [_I64, ctypes.POINTER(_SZ)]
+    lib.pl_chol_workspace_size.argtypes = [_I64, ctypes.c_int, ctypes.POINTER(_SZ)]
     lib.pl_chol_batched.restype = ctypes.c_int
-    lib.pl_chol_batched.argtypes = [_P, _I64, _I64, _I64, _P, _P, _P, _SZ, _P]
+    lib.pl_chol_batched.argtypes = [_P, _I64, _I64, _I64, ctypes.c_int, _P, _P, _P, _SZ, _P]
     lib.pl_profile_loglik.restype = ctypes.c_int
     lib.pl_profile_loglik.argtypes = [_P, _P, _P, _I64, _I64, _P, _I64, _P, _I64, _P, _P, _P,
                                       ctypes.POINTER(PlOpts), _P, _SZ, _P]

@@ -60,37 +60,43 @@ def workspace_size(n, p, K, M, precision="fp64", chunk=0) -> int:
     return int(out.value)
 
 
-def matern_cov(locs, omega, device="cuda", ld=None, stream=None):
+def matern_cov(locs, omega, device="cuda", ld=None, stream=None, dtype="f64"):
     """V_k = R(omega_k) + nu_k^2 I, lower triangle, as a (K, n, ld) tensor whose
-    row k*... is column-major per matrix (V[k].T[:n, :n] is the matrix)."""
+    row k*... is column-major per matrix (V[k].T[:n, :n] is the matrix).
+    dtype "f64" or "f32" (elements computed in FP64, rounded once)."""
     lib = load()
     locs_d = _dev_f64(locs, device)
     n = locs_d.shape[0]
     om = _host_f64(omega, 5)
     K = om.shape[0]
     ld = ld or n
-    V = torch.zeros((K, n, ld), dtype=torch.float64, device=device)
+    tdt = {"f64": torch.float64, "f32": torch.float32}[dtype]
+    V = torch.zeros((K, n, ld), dtype=tdt, device=device)
     wb = ctypes.c_size_t(0)
     check(lib.pl_matern_workspace_size(K, ctypes.byref(wb)), "pl_matern_workspace_size")
     work = torch.empty(max(1, wb.value), dtype=torch.uint8, device=device)
-    rc = lib.pl_matern_cov(_ptr(locs_d), n, om.ctypes.data_as(ctypes.c_void_p), K, _ptr(V), ld,
+    rc = lib.pl_matern_cov(_ptr(locs_d), n, om.ctypes.data_as(ctypes.c_void_p), K,
+                           _lib.PL_F64 if dtype == "f64" else _lib.PL_F32, _ptr(V), ld,
                            _ptr(work), wb.value, _stream_ptr(stream))
     check(rc, "pl_matern_cov")
     return V
 
 
 def chol_batched(V, n=None, stream=None):
-    """In-place Cholesky of V (K, n, ld) column-major matrices; returns (logdet, info)."""
+    """In-place Cholesky of V (K, n, ld) column-major matrices; returns
+    (logdet, info).  A float64 V is factored in FP64, a float32 V in the mixed
+    form (FP32 factor, FP64 diagonal tiles and log-determinant)."""
     lib = load()
     K, n_, ld = V.shape
     n = n or n_
+    prec = {torch.float64: _lib.PL_FP64, torch.float32: _lib.PL_MIXED}[V.dtype]
     logdet = torch.empty(K, dtype=torch.float64, device=V.device)
     info = torch.empty(K, dtype=torch.int32, device=V.device)
     wb = ctypes.c_size_t(0)
-    check(lib.pl_chol_workspace_size(K, ctypes.byref(wb)), "pl_chol_workspace_size")
+    check(lib.pl_chol_workspace_size(K, prec, ctypes.byref(wb)), "pl_chol_workspace_size")
     work = torch.empty(max(1, wb.value), dtype=torch.uint8, device=V.device)
-    rc = lib.pl_chol_batched(_ptr(V), n, K, ld, _ptr(logdet), _ptr(info), _ptr(work), wb.value,
-                             _stream_ptr(stream))
+    rc = lib.pl_chol_batched(_ptr(V), n, K, ld, prec, _ptr(logdet), _ptr(info), _ptr(work),
+                             wb.value, _stream_ptr(stream))
     check(rc, "pl_chol_batched")
     return logdet, info
 

@@ -194,20 +194,21 @@ int pl_matern_workspace_size(int64_t K, size_t* bytes) {
   return PL_OK;
 }
 
-int pl_matern_cov(const double* locs, int64_t n, const double* omega, int64_t K, double* V,
-                  int64_t ld, void* work, size_t work_bytes, void* stream) {
+int pl_matern_cov(const double* locs, int64_t n, const double* omega, int64_t K, int dtype,
+                  void* V, int64_t ld, void* work, size_t work_bytes, void* stream) {
   if (!locs) return -1;
   if (n < 1 || n > (1 << 30)) return -2;
   if (!omega) return -3;
   if (K < 1 || K > (1 << 24)) return -4;
   for (int64_t k = 0; k < K; ++k)
     if (!omega_ok(omega + 5 * k)) return -3;
-  if (!V) return -5;
-  if (ld < n) return -6;
-  if (!work) return -7;
+  if (dtype != PL_F64 && dtype != PL_F32) return -5;
+  if (!V) return -6;
+  if (ld < n) return -7;
+  if (!work) return -8;
   size_t need = 0;
   pl_matern_workspace_size(K, &need);
-  if (work_bytes < need) return -8;
+  if (work_bytes < need) return -9;
   hipStream_t s = (hipStream_t)stream;
   std::vector<MaternParams> hp(K);
   for (int64_t k = 0; k < K; ++k) hp[k] = make_matern_params(omega + 5 * k);
@@ -217,30 +218,38 @@ int pl_matern_cov(const double* locs, int64_t n, const double* omega, int64_t K,
   double* tables = cv.take<double>((size_t)K * TABLE * sizeof(double));
   if (stage_h2d(mp, hp.data(), K * sizeof(MaternParams), s) != hipSuccess) return PL_E_HIP;
   PL_CHECK(timed(PL_KC_TABLES, 0.0, s, [&] { return launch_cheb_tables(mp, nodes, tables, (int)K, s); }));
-  PL_CHECK(timed(PL_KC_MATERN, 0.0, s,
-                 [&] { return launch_matern_colmajor(V, ld, (int)n, locs, mp, tables, (int)K, s); }));
+  PL_CHECK(timed(PL_KC_MATERN, 0.0, s, [&] {
+    return dtype == PL_F64
+               ? launch_matern_colmajor((double*)V, ld, (int)n, locs, mp, tables, (int)K, s)
+               : launch_matern_colmajor_f32((float*)V, ld, (int)n, locs, mp, tables, (int)K, s);
+  }));
   return PL_OK;
 }
 
-int pl_chol_workspace_size(int64_t K, size_t* bytes) {
-  if (K < 1) return -1;
-  if (!bytes) return -2;
+int pl_chol_workspace_size(int64_t K, int precision, size_t* bytes) {
+  if (K < 1 || K > (1 << 24)) return -1;
+  if (precision != PL_FP64 && precision != PL_MIXED) return -2;
+  if (!bytes) return -3;
+  // FP64: W_J (FP64) per omega; mixed: the FP64 diagonal tile and W_J in FP32
   *bytes = align_up((size_t)K * T * T * sizeof(double));
+  if (precision == PL_MIXED) *bytes += align_up((size_t)K * T * T * sizeof(float));
   return PL_OK;
 }
 
-int pl_chol_batched(double* V, int64_t n, int64_t K, int64_t ld, double* logdet, int32_t* info,
-                    void* work, size_t work_bytes, void* stream) {
-  if (!V) return -1;
+int pl_chol_batched(void* V, int64_t n, int64_t K, int64_t ld, int precision, double* logdet,
+                    int32_t* info, void* work, size_t work_bytes, void* stream) {
+  const bool mixed = precision == PL_MIXED;
+  if (!V || (mixed && (reinterpret_cast<uintptr_t>(V) & 15) != 0)) return -1;
   if (n < 1 || n > (1 << 30)) return -2;
   if (K < 1 || K > (1 << 24)) return -3;
-  if (ld < n) return -4;
-  if (!logdet) return -5;
-  if (!info) return -6;
-  if (!work) return -7;
+  if (ld < n || (mixed && ld % 4 != 0)) return -4;
+  if (precision != PL_FP64 && precision != PL_MIXED) return -5;
+  if (!logdet) return -6;
+  if (!info) return -7;
+  if (!work) return -8;
   size_t need = 0;
-  pl_chol_workspace_size(K, &need);
-  if (work_bytes < need) return -8;
+  pl_chol_workspace_size(K, precision, &need);
+  if (work_bytes < need) return -9;
   hipStream_t s = (hipStream_t)stream;
   Lay lay{};
   lay.kind = 1;
@@ -248,18 +257,39 @@ int pl_chol_batched(double* V, int64_t n, int64_t K, int64_t ld, double* logdet,
   lay.Nv = (int)((n + T - 1) / T);
   lay.ld = ld;
   lay.mstride = ld * n;
-  double* W = (double*)work;
   PL_CHECK(launch_fill(logdet, 0.0, K, s));
   PL_CHECK(launch_fill_i32(info, 0, K, s));
+  if (mixed) {
+    // FP32 factor: off-diagonal updates and panel solves on FP32 MFMA with
+    // FP64 folds; each diagonal tile updated in FP64 into dscr and factored
+    // in FP64 (log|V| in FP64), L_JJ rounded into the matrix
+    float* V32 = (float*)V;
+    double* dscr = (double*)work;
+    float* W32 = (float*)((char*)work + align_up((size_t)K * T * T * sizeof(double)));
+    for (int J = 0; J < lay.Nv; ++J) {
+      PL_CHECK(timed(PL_KC_GEMM, J > 0 ? K * gemm_col_flops(lay, J, lay.Nv - J) : 0.0, s, [&] {
+        return launch_col_update_mx_plain(lay, V32, dscr, info, J, (int)K, MX_FLUSH, s);
+      }));
+      PL_CHECK(timed(PL_KC_POTRF, 0.0, s, [&] {
+        return launch_potrf_mx_plain(lay, V32, dscr, W32, logdet, info, J, (int)K, s);
+      }));
+      if (lay.Nv - J - 1 > 0)
+        PL_CHECK(timed(PL_KC_TRSM, 0.0, s,
+                       [&] { return launch_trsm_mx_plain(lay, V32, W32, info, J, (int)K, s); }));
+    }
+    return PL_OK;
+  }
+  double* W = (double*)work;
+  double* V64 = (double*)V;
   for (int J = 0; J < lay.Nv; ++J) {
     if (J > 0)
       PL_CHECK(timed(PL_KC_GEMM, K * gemm_col_flops(lay, J, lay.Nv - J), s,
-                     [&] { return launch_gemm_col(lay, V, info, J, lay.Nv - J, (int)K, s); }));
+                     [&] { return launch_gemm_col(lay, V64, info, J, lay.Nv - J, (int)K, s); }));
     PL_CHECK(timed(PL_KC_POTRF, 0.0, s,
-                   [&] { return launch_potrf(lay, V, W, logdet, info, J, (int)K, s); }));
+                   [&] { return launch_potrf(lay, V64, W, logdet, info, J, (int)K, s); }));
     if (lay.Nv - J - 1 > 0)
       PL_CHECK(timed(PL_KC_TRSM, 0.0, s,
-                     [&] { return launch_trsm(lay, V, W, info, J, lay.Nv - J - 1, (int)K, s); }));
+                     [&] { return launch_trsm(lay, V64, W, info, J, lay.Nv - J - 1, (int)K, s); }));
   }
   return PL_OK;
 }

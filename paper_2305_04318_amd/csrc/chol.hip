@@ -75,7 +75,7 @@ __device__ __forceinline__ void dev_col_mx(const Lay& lay, float* __restrict__ m
   if (act) {
     const int64_t ldc = lay.tile_ld(I);
     float* C = base + lay.tile_off(I, J) + 64 * wr + 64 * wc * ldc;
-    if (I < lay.Nv) {
+    if (I < lay.Nv && m64) {
       // V's own tile from the FP64 copy: the update is subtracted in FP64
       const double* Cin = m64 + (int64_t)k * m64stride + lay.tile_off(I, J) + 64 * wr + 64 * wc * T;
       store64_l<float, true>(Cin, T, C, ldc, acc, war, wbr, lane);
@@ -121,9 +121,16 @@ __device__ __forceinline__ void dev_diag_mx(const Lay& lay, float* __restrict__ 
                                    kmax, act, ni);
   }
   if (act) {
-    const double* Cin = m64 + (int64_t)k * m64stride + lay.tile_off(J, J) + 64 * wr + 64 * wc * T;
     double* Cout = dscratch + (int64_t)k * T * T + 64 * wr + 64 * wc * T;
-    store64<double, true>(Cin, T, Cout, T, acc, war, wbr, lane);
+    if (m64) {
+      const double* Cin = m64 + (int64_t)k * m64stride + lay.tile_off(J, J) + 64 * wr + 64 * wc * T;
+      store64<double, true>(Cin, T, Cout, T, acc, war, wbr, lane);
+    } else {
+      // no FP64 copy (the plain FP32 matrix of pl_chol_batched): V's tile as stored
+      const int64_t ldj = lay.tile_ld(J);
+      const float* Cin = base + lay.tile_off(J, J) + 64 * wr + 64 * wc * ldj;
+      store64<double, true>(Cin, ldj, Cout, T, acc, war, wbr, lane);
+    }
   }
 }
 
@@ -152,6 +159,30 @@ __global__ __launch_bounds__(256, 2) void k_col_update_mx(Lay lay, float* __rest
   const int k = wg / nOff, r = wg % nOff;
   if (info[k] != 0) return;
   dev_col_mx<true, FLUSH>(lay, m32, m64, m64stride, k, J + 1 + r, J, lds);
+}
+
+// Mixed form on a plain column-major FP32 matrix (pl_chol_batched with
+// PL_MIXED): no bordered row and no FP64 copy of V, so each tile's update is
+// subtracted from the FP32 tile itself (promoted to FP64).  The K diagonal
+// tiles come first, then the nOff tiles below each.
+template <int FLUSH>
+__global__ __launch_bounds__(256, 2) void k_col_update_mx_plain(Lay lay, float* __restrict__ m32,
+                                                                double* __restrict__ dscratch,
+                                                                const int32_t* __restrict__ info,
+                                                                int J, int nOff, int K) {
+  __shared__ __attribute__((aligned(16))) char lds_raw[GEMM_LDS_BYTES];
+  float* lds = reinterpret_cast<float*>(lds_raw);
+  const int b = blockIdx.x;
+  if (b < K) {
+    if (info[b] != 0) return;  // uniform for the workgroup
+    dev_diag_mx<true, false>(lay, m32, nullptr, 0, dscratch, b, J, lds);
+    return;
+  }
+  const int G = K * nOff;
+  const int wg = xcd_remap(b - K, G);
+  const int k = wg / nOff, r = wg % nOff;
+  if (info[k] != 0) return;
+  dev_col_mx<true, FLUSH>(lay, m32, nullptr, 0, k, J + 1 + r, J, lds);
 }
 
 static bool vec_ok(const Lay& lay, const void* p) {
@@ -196,6 +227,34 @@ hipError_t launch_gemm_col_mx(const Lay& lay, float* m32, const double* m64, int
   return hipGetLastError();
 }
 
+hipError_t launch_col_update_mx_plain(const Lay& lay, float* m32, double* dscratch,
+                                      const int32_t* info, int J, int K, int flush,
+                                      hipStream_t s) {
+  // 16-byte loads of every column: the matrix and ld must keep 4-float alignment
+  if (!(lay.kind == 1 && lay.ld % 4 == 0 && (reinterpret_cast<uintptr_t>(m32) & 15) == 0))
+    return hipErrorInvalidValue;
+  if (J < 0 || J >= lay.Nv) return hipErrorInvalidValue;
+  const int nOff = (J > 0) ? lay.Nv - 1 - J : 0;  // J = 0: no update below the diagonal
+  const int G = K * (nOff + 1);
+  switch (flush) {
+    case 1:
+      hipLaunchKernelGGL(k_col_update_mx_plain<1>, dim3(G), dim3(256), 0, s, lay, m32, dscratch,
+                         info, J, nOff, K);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_col_update_mx_plain<2>, dim3(G), dim3(256), 0, s, lay, m32, dscratch,
+                         info, J, nOff, K);
+      break;
+    case 4:
+      hipLaunchKernelGGL(k_col_update_mx_plain<4>, dim3(G), dim3(256), 0, s, lay, m32, dscratch,
+                         info, J, nOff, K);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 // ---- diagonal tile: factor and invert (dev_potrf) ---------------------------------
 // MODE 0 (FP64 form): the tile is read from and L written back to the packed
 //   matrix, W (FP64) to Wbuf[k].  MODE 1 (mixed form): the tile is read from
@@ -220,6 +279,28 @@ __global__ __launch_bounds__(256) void k_potrf(Lay lay, double* __restrict__ mat
 hipError_t launch_potrf(const Lay& lay, double* mats, double* W, double* logdet, int32_t* info,
                         int J, int K, hipStream_t s) {
   hipLaunchKernelGGL(k_potrf<0>, dim3(K), dim3(256), 0, s, lay, mats, W, (float*)nullptr, logdet,
+                     info, J);
+  return hipGetLastError();
+}
+
+// Plain FP32 matrix: the FP64 tile from dscratch[k], L_JJ rounded into the
+// matrix, W_J to the omega's single FP32 slot W32[k].
+__global__ __launch_bounds__(256) void k_potrf_mx_plain(Lay lay, float* __restrict__ m32,
+                                                        double* __restrict__ dscratch,
+                                                        float* __restrict__ W32,
+                                                        double* __restrict__ logdet,
+                                                        int32_t* __restrict__ info, int J) {
+  __shared__ double smem[POTRF_SMEM_DOUBLES];
+  const int k = blockIdx.x;
+  if (info[k] != 0) return;
+  dev_potrf<2>(lay, dscratch + (int64_t)k * T * T, T, nullptr, W32 + (int64_t)k * T * T,
+               logdet + k, info + k, J, smem, m32 + (int64_t)k * lay.mstride + lay.tile_off(J, J),
+               lay.tile_ld(J));
+}
+
+hipError_t launch_potrf_mx_plain(const Lay& lay, float* m32, double* dscratch, float* W32,
+                                 double* logdet, int32_t* info, int J, int K, hipStream_t s) {
+  hipLaunchKernelGGL(k_potrf_mx_plain, dim3(K), dim3(256), 0, s, lay, m32, dscratch, W32, logdet,
                      info, J);
   return hipGetLastError();
 }
@@ -386,6 +467,18 @@ hipError_t launch_trsm_mx(const Lay& lay, float* m32, const float* W32, const in
   const int64_t ws = (int64_t)lay.Nv * T * T;
   hipLaunchKernelGGL((k_trsm<float, true>), dim3(G), dim3(256), 0, s, lay, m32,
                      W32 + (int64_t)J * T * T, info, J, nI, G, ws);
+  return hipGetLastError();
+}
+
+hipError_t launch_trsm_mx_plain(const Lay& lay, float* m32, const float* W32,
+                                const int32_t* info, int J, int K, hipStream_t s) {
+  if (!(lay.kind == 1 && lay.ld % 4 == 0 && (reinterpret_cast<uintptr_t>(m32) & 15) == 0))
+    return hipErrorInvalidValue;
+  const int nI = lay.Nv - J - 1;
+  if (nI <= 0) return hipSuccess;
+  const int G = K * nI;
+  hipLaunchKernelGGL((k_trsm<float, true>), dim3(G), dim3(256), 0, s, lay, m32, W32, info, J, nI,
+                     G, (int64_t)T * T);
   return hipGetLastError();
 }
 

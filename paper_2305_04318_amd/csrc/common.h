@@ -93,6 +93,9 @@ hipError_t launch_matern_packed(const Lay& lay, double* mats, const double* locs
 hipError_t launch_matern_colmajor(double* V, int64_t ld, int n, const double* locs,
                                   const MaternParams* mp, const double* tables, int K,
                                   hipStream_t s);
+hipError_t launch_matern_colmajor_f32(float* V, int64_t ld, int n, const double* locs,
+                                      const MaternParams* mp, const double* tables, int K,
+                                      hipStream_t s);
 hipError_t launch_potrf(const Lay& lay, double* mats, double* W, double* logdet,
                         int32_t* info, int J, int K, hipStream_t s);
 hipError_t launch_trsm(const Lay& lay, double* mats, const double* W, const int32_t* info,
@@ -134,6 +137,18 @@ hipError_t launch_potrf_mx(const Lay& lay, double* dscratch, float* W32, double*
                            int32_t* info, int J, int K, hipStream_t s);
 hipError_t launch_trsm_mx(const Lay& lay, float* m32, const float* W32, const int32_t* info, int J,
                           int nI, int K, hipStream_t s);
+// mixed form on a plain column-major FP32 matrix (kind 1): the update of
+// block column J (diagonal tile in FP64 into dscratch, the nI - 1 tiles below
+// it in FP32 MFMA with FP64 folds, in place), the diagonal factor (L_JJ
+// rounded into the matrix, W_J in FP32 to W32[k], one T x T slot per omega)
+// and the panel solve of the nI - 1 tiles below J
+hipError_t launch_col_update_mx_plain(const Lay& lay, float* m32, double* dscratch,
+                                      const int32_t* info, int J, int K, int flush,
+                                      hipStream_t s);
+hipError_t launch_potrf_mx_plain(const Lay& lay, float* m32, double* dscratch, float* W32,
+                                 double* logdet, int32_t* info, int J, int K, hipStream_t s);
+hipError_t launch_trsm_mx_plain(const Lay& lay, float* m32, const float* W32,
+                                const int32_t* info, int J, int K, hipStream_t s);
 hipError_t launch_backsolve(const Lay& lay, const float* m32, const float* W32,
                             const int32_t* info, double* X, int K, hipStream_t s);
 hipError_t launch_qform(const Lay& lay, const double* m64, int64_t stride64, const double* X,

@@ -118,8 +118,8 @@ __global__ __launch_bounds__(256) void k_matern(Lay lay, double* __restrict__ ma
   while ((I + 1) * (I + 2) / 2 <= t) ++I;
   const int J = t - I * (I + 1) / 2;
   const int64_t off = lay.tile_off(I, J);
-  double* C = mats + (int64_t)k * stride64 + off;
-  float* C32 = (MODE == 2) ? m32 + (int64_t)k * stride32 + off : nullptr;
+  double* C = (MODE != 3) ? mats + (int64_t)k * stride64 + off : nullptr;
+  float* C32 = (MODE == 2 || MODE == 3) ? m32 + (int64_t)k * stride32 + off : nullptr;
   dev_matern_tile<MODE>(lay, mp[k], tables + (int64_t)k * TABLE, locs, I, J, C, lay.tile_ld(I),
                         C32, smem);
 }
@@ -157,6 +157,23 @@ hipError_t launch_matern_colmajor(double* V, int64_t ld, int n, const double* lo
   const int G = K * ntiles;
   hipLaunchKernelGGL(k_matern<1>, dim3(G), dim3(256), 0, s, lay, V, lay.mstride, (float*)nullptr,
                      (int64_t)0, locs, mp, tables, ntiles, G);
+  return hipGetLastError();
+}
+
+// FP32 column-major V: every element computed in FP64 as above, rounded once.
+hipError_t launch_matern_colmajor_f32(float* V, int64_t ld, int n, const double* locs,
+                                      const MaternParams* mp, const double* tables, int K,
+                                      hipStream_t s) {
+  Lay lay{};
+  lay.kind = 1;
+  lay.n = n;
+  lay.Nv = (n + T - 1) / T;
+  lay.ld = ld;
+  lay.mstride = ld * (int64_t)n;
+  const int ntiles = lay.Nv * (lay.Nv + 1) / 2;
+  const int G = K * ntiles;
+  hipLaunchKernelGGL(k_matern<3>, dim3(G), dim3(256), 0, s, lay, (double*)nullptr, (int64_t)0, V,
+                     lay.mstride, locs, mp, tables, ntiles, G);
   return hipGetLastError();
 }
 

@@ -79,7 +79,8 @@ __device__ __forceinline__ double rho_eval(const MaternParams& P, const double* 
 // every other column, so each column store is one contiguous 1 KB run.
 
 // MODE 0: packed FP64 tiles (full diagonal tiles); MODE 1: column-major,
-// lower triangle only; MODE 2: packed FP64 tiles plus an FP32 copy.
+// lower triangle only; MODE 2: packed FP64 tiles plus an FP32 copy; MODE 3:
+// column-major, lower triangle only, FP32 only (C32; C is not written).
 template <int MODE>
 __device__ __forceinline__ void matern_tile(const MaternParams& P, const double* tab,
                                             const double* __restrict__ locs, int n, int I, int J,
@@ -93,7 +94,7 @@ __device__ __forceinline__ void matern_tile(const MaternParams& P, const double*
   const int cmax = min(T, n - J * T);
   for (int c = hh; c < cmax; c += 2) {
     const int gj = J * T + c;
-    if (MODE == 1 && gj > gi) continue;
+    if ((MODE == 1 || MODE == 3) && gj > gi) continue;
     double v;
     if (gi == gj) {
       v = 1.0 + P.nugget;
@@ -104,14 +105,14 @@ __device__ __forceinline__ void matern_tile(const MaternParams& P, const double*
       const double a = u1 * P.inv_phix, b = u2 * P.inv_phiy;
       v = rho_eval(P, tab, a * a + b * b);
     }
-    C[(int64_t)c * ldc + r] = v;
-    if (MODE == 2) C32[(int64_t)c * ldc + r] = (float)v;
+    if (MODE != 3) C[(int64_t)c * ldc + r] = v;
+    if (MODE == 2 || MODE == 3) C32[(int64_t)c * ldc + r] = (float)v;
   }
 }
 
 // One T x T tile (I, J) of V for one omega: the omega's table and the tile's
 // column coordinates are staged in smem (TABLE + 2T doubles).  C points at the
-// tile (leading dimension ldc); MODE 2 also writes C32.
+// tile (leading dimension ldc); MODE 2 also writes C32, MODE 3 only C32.
 template <int MODE>
 __device__ __forceinline__ void dev_matern_tile(const Lay& lay, const MaternParams& P,
                                                 const double* __restrict__ tab_g,

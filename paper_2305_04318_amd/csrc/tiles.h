@@ -651,14 +651,16 @@ __device__ __forceinline__ void dev_gemm_diag_border(const Lay& lay, double* bas
 //    W_rc -= L_rm W_mc for r > m, c < m; W_rm = -L_rm / L_mm; W_mm = 1/L_mm.
 // C (leading dimension ld) holds the tile's lower triangle.  MODE 0: L is
 // written back to C and W (FP64, ld T) to Wd.  MODE 1: C is read only and W is
-// written in FP32 to W32.  log|V| is added to *logdet_k; a non-positive pivot
-// sets *info_k and returns (uniformly).  smem: at least 5*T + 256 doubles.
+// written in FP32 to W32.  MODE 2: as MODE 1, and L is rounded to FP32 into
+// L32 (leading dimension ld32).  log|V| is added to *logdet_k; a non-positive
+// pivot sets *info_k and returns (uniformly).  smem: at least 5*T + 256
+// doubles.
 constexpr int POTRF_SMEM_DOUBLES = 5 * T + 256;
 
 template <int MODE>
 __device__ __forceinline__ void dev_potrf(const Lay& lay, double* C, int64_t ld, double* Wd,
                                           float* W32, double* logdet_k, int32_t* info_k, int J,
-                                          double* smem) {
+                                          double* smem, float* L32 = nullptr, int64_t ld32 = 0) {
   double (*bc0)[T] = reinterpret_cast<double (*)[T]>(smem);
   double (*bc1)[T] = reinterpret_cast<double (*)[T]>(smem + 2 * T);
   double* dinv = smem + 4 * T;
@@ -735,6 +737,15 @@ __device__ __forceinline__ void dev_potrf(const Lay& lay, double* C, int64_t ld,
       for (int cc = 0; cc < 8; ++cc) {
         const int r = 8 * bi + rr, c = 8 * bj + cc;
         if (r < nv && c < nv && r >= c) C[(int64_t)c * ld + r] = a[rr][cc];
+      }
+  }
+  if (MODE == 2 && low) {
+#pragma unroll
+    for (int rr = 0; rr < 8; ++rr)
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc) {
+        const int r = 8 * bi + rr, c = 8 * bj + cc;
+        if (r < nv && c < nv && r >= c) L32[(int64_t)c * ld32 + r] = (float)a[rr][cc];
       }
   }
   __syncthreads();

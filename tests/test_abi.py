@@ -99,14 +99,27 @@ def test_matern_and_chol_argument_errors():
     lib = pl.load()
     om = np.array([[1.0, 1.0, 0.1, 1.0, 0.0]])
     P = ctypes.c_void_p
-    assert lib.pl_matern_cov(None, 10, om.ctypes.data_as(P), 1, P(1), 10, P(1), 1 << 30, None) == -1
-    assert lib.pl_matern_cov(P(1), 0, om.ctypes.data_as(P), 1, P(1), 10, P(1), 1 << 30, None) == -2
-    assert lib.pl_matern_cov(P(1), 10, om.ctypes.data_as(P), 1, P(1), 5, P(1), 1 << 30, None) == -6
-    assert lib.pl_matern_cov(P(1), 10, om.ctypes.data_as(P), 1, P(1), 10, P(1), 8, None) == -8
-    assert lib.pl_chol_batched(None, 10, 1, 10, P(1), P(1), P(1), 1 << 30, None) == -1
-    assert lib.pl_chol_batched(P(1), 10, 1, 9, P(1), P(1), P(1), 1 << 30, None) == -4
-    assert lib.pl_chol_batched(P(1), 10, 1, 10, P(1), None, P(1), 1 << 30, None) == -6
-    assert lib.pl_chol_batched(P(1), 10, 1, 10, P(1), P(1), P(1), 8, None) == -8
+    O = om.ctypes.data_as(P)
+    F64, F32 = _lib.PL_F64, _lib.PL_F32
+    assert lib.pl_matern_cov(None, 10, O, 1, F64, P(1), 10, P(1), 1 << 30, None) == -1
+    assert lib.pl_matern_cov(P(1), 0, O, 1, F64, P(1), 10, P(1), 1 << 30, None) == -2
+    assert lib.pl_matern_cov(P(1), 10, O, 1, 2, P(1), 10, P(1), 1 << 30, None) == -5
+    assert lib.pl_matern_cov(P(1), 10, O, 1, F32, None, 10, P(1), 1 << 30, None) == -6
+    assert lib.pl_matern_cov(P(1), 10, O, 1, F32, P(1), 5, P(1), 1 << 30, None) == -7
+    assert lib.pl_matern_cov(P(1), 10, O, 1, F64, P(1), 10, P(1), 8, None) == -9
+    FP64, MIX = _lib.PL_FP64, _lib.PL_MIXED
+    assert lib.pl_chol_batched(None, 10, 1, 10, FP64, P(1), P(1), P(1), 1 << 30, None) == -1
+    assert lib.pl_chol_batched(P(8), 10, 1, 12, MIX, P(1), P(1), P(1), 1 << 30, None) == -1
+    assert lib.pl_chol_batched(P(1), 10, 1, 9, FP64, P(1), P(1), P(1), 1 << 30, None) == -4
+    assert lib.pl_chol_batched(P(16), 10, 1, 10, MIX, P(1), P(1), P(1), 1 << 30, None) == -4
+    assert lib.pl_chol_batched(P(16), 10, 1, 12, 5, P(1), P(1), P(1), 1 << 30, None) == -5
+    assert lib.pl_chol_batched(P(1), 10, 1, 10, FP64, P(1), None, P(1), 1 << 30, None) == -7
+    assert lib.pl_chol_batched(P(1), 10, 1, 10, FP64, P(1), P(1), P(1), 8, None) == -9
+    w64, wmx = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert lib.pl_chol_workspace_size(3, FP64, ctypes.byref(w64)) == 0
+    assert lib.pl_chol_workspace_size(3, MIX, ctypes.byref(wmx)) == 0
+    assert w64.value >= 3 * 128 * 128 * 8 and wmx.value >= 3 * 128 * 128 * 12
+    assert lib.pl_chol_workspace_size(3, 9, ctypes.byref(wmx)) == -2
 
 
 def test_opts_struct_layout():
