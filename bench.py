@@ -34,26 +34,37 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "block_column_update_hbm_traffi
 GEMM_SOURCES = ("common.h", "tiles.h", "chol.hip")
 
 
-def measured_traffic():
-    """HBM bytes per block-column update launch from the committed FETCH_SIZE/WRITE_SIZE
-    summary, or None when the kernel sources changed since it was taken."""
+COV_PROFILE = os.path.join(ROOT, "profiles", "covariance_build_aniso_n2000_K1024.md")
+COV_SOURCES = ("common.h", "matern_dev.h", "matern.hip")
+
+
+def profile_value(path, key, sources):
+    """A figure from the machine-readable lines of a committed rocprofv3
+    summary, or None when the kernel sources (sha256 over `sources`, in that
+    order) changed since the counters were taken."""
     import hashlib
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(path).read()
         want = {}
         for line in text.splitlines():
             k, _, v = line.strip().partition(": ")
-            if k in ("traffic_bytes_per_launch", "sources_sha256"):
+            if k in (key, "sources_sha256"):
                 want[k] = v.strip()
         h = hashlib.sha256()
-        for f in GEMM_SOURCES:
+        for f in sources:
             with open(os.path.join(ROOT, "paper_2305_04318_amd", "csrc", f), "rb") as fh:
                 h.update(fh.read())
         if h.hexdigest() != want.get("sources_sha256"):
             return None
-        return float(want["traffic_bytes_per_launch"])
+        return float(want[key])
     except (OSError, KeyError, ValueError):
         return None
+
+
+def measured_traffic():
+    """HBM bytes per block-column update launch from the committed FETCH_SIZE/WRITE_SIZE
+    summary, or None when the kernel sources changed since it was taken."""
+    return profile_value(TRAFFIC_PROFILE, "traffic_bytes_per_launch", GEMM_SOURCES)
 
 
 def log(msg):
@@ -74,6 +85,47 @@ def _oracle_point(k):
     pr = _CPU_PR
     with threadpool_limits(1):
         return k, oracle.profile_loglik(pr.locs, pr.y, pr.X, pr.omega[k:k + 1], pr.lam)["loglik"][0]
+
+
+def host_cpu():
+    """Host processor model and logical core count, as nproc and lscpu show them."""
+    import subprocess
+    model = ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if not model:
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        model = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count() or 1
+    return {"nproc": nproc, "model": model}
+
+
+def cpu_single_core(pr, n_omega):
+    """The oracle on one core (this process, one BLAS thread): points/s."""
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    t0 = time.perf_counter()
+    with threadpool_limits(1):
+        for k in range(n_omega):
+            oracle.profile_loglik(pr.locs, pr.y, pr.X, pr.omega[k:k + 1], pr.lam)
+    dt = time.perf_counter() - t0
+    return {"points_per_s": n_omega * pr.M / dt, "omega": n_omega, "seconds": dt}
 
 
 def cpu_baseline(pr, n_omega, workers):
@@ -169,6 +221,29 @@ def mixed_error(rec_mx, rec_64, n):
     return {"max_abs_dl": float(d.max()), "p99_abs_dl": _pct(d, 99), "median_abs_dl": _pct(d, 50),
             "frac_over_1e-2": float(np.mean(d > 1e-2)), "max_abs_dbeta": float(db.max()),
             "fallback_points": fb}
+
+
+GOLDEN = os.path.join(ROOT, "tests", "golden", "large_samples.json")
+
+
+def oracle_sample_error(rec, pr, name):
+    """Records of the sampled omega points against the oracle values stored in
+    tests/golden/large_samples.json (written by the oracle alone): max |dl|,
+    max |dl| / max(|l|, 1), and the sample size."""
+    import numpy as np
+    with open(GOLDEN) as f:
+        g = json.load(f)[name]
+    fp = g["fingerprint"]
+    if (pr.n, pr.p, pr.K, pr.M) != (fp["n"], fp["p"], fp["K"], fp["M"]) or \
+            abs(float(np.sum(pr.y)) - fp["sum_y"]) > 1e-12 * max(1.0, abs(fp["sum_y"])):
+        return None
+    idx = np.asarray(g["omega_index"])
+    ref = np.asarray(g["records"]["loglik"])
+    got = rec["loglik"][idx]
+    ok = np.asarray(g["records"]["info"]) == 0
+    d = np.abs(got - ref)[ok]
+    return {"oracle_points": int(ok.sum()), "oracle_max_abs_dl": float(d.max()),
+            "oracle_max_rel_dl": float((d / np.maximum(np.abs(ref[ok]), 1.0)).max())}
 
 
 def tune(pl, pr, tol=1e-3, sample=0):
@@ -281,9 +356,26 @@ def bench_serving(pl, seconds, rate, slots, budget_gib):
         s["failed_points"] = int(sum(np.sum((r.result["info"] != 0) &
                                             (r.result["info"] != pl.PL_INFO_FALLBACK))
                                      for r in done))
+        # the largest sustainable arrival rate: the first `cap_n` requests all
+        # present at time 0; the service rate at saturation bounds any stable rate
+        cap_n = min(len(probs), 120)
+        ex = sv.GpuExecutor(budget_gib << 30, slots=slots, max_request_work=48 << 30)
+        sat = [sv.Request(i, 0.0, pr.locs, pr.y, pr.X, pr.omega, pr.lam, prec)
+               for i, pr in enumerate(probs[:cap_n])]
+        t0 = time.perf_counter()
+        sv.Server(ex).run(sat)
+        span = time.perf_counter() - t0
+        ex.close()
+        del ex
+        torch.cuda.empty_cache()
+        s["max_sustainable_rate_per_s"] = cap_n / span
+        s["saturation_sample"] = (f"first {cap_n} requests of the stream, all present at t=0: "
+                                  f"{span:.2f} s")
+        s["stable"] = bool(rate < cap_n / span)
         out[prec] = s
         log(f"serving {prec}: p50 {s['p50_s'] * 1e3:.0f} ms p99 {s['p99_s'] * 1e3:.0f} ms "
-            f"{s['points_per_s']:.0f} points/s over {s['span_s']:.1f} s")
+            f"{s['points_per_s']:.0f} points/s over {s['span_s']:.1f} s; "
+            f"max sustainable {cap_n / span:.1f} req/s")
     return out
 
 
@@ -307,7 +399,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="omega points timed on the oracle (default 6 per worker)")
-    ap.add_argument("--cpu-workers", type=int, default=0, help="oracle processes (default min(16, cores))")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="oracle processes (default min(16, cores): 16 cores is the host "
+                         "share of one GPU on the measured boxes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=2000)
     ap.add_argument("--K", type=int, default=1024)
@@ -316,7 +410,7 @@ def main():
                     help="form of the headline steps (the metric is quoted on fp64)")
     ap.add_argument("--extras", default=",".join(EXTRAS),
                     help=f"comma list from {EXTRAS}, or 'none'")
-    ap.add_argument("--serve-seconds", type=float, default=8.0)
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device three times (the known-size "
@@ -348,7 +442,11 @@ def main():
         n_omega = args.cpu_sample or 6 * workers
         log(f"timing the oracle on {n_omega} omega points, {workers} processes")
         cb, cpu_ll = cpu_baseline(pr, n_omega, workers)
-        log(f"oracle {cb['value']:.1f} points/s")
+        cb["host"] = host_cpu()
+        cb["single_core"] = cpu_single_core(pr, 2)
+        log(f"oracle {cb['value']:.1f} points/s on {workers} processes, "
+            f"{cb['single_core']['points_per_s']:.1f} on one core "
+            f"(nproc {cb['host']['nproc']}, {cb['host']['model']})")
 
     import torch
 
@@ -436,13 +534,27 @@ def main():
         "kernel_ms_per_step": {c: round(v["ms"] / args.steps, 3) for c, v in prof.items()},
         "failed_points": int(np.sum(rec64["info"] != 0)),
     }
+    # covariance build: the VALU-bound row; algorithmic bytes are the stored
+    # lower triangle (8 B per element in FP64; the mixed form also stores 4 B)
+    mt = prof["matern"]["ms"] / args.steps / 1e3
+    if mt > 0:
+        elems = K * n * (n + 1) / 2.0
+        nbytes = elems * (8 if prec == "fp64" else 12)
+        line["covariance_build"] = {
+            "ms_per_step": mt * 1e3, "correlations_per_s": K * n * (n - 1) / 2.0 / mt,
+            "alg_bytes_per_step": nbytes, "gb_per_s": nbytes / mt / 1e9,
+            "hbm_frac": nbytes / mt / 8e12,
+            "valu_busy": (profile_value(COV_PROFILE, "valu_busy_frac", COV_SOURCES)
+                          if (prec == "fp64" and (n, K, M) == (2000, 1024, 8)) else None)}
     if cb is not None:
         k = cpu_ll.shape[0]
         ref = cpu_ll
-        err = float(np.max(np.abs(rec64["loglik"][:k] - ref) / np.maximum(np.abs(ref), n)))
+        err = float(np.max(np.abs(rec64["loglik"][:k] - ref) / np.maximum(np.abs(ref), 1.0)))
         line["cpu_baseline"] = cb
         line["oracle_max_rel_err"] = err
         log(f"max rel err vs oracle {err:.2e}")
+    if prec == "fp64" and (n, K, M) == (2000, 1024, 8):
+        line["vs_oracle_sample"] = oracle_sample_error(rec64, pr, "aniso_n2000")
 
     def guarded(name, fn):
         try:
@@ -456,6 +568,7 @@ def main():
         def mixed2000():
             st, rec = run_form(pl, pr, "mixed", args.steps, args.warmup)
             st.update(mixed_error(rec, rec64, n))
+            st["vs_oracle"] = oracle_sample_error(rec, pr, "aniso_n2000")
             st["autotune_tol_1e-3"] = tune(pl, pr)
             log(f"mixed n={n}: {st['ms_median']:.1f} ms, max |dl| {st['max_abs_dl']:.2e}")
             return st
@@ -469,9 +582,13 @@ def main():
             q = synth.config_mixed() if big == 4000 else synth.config_aniso(n=8000, K=256, M=8)
             res = {}
             s64, r64 = run_form(pl, q, "fp64", max(2, args.steps // 2), 1)
+            s64["vs_oracle"] = oracle_sample_error(r64, q, f"aniso_n{big}")
             res["fp64"] = s64
             smx, rmx = run_form(pl, q, "mixed", max(2, args.steps // 2), 1)
+            # error statistics over every point against the FP64 records (which
+            # match the oracle to 1e-8), and on the stored oracle sample itself
             smx.update(mixed_error(rmx, r64, q.n))
+            smx["vs_oracle"] = oracle_sample_error(rmx, q, f"aniso_n{big}")
             res["mixed"] = smx
             res["autotune_tol_1e-3"] = tune(pl, q, sample=64 if big == 8000 else 0)
             log(f"n={big}: fp64 {s64['ms_median']:.1f} ms, mixed {smx['ms_median']:.1f} ms, "

@@ -184,7 +184,7 @@ int pl_chol_batched(void* V, int64_t n, int64_t K, int64_t ld, int precision,
  *   xvx_inv  device, K*p*p doubles: (X^T V_k^-1 X)^-1 row-major at
  *            xvx_inv + k*p*p (NaN where it does not exist), or NULL.  With
  *            the records it gives the profiles of single coefficients and of
- *            sigma (Section 3.3, "Profile likelihood for beta_p" and "for
+ *            sigma (Section 3.4, "Profile likelihood for beta_p" and "for
  *            sigma"); see pl_profile_curves.
  *   opts     NULL for defaults
  *   work     device workspace, see pl_workspace_size
@@ -238,8 +238,8 @@ int pl_profile_loglik_noalloc(const double* locs, const double* y, const double*
 
 /*
  * Profile curves of sigma and of single regression coefficients from the
- * output of pl_profile_loglik (Section 3.3, the subsections "Profile
- * likelihood for beta_p" and "Profile likelihood for sigma", maximised over
+ * output of pl_profile_loglik (Sections 3.4 and 3.5, the profile
+ * likelihoods for beta_p and for sigma, maximised over
  * the evaluated points as in Step 6).  For every grid value the curve is the
  * maximum over the usable records (info 0 or PL_INFO_FALLBACK) of
  *   sigma:   -1/2 [SSR/sigma^2 + n log sigma^2 + log|V| + n log 2 pi]
@@ -276,7 +276,7 @@ int pl_profile_curves(const pl_result* rec, const double* beta_hat, const double
 /*
  * Univariate profile likelihood of one correlation parameter or of lambda
  * from the records of one pl_profile_loglik call, and its likelihood interval
- * (Step 4 of the method; Section 3.3, "Profile likelihood for correlation
+ * (Step 4 of the method; Section 3.6, "Profile likelihood for correlation
  * parameters"; the likelihood-based interval of Section 2).  Host arrays,
  * host computation (a few thousand points).
  *   which 0..4: column of omega (range, shape, nugget, ratio, angle).  The
@@ -306,7 +306,7 @@ int pl_profile_param(const pl_result* rec, int64_t K, int64_t M, const double* o
                      double* curve_y, int64_t* npts, double* interval, int32_t* open_ends);
 
 /*
- * Internal parameters of Step 2 (Section 3.3, "Reparameterization"):
+ * Internal parameters of Step 2 (Section 3.2, "Reparameterization"):
  *   omega' = (gamma1, kappa~, nu, gamma2, gamma3),
  *   gamma1 = log phi_X + log phi_Y (exp(gamma1/2) is the combined range),
  *   gamma2 = sqrt(phi_X/phi_Y - 1) cos(2 phi_A),
@@ -330,7 +330,7 @@ int pl_from_internal(const double* internal, int64_t K, int shape_transform, dou
 
 /*
  * Maximum-likelihood estimates of (omega, lambda) (Step 1 of the method,
- * Section 3.3: numerical maximisation of equation "profile", or with reml = 1
+ * Section 3.1: numerical maximisation of equation "profile", or with reml = 1
  * of the restricted profile log-likelihood of Appendix "remlpro").
  *
  * Batched compass search in the coordinates (gamma1, log kappa, log nu^2,
@@ -378,7 +378,7 @@ int pl_mle(const double* locs, const double* y, const double* X, int64_t n, int6
            void* work, size_t work_bytes, void* stream);
 
 /*
- * Representative parameter points (Step 2 of the method, Section 3.3,
+ * Representative parameter points (Step 2 of the method, Section 3.2,
  * "Hessian matrix" and "Obtaining representative points").
  *
  * pl_hessian: the Hessian H of l_p(omega', lambda_hat) in the internal

@@ -15,7 +15,7 @@ Every function is written from the paper's statement of the method:
     Step 3 sub-steps (Section 3.3),
   * the restricted (REML) profile log-likelihood of the Appendix,
   * the profile curves of sigma and of single regression coefficients
-    (Section 3.3, "Profile likelihood for beta_p" and "for sigma").
+    (Sections 3.4 and 3.5, the profile likelihoods for beta_p and for sigma).
 
 Readings of points where the paper is garbled or silent are listed in the
 project's design notes; the ones that change arithmetic are repeated where

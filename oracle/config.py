@@ -1,7 +1,7 @@
 """Representative parameter points of Step 2, FP64.  TEST INFRASTRUCTURE ONLY
 (see the package docstring).
 
-Section 3.3, "Hessian matrix": the Hessian of l_p(omega', lambda_hat) in the
+Section 3.2, "Hessian matrix": the Hessian of l_p(omega', lambda_hat) in the
 internal parameters omega' (oracle.mle), by numerical differentiation on
 51 points for the five-dimensional case and 33 for the four-dimensional one
 (shape held fixed), each at lambda_hat and lambda_hat +- delta -- the counts

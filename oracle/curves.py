@@ -2,7 +2,7 @@
 the cross products of Table "tab:tocpu".  TEST INFRASTRUCTURE ONLY (see the
 package docstring).
 
-Section 3.3, "Profile likelihood for beta_p": with beta_j fixed at b the other
+Section 3.4, "Profile likelihood for beta_p": with beta_j fixed at b the other
 coefficients and sigma take their closed-form maximum-likelihood values, and
 the residual quadratic form is assembled from rows and columns of ssqYX:
   (y' - X_j b)^T V^-1 (y' - X_j b)
@@ -12,7 +12,7 @@ the residual quadratic form is assembled from rows and columns of ssqYX:
                      G = (X^T V^-1 X)_-j,-j,
 SSR(b) is the first minus the second; sigma-hat^2 = SSR(b)/n and the
 likelihood is equation (2) at those values, i.e. equation "profile" with
-SSR(b) in place of SSR.  Section 3.3, "Profile likelihood for sigma": beta at
+SSR(b) in place of SSR.  Section 3.5, "Profile likelihood for sigma": beta at
 its MLE, sigma fixed (equation "profileSigma").  Both curves are maximised
 over the evaluated (omega_k, lambda_m), as in Step 6.
 """

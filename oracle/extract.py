@@ -2,7 +2,7 @@
 evaluated points, and likelihood intervals.  TEST INFRASTRUCTURE ONLY (see the
 package docstring).
 
-Section 3.3, "Profile likelihood for correlation parameters": for parameter
+Section 3.6, "Profile likelihood for correlation parameters": for parameter
 theta the point cloud is (theta_k, max over lambda of l_p(omega_k, lambda));
 the points on its upper convex hull are the best likelihoods and the profile
 curve interpolates them linearly.  For lambda the curve interpolates

@@ -1,7 +1,7 @@
 """Internal parameters of Step 2 and checks of a maximum-likelihood estimate,
 FP64.  TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-Section 3.3, "Reparameterization": the internal parameters are
+Section 3.2, "Reparameterization": the internal parameters are
   omega' = (gamma1, kappa~, nu, gamma2, gamma3),
   gamma1 = log phi_X + log phi_Y,
   gamma2 = sqrt(phi_X/phi_Y - 1) cos(2 phi_A),
@@ -15,7 +15,7 @@ gives the same scaled distance and so the same V.  The inverse follows from
 the definitions: phi_X/phi_Y = 1 + gamma2^2 + gamma3^2, phi_X phi_Y =
 exp(gamma1), 2 phi_A = the polar angle of (gamma2, gamma3).
 
-Step 1 (Section 3.3) is the numerical maximisation of the profile likelihood
+Step 1 (Section 3.1) is the numerical maximisation of the profile likelihood
 (equation "profile") over omega and lambda; the helpers below evaluate the
 objective at given points, by the oracle's likelihood, so that a maximiser's
 answer can be checked: its value, a brute-force grid it must beat, and the

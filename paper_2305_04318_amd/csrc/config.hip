@@ -1,4 +1,4 @@
-// Representative parameter points (Step 2 of the method, Section 3.3):
+// Representative parameter points (Step 2 of the method, Section 3.2):
 // a numerical Hessian of the profile log-likelihood in the internal
 // parameters, evaluated in one batched likelihood call; the eigen-repair of
 // minus the Hessian; points spread over the unit sphere (maximin) and mapped

@@ -1,5 +1,5 @@
 // Profile curves of sigma and of single regression coefficients from the
-// records of the path (Section 3.3: the subsections on the profile likelihood
+// records of the path (Sections 3.4 and 3.5: the profile likelihood
 // for beta_p and for sigma, and Step 6's maximisation over the evaluated
 // (omega, lambda) points).
 #include <math.h>

@@ -1,6 +1,6 @@
 // Univariate profile likelihoods of the correlation parameters and of lambda
 // from the evaluated points, and their likelihood intervals (Step 4 of the
-// method; Section 3.3, "Profile likelihood for correlation parameters";
+// method; Section 3.6, "Profile likelihood for correlation parameters";
 // Section 2's likelihood-based interval).  Host code: a few thousand points.
 #include <math.h>
 

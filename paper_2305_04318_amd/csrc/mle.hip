@@ -1,6 +1,6 @@
 // Maximum-likelihood estimates of (omega, lambda) by numerical maximisation of
-// the profile likelihood (Step 1 of the method, Section 3.3), and the internal
-// parametrisation of Step 2 (Section 3.3, "Reparameterization").  Host code
+// the profile likelihood (Step 1 of the method, Section 3.1), and the internal
+// parametrisation of Step 2 (Section 3.2, "Reparameterization").  Host code
 // driving pl_profile_loglik: every likelihood is evaluated on the device.
 //
 // The maximiser is a batched compass (coordinate pattern) search: each

@@ -12,6 +12,15 @@ request is never starved by smaller ones behind it.  Inputs and factors stay
 device-resident for the life of the request; a request whose full workspace
 would exceed the per-request cap runs its omega points in chunks.
 
+Failure handling.  A request may carry a deadline (seconds after its
+arrival): one still waiting for admission when its deadline passes is
+dropped unstarted ("expired").  Server.cancel(rid), callable from any
+thread, drops a waiting request at once and, for a request already on the
+device, discards its result when its kernels finish (work on the GPU is not
+interrupted; its memory and slot are released as usual).  Dropped requests
+are kept in Server.dropped with their status; run() returns the completed
+ones.
+
 The scheduler (Server) does not touch the device: it drives an executor
 through reserve/start/poll/finish/release, so its admission logic is tested
 on the CPU with a fake executor.  GpuExecutor is the device one.
@@ -40,10 +49,12 @@ class Request:
     omega: np.ndarray
     lam: np.ndarray
     precision: str = "fp64"
+    deadline: float = float("inf")   # admission deadline, seconds after arrival
     # filled in by the server
     admitted: float = float("nan")
     finished: float = float("nan")
     result: dict = field(default_factory=dict)
+    status: str = "pending"          # "done", "expired" or "cancelled" at the end
 
     @property
     def n(self) -> int:
@@ -120,11 +131,26 @@ class Server:
     admission by HBM footprint (see the module docstring)."""
 
     def __init__(self, executor, poll_sleep: float = 2e-4):
+        import threading
         self.ex = executor
         self.poll_sleep = poll_sleep
         self.trace = []          # (time, event, rid)
         self.max_inflight = 0
         self.peak_bytes = 0
+        self.dropped = []        # expired or cancelled requests
+        self._cancel = set()
+        self._lock = threading.Lock()
+
+    def cancel(self, rid) -> None:
+        """Drop request `rid`: unstarted, it never runs; on the device, its
+        result is discarded when it finishes.  Thread-safe."""
+        with self._lock:
+            self._cancel.add(rid)
+
+    def _take_cancels(self):
+        with self._lock:
+            c, self._cancel = self._cancel, set()
+        return c
 
     def run(self, requests, clock=time.perf_counter):
         """Serve `requests` (any order; arrival times relative to the start)
@@ -135,25 +161,49 @@ class Server:
                 raise ValueError(f"request {r.rid} (n={r.n}, K={r.K}) can never fit the HBM budget")
         queue, inflight, done = [], [], []
         free_slots = list(range(self.ex.slots))
+        cancelled = set()        # requests to drop, by id
         t0 = clock()
         i = 0
-        while len(done) < len(pending):
+
+        def drop(req, status, when):
+            req.status = status
+            req.finished = when
+            self.dropped.append(req)
+            self.trace.append((when, status, req.rid))
+
+        while len(done) + len(self.dropped) < len(pending):
             now = clock() - t0
             while i < len(pending) and pending[i].arrival <= now:
                 queue.append(pending[i])
                 self.trace.append((now, "arrive", pending[i].rid))
                 i += 1
+            cancelled |= self._take_cancels()
             progressed = False
+            # unstarted requests that were cancelled or outlived their deadline
+            for req in list(queue):
+                if req.rid in cancelled:
+                    queue.remove(req)
+                    drop(req, "cancelled", now)
+                    progressed = True
+                elif now > req.arrival + req.deadline:
+                    queue.remove(req)
+                    drop(req, "expired", now)
+                    progressed = True
             for h in list(inflight):
                 req, slot, tok, handle = h
                 if self.ex.poll(handle):
-                    req.result = self.ex.finish(handle)
+                    result = self.ex.finish(handle)
                     self.ex.release(tok)
-                    req.finished = clock() - t0
                     free_slots.append(slot)
                     inflight.remove(h)
-                    done.append(req)
-                    self.trace.append((req.finished, "finish", req.rid))
+                    if req.rid in cancelled:
+                        drop(req, "cancelled", clock() - t0)
+                    else:
+                        req.result = result
+                        req.status = "done"
+                        req.finished = clock() - t0
+                        done.append(req)
+                        self.trace.append((req.finished, "finish", req.rid))
                     progressed = True
             while queue and free_slots:
                 tok = self.ex.reserve(queue[0])

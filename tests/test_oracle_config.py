@@ -14,7 +14,7 @@ from oracle import mle as om
 # ---------------------------------------------------------------- oracle pins
 
 def test_stencil_sizes_are_the_papers_counts():
-    # Section 3.3: 51 x 3 likelihoods for the 5-D Hessian, 33 x 3 for 4-D
+    # Section 3.2: 51 x 3 likelihoods for the 5-D Hessian, 33 x 3 for 4-D
     assert oc.stencil(5).shape[0] == 51
     assert oc.stencil(4).shape[0] == 33
     assert len(oc.free_coords(False)) == 5 and len(oc.free_coords(True)) == 4
@@ -43,7 +43,7 @@ def test_central_hessian_exact_on_polynomials():
 
 
 def _internal_by_hand(om_row, shape_transform):
-    """The internal parameters written out from the definitions of Section 3.3
+    """The internal parameters written out from the definitions of Section 3.2
     (independent of oracle.mle): gamma1 = log phi_X + log phi_Y, kappa~, nu =
     sqrt(nu^2), gamma2/3 = sqrt(phi_X/phi_Y - 1) (cos, sin)(2 phi_A)."""
     phi_x, kappa, nug, ratio, ang = om_row

@@ -1,5 +1,5 @@
 """Pins of the oracle's sigma and single-coefficient profile curves
-(Section 3.3, "Profile likelihood for beta_p" and "for sigma")."""
+(Sections 3.4 and 3.5, the profile likelihoods for beta_p and for sigma)."""
 import math
 
 import numpy as np

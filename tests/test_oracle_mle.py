@@ -30,7 +30,7 @@ def _random_omega(rng, K):
 
 
 def test_combined_range_matches_paper_table():
-    # Section 3.3: exp(gamma1 / 2) is the combined range sqrt(phi_X phi_Y);
+    # Section 3.2: exp(gamma1 / 2) is the combined range sqrt(phi_X phi_Y);
     # the paper's tables print range, ratio and combined range side by side
     for name, (rng_x, combined, ratio, _sigma, nugget, _tau, *_angle_gammas) in _golden().items():
         w = om.to_internal([[rng_x, 1.0, nugget, ratio, 0.3]])[0]
@@ -57,7 +57,7 @@ def _gamma_range(ratio, angle, which):
 
 
 def test_gammas_match_paper_tables():
-    # Section 3.3 "Reparameterization": the Swiss and soil tables print the
+    # Section 3.2 "Reparameterization": the Swiss and soil tables print the
     # anisotropy ratio, the angle and the internal parameters aniso1 (gamma2)
     # and aniso2 (gamma3) of the same fit.  The printed gammas must lie in the
     # range that the printed (ratio, angle), within their rounding, give.

@@ -145,3 +145,44 @@ def test_server_rejects_request_over_budget():
     ex = FakeExecutor(4 * ALIGN, 2, {0: 5 * ALIGN}, {0: 0.0})
     with pytest.raises(ValueError):
         Server(ex).run([_req(0, 0.0)])
+
+
+def test_server_expires_requests_past_their_deadline():
+    """A request still waiting for memory when its admission deadline passes
+    is dropped unstarted; the others run."""
+    mem = {0: 6 * ALIGN, 1: 6 * ALIGN, 2: ALIGN}
+    dur = {0: 0.05, 1: 0.01, 2: 0.01}
+    ex = FakeExecutor(8 * ALIGN, 4, mem, dur)
+    srv = Server(ex)
+    r1 = _req(1, 0.001)
+    r1.deadline = 0.01            # request 0 holds the memory for 0.05 s
+    done = srv.run([_req(0, 0.0), r1, _req(2, 0.002)])
+    assert sorted(r.rid for r in done) == [0, 2]
+    assert [(r.rid, r.status) for r in srv.dropped] == [(1, "expired")]
+    assert r1.result == {} and np.isnan(r1.admitted)
+    assert all(r.status == "done" for r in done)
+    assert ex.arena.used == 0 and not ex.running
+
+
+def test_server_cancel_waiting_and_running_requests():
+    """Cancelling a queued request drops it unstarted; cancelling one on the
+    device discards its result once it finishes and frees its slot and
+    memory."""
+    import threading
+    mem = {0: 6 * ALIGN, 1: 6 * ALIGN, 2: ALIGN, 3: ALIGN}
+    dur = {0: 0.06, 1: 0.01, 2: 0.01, 3: 0.01}
+    ex = FakeExecutor(8 * ALIGN, 2, mem, dur)
+    srv = Server(ex, poll_sleep=1e-4)
+    reqs = [_req(0, 0.0), _req(1, 0.001), _req(2, 0.002), _req(3, 0.003)]
+    timer = threading.Timer(0.02, lambda: (srv.cancel(1), srv.cancel(0)))
+    timer.start()
+    done = srv.run(reqs)
+    timer.join()
+    st = {r.rid: r.status for r in srv.dropped}
+    assert st == {0: "cancelled", 1: "cancelled"}
+    assert sorted(r.rid for r in done) == [2, 3]
+    assert reqs[0].result == {} and not np.isnan(reqs[0].admitted)   # ran, result discarded
+    assert np.isnan(reqs[1].admitted)                                 # never started
+    assert ex.arena.used == 0 and not ex.running
+    s = latency_summary(done)
+    assert s["requests"] == 2
