@@ -254,15 +254,10 @@ def tune(pl, pr, tol=1e-3, sample=0):
     return {"choice": choice, "report": report, "sample": sample}
 
 
-def bench_uneven(pl, runs):
+def _run_batch(pl, probs, runs, **kw):
     import numpy as np
     import torch
-
-    import synth
-    t0 = time.perf_counter()
-    probs = synth.config_uneven()
-    log(f"uneven: generated {len(probs)} datasets in {time.perf_counter() - t0:.1f} s")
-    b = pl.batch.Batch(probs, probs[0].lam)
+    b = pl.batch.Batch(probs, probs[0].lam, **kw)
     b.run()
     torch.cuda.synchronize()
     err = b.error()
@@ -273,18 +268,54 @@ def bench_uneven(pl, runs):
         b.run()
         torch.cuda.synchronize()
         ts.append((time.perf_counter() - t0) * 1e3)
-    info = b.records()["info"].cpu().numpy()
+    rec = {k: v.cpu().numpy() for k, v in b.records().items()}
     med = float(np.median(ts))
     pts = b.units * probs[0].M
     flops = sum(p.K * p.n ** 3 / 3.0 for p in probs)
-    st = {"datasets": len(probs), "units": b.units, "tasks": b.tasks, "slabs": b.slabs,
-          "workspace_gib": b.work.numel() / 2 ** 30, "ms_median": med,
+    st = {"ms_median": med, "ms_p10": _pct(ts, 10), "ms_p90": _pct(ts, 90),
           "points_per_s": pts / (med / 1e3), "omega_per_s": b.units / (med / 1e3),
-          "chol_path_tflops": flops / (med / 1e3) / 1e12, "device_error": err,
-          "failed_points": int(np.sum(info[:, 0] != 0)), "precision": "fp64"}
+          "chol_path_tflops": flops / (med / 1e3) / 1e12,
+          "chol_path_frac_fp64_peak": flops / (med / 1e3) / 1e12 / PEAK_FP64_TFLOPS,
+          "workspace_gib": b.work.numel() / 2 ** 30, "device_error": err,
+          "failed_points": int(np.sum((rec["info"][:, 0] & ~pl.PL_INFO_FALLBACK) != 0)),
+          "fallback_points": int(np.sum((rec["info"][:, 0] & pl.PL_INFO_FALLBACK) != 0))}
+    if b.schedule == "persistent":
+        st.update({"tasks": b.tasks, "slabs": b.slabs})
+    else:
+        st.update({"passes": b.passes, "streams": b.lanes})
     b.close()
     del b
     torch.cuda.empty_cache()
+    return st, rec
+
+
+def bench_uneven(pl, runs):
+    import numpy as np
+    import torch
+
+    import synth
+    t0 = time.perf_counter()
+    probs = synth.config_uneven()
+    log(f"uneven: generated {len(probs)} datasets in {time.perf_counter() - t0:.1f} s")
+    st = {"datasets": len(probs), "units": sum(p.K for p in probs),
+          "points": sum(p.K for p in probs) * probs[0].M}
+    # the size-bucketed schedule in both forms (one graph launch each), then
+    # the persistent kernel (FP64)
+    s64, r64 = _run_batch(pl, probs, runs)
+    st["fp64"] = s64
+    log(f"uneven bucketed fp64: {s64['ms_median']:.0f} ms")
+    smx, rmx = _run_batch(pl, probs, runs, precision="mixed")
+    ok = r64["info"] == 0
+    d = np.abs(rmx["loglik"][ok] - r64["loglik"][ok])
+    smx.update({"max_abs_dl_vs_fp64": float(d.max()), "p99_abs_dl_vs_fp64": _pct(d, 99)})
+    st["mixed"] = smx
+    log(f"uneven bucketed mixed: {smx['ms_median']:.0f} ms, max |dl| {d.max():.2e}")
+    spe, rpe = _run_batch(pl, probs, runs, schedule="persistent")
+    spe["max_rel_diff_vs_bucketed"] = float(np.max(
+        np.abs(rpe["loglik"][ok] - r64["loglik"][ok]) / np.maximum(np.abs(r64["loglik"][ok]), 1)))
+    st["persistent_fp64"] = spe
+    log(f"uneven persistent fp64: {spe['ms_median']:.0f} ms")
+    pts = st["points"]
     # the same datasets as independent calls on four streams (the serving
     # executor with every request present at the start), in both forms
     from paper_2305_04318_amd import serve as sv

@@ -97,7 +97,8 @@ typedef struct pl_opts {
                            the persistent launch, microseconds; 0 = default
                            (PL_BATCH_WAIT_US).  A wait that outlives it makes
                            the launch drain without results (pl_batch_error)  */
-  int32_t reserved;
+  int32_t lanes;        /* pl_batch_create, size-bucketed schedule: streams the
+                           passes are spread over (1-16; 0 = 4)               */
 } pl_opts;
 
 #define PL_BATCH_WAIT_US 4000000  /* 4 s: far above any legitimate task wait */
@@ -105,6 +106,8 @@ typedef struct pl_opts {
 /* pl_opts.flags */
 #define PL_OPT_NO_FALLBACK 1  /* PL_MIXED: do not synchronise to redo FP32
                                  breakdowns in FP64 (they keep info > 0)        */
+#define PL_OPT_BATCH_PERSISTENT 2  /* pl_batch_create: the persistent-kernel
+                                      schedule (PL_FP64 only)                   */
 
 /* Library version string. */
 const char* pl_version(void);
@@ -499,9 +502,16 @@ int pl_autotune(const double* locs, const double* y, const double* X, int64_t n,
 
 /*
  * Many independent datasets of uneven size (each with its own omega points)
- * in one persistent launch (Section 3.3's Step 3 per (dataset, omega) unit;
- * the paper's memory-bounded chunking of parameter sets, Section 3.3, becomes
- * a pool of recycled matrix slabs).
+ * evaluated by one graph launch (Section 3.3's Step 3 per (dataset, omega)
+ * unit; the paper's memory-bounded chunking of parameter sets, Section 3.3,
+ * becomes passes over workspace regions that are reused).  Two schedules:
+ *   size-bucketed (default; PL_FP64 or PL_MIXED): units grouped by their
+ *     number of 128-row tiles run through the step kernels of
+ *     pl_profile_loglik in passes of many units, each unit with its own n;
+ *     the passes are spread over opts->lanes streams (largest first, to the
+ *     least loaded), all captured into one HIP graph;
+ *   persistent (PL_OPT_BATCH_PERSISTENT, PL_FP64): one persistent kernel
+ *     pulls tile tasks from a queue, units recycling a pool of matrix slabs.
  *
  * One dataset: locs (device, n x 2 row-major), y (device, n, > 0), X (device,
  * n x p column-major), omega (host, K x 5), all shared lambda values.
@@ -520,18 +530,25 @@ typedef struct pl_dataset {
 typedef struct pl_batch pl_batch;
 
 /*
- * Build a plan on the host (no GPU call).  opts->chunk, when > 0, caps the
- * number of matrix slabs (default min(units, 2048)); only PL_FP64 is
- * supported.  The plan keeps the dataset pointers, which must stay valid.
+ * Build a plan on the host (no GPU call).  opts (NULL for defaults):
+ * precision, refine, flush and PL_OPT_NO_FALLBACK as for pl_profile_loglik;
+ * PL_OPT_BATCH_PERSISTENT selects the persistent schedule; opts->chunk, when
+ * > 0, caps the units per pass (size-bucketed; default: as many as fit
+ * 4 GiB) or the number of matrix slabs (persistent; default min(units,
+ * 2048)); opts->lanes, opts->wait_us as documented in pl_opts.  The plan
+ * keeps the dataset pointers, which must stay valid.
  * Errors: -1 datasets NULL or a dataset invalid (n < 2, n <= p, pointers
  * NULL, K < 1, omega out of domain), -2 D out of range, -3 p out of range,
- * -4 lambda NULL or not finite, -5 M out of range, -6 bad option, -7 plan NULL;
- * PL_E_UNSUPPORTED if the task list cannot be built.
+ * -4 lambda NULL or not finite, -5 M out of range, -6 bad option (including
+ * PL_MIXED with the persistent schedule), -7 plan NULL; PL_E_UNSUPPORTED if
+ * the task list cannot be built or PL_MIXED has M + p > 32.
  */
 int pl_batch_create(const pl_dataset* datasets, int64_t D, int64_t p, const double* lambda,
                     int64_t M, const pl_opts* opts, pl_batch** plan);
 int pl_batch_workspace_size(const pl_batch* plan, size_t* bytes);
-/* Units (sum of K over datasets), tasks and slabs of a plan (NULL to skip). */
+/* Units (sum of K over datasets), tasks and slabs of a plan (NULL to skip):
+ * persistent: tile tasks and matrix slabs; size-bucketed: device passes and
+ * streams. */
 int pl_batch_stats(const pl_batch* plan, int64_t* units, int64_t* tasks, int64_t* slabs);
 /*
  * Evaluate every record: out (device) receives sum_d K_d * M records, dataset
@@ -539,6 +556,8 @@ int pl_batch_stats(const pl_batch* plan, int64_t* units, int64_t* tasks, int64_t
  * record.  The first call (and any call with a different work, out or
  * beta_hat) uploads the plan into the workspace and captures the launch
  * sequence into a HIP graph; every call then launches that graph on `stream`.
+ * PL_MIXED without PL_OPT_NO_FALLBACK then synchronises `stream` once and
+ * redoes FP32 breakdowns with the FP64 form (info |= PL_INFO_FALLBACK).
  * Errors: -1 plan NULL, -2 out NULL, -4 work NULL, -5 work too small, PL_E_HIP.
  */
 int pl_batch_run(pl_batch* plan, pl_result* out, double* beta_hat, void* work, size_t work_bytes,

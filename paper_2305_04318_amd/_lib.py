@@ -37,10 +37,11 @@ class PlOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("refine", ctypes.c_int32),
                 ("chunk", ctypes.c_int64), ("flags", ctypes.c_int32),
                 ("flush", ctypes.c_int32), ("wait_us", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("lanes", ctypes.c_int32)]
 
 
 PL_OPT_NO_FALLBACK = 1
+PL_OPT_BATCH_PERSISTENT = 2
 
 
 class PlDataset(ctypes.Structure):

@@ -1,4 +1,6 @@
-"""Uneven batches of datasets in one persistent launch (pl_batch_* of the C ABI)."""
+"""Uneven batches of datasets evaluated by one graph launch (pl_batch_* of the
+C ABI): the size-bucketed schedule (FP64 or mixed) or the persistent kernel
+(FP64)."""
 from __future__ import annotations
 
 import ctypes
@@ -13,9 +15,14 @@ from .api import Inputs, _host_f64, _opts, _stream_ptr, unpack_records
 
 class Batch:
     """A plan over many datasets; run() evaluates every (dataset, omega, lambda)
-    record with one graph launch (a persistent kernel plus small prologue)."""
+    record with one graph launch.  schedule "bucketed" (default): units grouped
+    by tile count run the step kernels in passes of at most `chunk` units
+    (0: as many as fit 4 GiB) spread over `lanes` streams; "persistent": one
+    persistent kernel over a pool of `max_slabs` matrix slabs (FP64 only)."""
 
-    def __init__(self, problems, lam, device="cuda", max_slabs=0, inputs=None, wait_us=0):
+    def __init__(self, problems, lam, device="cuda", max_slabs=0, inputs=None, wait_us=0,
+                 precision="fp64", schedule="bucketed", lanes=0, chunk=0, flush=0, refine=1,
+                 fallback=True):
         lib = load()
         self.device = device
         self.inputs = inputs if inputs is not None else [
@@ -32,8 +39,15 @@ class Batch:
             arr[i] = PlDataset(inp.locs.data_ptr(), inp.y.data_ptr(), inp.Xc.data_ptr(), inp.n,
                                om.ctypes.data, om.shape[0])
         self._arr = arr
-        o = _opts("fp64", max_slabs)
+        if schedule not in ("bucketed", "persistent"):
+            raise ValueError(f"unknown schedule {schedule!r}")
+        self.schedule, self.precision = schedule, precision
+        persistent = schedule == "persistent"
+        o = _opts(precision, max_slabs if persistent else chunk, refine, fallback, flush)
         o.wait_us = int(wait_us)  # limit of one task wait (0: the library's default)
+        o.lanes = int(lanes)
+        if persistent:
+            o.flags |= _lib.PL_OPT_BATCH_PERSISTENT
         h = ctypes.c_void_p()
         check(lib.pl_batch_create(arr, D, self.p, self.lam.ctypes.data_as(ctypes.c_void_p),
                                   self.lam.shape[0], ctypes.byref(o), ctypes.byref(h)),
@@ -46,6 +60,8 @@ class Batch:
         check(lib.pl_batch_stats(h, ctypes.byref(u), ctypes.byref(t), ctypes.byref(s)),
               "pl_batch_stats")
         self.units, self.tasks, self.slabs = u.value, t.value, s.value
+        # size-bucketed: device passes and streams
+        self.passes, self.lanes = (0, 0) if persistent else (t.value, s.value)
         M = self.lam.shape[0]
         self.offsets = np.concatenate([[0], np.cumsum([om.shape[0] for om in self.omegas])])
         self.out = torch.empty((self.units, M, 10), dtype=torch.float64, device=device)

@@ -33,7 +33,9 @@ bool omega_ok(const double* om) {
          om[3] > 0.0;
 }
 
-Lay packed_layout(int64_t n, int64_t q) {
+}  // namespace
+
+Lay plk::packed_layout(int64_t n, int64_t q) {
   Lay lay{};
   lay.kind = 0;
   lay.n = (int)n;
@@ -43,6 +45,8 @@ Lay packed_layout(int64_t n, int64_t q) {
   lay.mstride = packed_stride(lay.Nv, lay.TB);
   return lay;
 }
+
+namespace {
 
 size_t per_omega_bytes(const Lay& lay) {
   return align_up(lay.mstride * sizeof(double)) + align_up((size_t)T * T * sizeof(double)) +
@@ -57,7 +61,7 @@ int64_t v_stride64(const Lay& lay) { return (int64_t)lay.Nv * (lay.Nv + 1) / 2 *
 size_t per_omega_bytes_mixed(const Lay& lay) {
   return align_up(lay.mstride * sizeof(float)) + align_up(v_stride64(lay) * sizeof(double)) +
          align_up((size_t)lay.Nv * T * T * sizeof(float)) + align_up((size_t)T * T * sizeof(double)) +
-         align_up((size_t)lay.n * lay.TB * sizeof(double)) +
+         align_up((size_t)x0_stride(lay) * sizeof(double)) +
          align_up((size_t)lay.Nv * (lay.Nv + 1) / 2 * lay.TB * lay.TB * sizeof(double)) + 2 * ALIGN;
 }
 
@@ -100,6 +104,7 @@ struct Prof {
   }
 };
 Prof g_prof;
+bool g_prof_paused_on = false;  // timing was on when paused
 
 // Runs `launch`, bracketed by events on stream s when profiling is on.
 template <class F>
@@ -130,6 +135,128 @@ double gemm_col_flops(const Lay& lay, int J, int nI) {
 }
 
 }  // namespace
+
+bool plk::profiling_pause(bool pause) {
+  const bool was = pause ? g_prof.on : g_prof_paused_on;
+  if (pause) {
+    g_prof_paused_on = g_prof.on;
+    g_prof.on = false;
+  } else {
+    g_prof.on = g_prof_paused_on;
+    g_prof_paused_on = false;
+  }
+  return was;
+}
+
+// Per-pass buffers for kc omega points of layout lay, carved from base.
+PassBufs plk::carve_pass(char* base, const Lay& lay, bool mixed, int64_t kc) {
+  Carve cv{base};
+  PassBufs b{};
+  if (!mixed) {
+    b.mats = cv.take<double>((size_t)kc * lay.mstride * sizeof(double));
+    b.W = cv.take<double>((size_t)kc * T * T * sizeof(double));
+  } else {
+    b.m32 = cv.take<float>((size_t)kc * lay.mstride * sizeof(float));
+    b.m64 = cv.take<double>((size_t)kc * v_stride64(lay) * sizeof(double));
+    b.W32 = cv.take<float>((size_t)kc * lay.Nv * T * T * sizeof(float));
+    b.dscr = cv.take<double>((size_t)kc * T * T * sizeof(double));
+    b.x0 = cv.take<double>((size_t)kc * x0_stride(lay) * sizeof(double));
+    b.slots = cv.take<double>((size_t)kc * lay.Nv * (lay.Nv + 1) / 2 * lay.TB * lay.TB *
+                              sizeof(double));
+  }
+  b.logdet = cv.take<double>((size_t)kc * sizeof(double));
+  b.info = cv.take<int32_t>((size_t)kc * sizeof(int32_t));
+  b.bytes = cv.off;
+  return b;
+}
+
+size_t plk::pass_bytes(const Lay& lay, bool mixed, int64_t kc) {
+  return (size_t)kc * (mixed ? per_omega_bytes_mixed(lay) : per_omega_bytes(lay));
+}
+
+// Steps 1-8 of Section 3.3 for kk omega points sharing one layout: the
+// bordered right-hand sides, the covariance tiles, the bordered blocked
+// Cholesky (FP64, or the mixed form with its back substitution and refined
+// cross products), the p x p stage.  Records go to a.out (omega k at
+// a.out + k M, or at its UnitInfo index in an uneven batch).
+hipError_t plk::run_pass(const PassArgs& a, const PassBufs& b, int kk, hipStream_t s) {
+  const Lay& lay = a.lay;
+  hipError_t e = timed(PL_KC_OTHER, 0.0, s, [&] {
+    hipError_t r = a.mixed ? launch_border_init_f32(lay, b.m32, a.rhs, kk, s)
+                           : launch_border_init(lay, b.mats, a.rhs, kk, s);
+    if (r == hipSuccess) r = launch_fill(b.logdet, 0.0, kk, s);
+    if (r == hipSuccess) r = launch_fill_i32(b.info, 0, kk, s);
+    return r;
+  });
+  if (e != hipSuccess) return e;
+  e = timed(PL_KC_MATERN, 0.0, s, [&] {
+    return a.mixed ? launch_matern_mixed(lay, b.m64, v_stride64(lay), b.m32, a.locs, a.mp,
+                                         a.tables, kk, s)
+                   : launch_matern_packed(lay, b.mats, a.locs, a.mp, a.tables, kk, s);
+  });
+  if (e != hipSuccess) return e;
+  if (!a.mixed) {
+    // per block column: the update of every tile of the column (the bordered
+    // row folded into the diagonal tile's workgroup), the diagonal tile's
+    // factor and inverse, the panel solve; the bordered row's own block
+    // closes the factorisation
+    for (int J = 0; J <= lay.Nv; ++J) {
+      if (J < lay.Nv) {
+        if (J > 0) {
+          e = timed(PL_KC_GEMM, kk * gemm_col_flops(lay, J, lay.Nv - J + 1), s,
+                    [&] { return launch_col_update(lay, b.mats, b.info, J, kk, s); });
+          if (e != hipSuccess) return e;
+        }
+        e = timed(PL_KC_POTRF, 0.0, s,
+                  [&] { return launch_potrf(lay, b.mats, b.W, b.logdet, b.info, J, kk, s); });
+        if (e != hipSuccess) return e;
+        e = timed(PL_KC_TRSM, 0.0, s,
+                  [&] { return launch_trsm(lay, b.mats, b.W, b.info, J, lay.Nv - J, kk, s); });
+        if (e != hipSuccess) return e;
+      } else {
+        e = timed(PL_KC_GEMM, kk * gemm_col_flops(lay, J, 1), s, [&] {
+          return lay.TB <= 32 ? launch_border_block(lay, b.mats, b.info, kk, s)
+                              : launch_gemm_col(lay, b.mats, b.info, J, 1, kk, s);
+        });
+        if (e != hipSuccess) return e;
+      }
+    }
+  } else {
+    for (int J = 0; J < lay.Nv; ++J) {
+      // J = 0 has no update: the diagonal kernel then copies V's FP64 tile
+      const int nI = (J == 0) ? 1 : lay.Nv - J + 1;
+      e = timed(PL_KC_GEMM, kk * gemm_col_flops(lay, J, nI), s, [&] {
+        return launch_gemm_col_mx(lay, b.m32, b.m64, v_stride64(lay), b.dscr, b.info, J, nI, kk,
+                                  a.flush, s);
+      });
+      if (e != hipSuccess) return e;
+      e = timed(PL_KC_POTRF, 0.0, s,
+                [&] { return launch_potrf_mx(lay, b.dscr, b.W32, b.logdet, b.info, J, kk, s); });
+      if (e != hipSuccess) return e;
+      e = timed(PL_KC_TRSM, 0.0, s,
+                [&] { return launch_trsm_mx(lay, b.m32, b.W32, b.info, J, lay.Nv - J, kk, s); });
+      if (e != hipSuccess) return e;
+    }
+    e = timed(PL_KC_OTHER, 0.0, s, [&] {
+      hipError_t r = launch_backsolve(lay, b.m32, b.W32, b.info, b.x0, kk, s);
+      if (r == hipSuccess)
+        r = launch_qform(lay, b.m64, v_stride64(lay), b.x0, a.rhs, b.info, b.slots, a.refine, kk,
+                         s);
+      return r;
+    });
+    if (e != hipSuccess) return e;
+  }
+  return timed(PL_KC_OTHER, 0.0, s, [&] {
+    hipError_t r = hipSuccess;
+    if (a.mixed) r = launch_slot_reduce(lay, b.slots, b.dscr, (int64_t)T * T, kk, s);
+    if (r == hipSuccess)
+      r = launch_finalize(lay, b.mats, a.mixed ? b.dscr : nullptr, (int64_t)T * T, b.logdet,
+                          b.info, a.jac, a.yflags, a.lam, lay.n, a.p, a.M, kk, a.out, a.beta,
+                          a.xvx, s);
+    if (r == hipSuccess && a.info_out) r = launch_copy_i32(b.info, a.info_out, kk, s);
+    return r;
+  });
+}
 
 // Constants for one omega = (phi_X, kappa, nu^2, phi_R, phi_A); phi_Y = phi_X / phi_R.
 MaternParams plk::make_matern_params(const double* om) {
@@ -364,28 +491,7 @@ int pl_profile_loglik(const double* locs, const double* y, const double* X, int6
   double* jac = cv.take<double>(sizeof(double));
   int32_t* yflags = cv.take<int32_t>(sizeof(int32_t));
   int32_t* info_all = cv.take<int32_t>(K * sizeof(int32_t));
-  // per-chunk buffers
-  double* mats = nullptr;
-  double* W = nullptr;
-  float* m32 = nullptr;
-  double* m64 = nullptr;
-  float* W32 = nullptr;
-  double* dscr = nullptr;
-  double* x0 = nullptr;
-  double* slots = nullptr;
-  if (!mixed) {
-    mats = cv.take<double>((size_t)kc * lay.mstride * sizeof(double));
-    W = cv.take<double>((size_t)kc * T * T * sizeof(double));
-  } else {
-    m32 = cv.take<float>((size_t)kc * lay.mstride * sizeof(float));
-    m64 = cv.take<double>((size_t)kc * v_stride64(lay) * sizeof(double));
-    W32 = cv.take<float>((size_t)kc * lay.Nv * T * T * sizeof(float));
-    dscr = cv.take<double>((size_t)kc * T * T * sizeof(double));
-    x0 = cv.take<double>((size_t)kc * n * lay.TB * sizeof(double));
-    slots = cv.take<double>((size_t)kc * lay.Nv * (lay.Nv + 1) / 2 * lay.TB * lay.TB * sizeof(double));
-  }
-  double* logdet = cv.take<double>((size_t)kc * sizeof(double));
-  int32_t* info = cv.take<int32_t>((size_t)kc * sizeof(int32_t));
+  const PassBufs pb = carve_pass(cv.base + cv.off, lay, mixed, kc);
 
   std::vector<MaternParams> hp(K);
   for (int64_t k = 0; k < K; ++k) hp[k] = make_matern_params(omega + 5 * k);
@@ -398,73 +504,27 @@ int pl_profile_loglik(const double* locs, const double* y, const double* X, int6
     return launch_boxcox_rhs(y, X, lam_d, (int)n, (int)p, (int)M, rhs, jac, yflags, s);
   }));
 
+  PassArgs pa{};
+  pa.lay = lay;
+  pa.mixed = mixed;
+  pa.flush = flush;
+  pa.refine = refine;
+  pa.locs = locs;
+  pa.rhs = rhs;
+  pa.jac = jac;
+  pa.yflags = yflags;
+  pa.lam = lam_d;
+  pa.p = (int)p;
+  pa.M = (int)M;
   for (int64_t c0 = 0; c0 < K; c0 += kc) {
     const int kk = (int)std::min<int64_t>(kc, K - c0);
-    PL_CHECK(timed(PL_KC_OTHER, 0.0, s, [&] {
-      hipError_t e = mixed ? launch_border_init_f32(lay, m32, rhs, kk, s)
-                           : launch_border_init(lay, mats, rhs, kk, s);
-      if (e == hipSuccess) e = launch_fill(logdet, 0.0, kk, s);
-      if (e == hipSuccess) e = launch_fill_i32(info, 0, kk, s);
-      return e;
-    }));
-    PL_CHECK(timed(PL_KC_MATERN, 0.0, s, [&] {
-      return mixed ? launch_matern_mixed(lay, m64, v_stride64(lay), m32, locs, mp + c0,
-                                         tables + c0 * TABLE, kk, s)
-                   : launch_matern_packed(lay, mats, locs, mp + c0, tables + c0 * TABLE, kk, s);
-    }));
-    if (!mixed) {
-      // per block column: the update of every tile of the column (the
-      // bordered row folded into the diagonal tile's workgroup), the
-      // diagonal tile's factor and inverse, the panel solve; the bordered
-      // row's own block closes the factorisation
-      for (int J = 0; J <= lay.Nv; ++J) {
-        if (J < lay.Nv) {
-          if (J > 0)
-            PL_CHECK(timed(PL_KC_GEMM, kk * gemm_col_flops(lay, J, lay.Nv - J + 1), s,
-                           [&] { return launch_col_update(lay, mats, info, J, kk, s); }));
-          PL_CHECK(timed(PL_KC_POTRF, 0.0, s,
-                         [&] { return launch_potrf(lay, mats, W, logdet, info, J, kk, s); }));
-          PL_CHECK(timed(PL_KC_TRSM, 0.0, s,
-                         [&] { return launch_trsm(lay, mats, W, info, J, lay.Nv - J, kk, s); }));
-        } else {
-          PL_CHECK(timed(PL_KC_GEMM, kk * gemm_col_flops(lay, J, 1), s, [&] {
-            return lay.TB <= 32 ? launch_border_block(lay, mats, info, kk, s)
-                                : launch_gemm_col(lay, mats, info, J, 1, kk, s);
-          }));
-        }
-      }
-    } else {
-      for (int J = 0; J < lay.Nv; ++J) {
-        // J = 0 has no update: the diagonal kernel then copies V's FP64 tile
-        const int nI = (J == 0) ? 1 : lay.Nv - J + 1;
-        PL_CHECK(timed(PL_KC_GEMM, kk * gemm_col_flops(lay, J, nI), s, [&] {
-          return launch_gemm_col_mx(lay, m32, m64, v_stride64(lay), dscr, info, J, nI, kk, flush,
-                                    s);
-        }));
-        PL_CHECK(timed(PL_KC_POTRF, 0.0, s,
-                       [&] { return launch_potrf_mx(lay, dscr, W32, logdet, info, J, kk, s); }));
-        PL_CHECK(timed(PL_KC_TRSM, 0.0, s,
-                       [&] { return launch_trsm_mx(lay, m32, W32, info, J, lay.Nv - J, kk, s); }));
-      }
-      PL_CHECK(timed(PL_KC_OTHER, 0.0, s, [&] {
-        hipError_t e = launch_backsolve(lay, m32, W32, info, x0, kk, s);
-        if (e == hipSuccess)
-          e = launch_qform(lay, m64, v_stride64(lay), x0, rhs, info, slots, refine, kk, s);
-        return e;
-      }));
-    }
-    PL_CHECK(timed(PL_KC_OTHER, 0.0, s, [&] {
-      hipError_t e = hipSuccess;
-      if (mixed) e = launch_slot_reduce(lay, slots, dscr, (int64_t)T * T, kk, s);
-      if (e == hipSuccess)
-        e = launch_finalize(lay, mats, mixed ? dscr : nullptr, (int64_t)T * T, logdet, info, jac,
-                            yflags, lam_d, (int)n,
-                                     (int)p, (int)M, kk, out + c0 * M,
-                                     beta_hat ? beta_hat + c0 * M * p : nullptr,
-                                     xvx_inv ? xvx_inv + c0 * p * p : nullptr, s);
-      if (e == hipSuccess) e = launch_copy_i32(info, info_all + c0, kk, s);
-      return e;
-    }));
+    pa.mp = mp + c0;
+    pa.tables = tables + c0 * TABLE;
+    pa.out = out + c0 * M;
+    pa.beta = beta_hat ? beta_hat + c0 * M * p : nullptr;
+    pa.xvx = xvx_inv ? xvx_inv + c0 * p * p : nullptr;
+    pa.info_out = info_all + c0;
+    PL_CHECK(run_pass(pa, pb, kk, s));
   }
 
   if (mixed && !(flags & PL_OPT_NO_FALLBACK)) {

@@ -1,23 +1,34 @@
-// Many independent datasets of uneven size in one persistent launch.
+// Many independent datasets of uneven size, evaluated by one graph launch.
 //
 // Every (dataset d, omega k) pair is a unit: Step 3 of Section 3.3 for one V.
-// A unit's work is cut into tile tasks grouped in phases that must run in
-// order (bordering + covariance tiles; then, per block column J, the
-// left-looking updates, the diagonal factor, the panel solves; the final
-// Schur tile; the p x p stage).  The host lists all tasks so that every task
-// depends only on tasks listed before it; one persistent kernel (grid = the
-// number of resident workgroups) pops tasks from an atomic queue, waits until
-// its unit has completed the earlier phases (a per-unit completion counter),
-// runs the task and counts it done.  A task popped earlier is held by a
-// running workgroup whose own dependencies were listed earlier still, so the
-// queue drains.  Units recycle a pool of matrix slabs: a unit's first phase
-// also waits for the previous user of its slab.  Every wait is bounded by wall
-// time (the device's constant-rate counter): a wait that outlives its limit
-// sets an error flag, after which every wait returns at once and every task
-// skips its work, so the kernel always drains and terminates.
+// Two schedules share the plan interface.
 //
-// The launch sequence (counter resets, omega tables, Box-Cox right-hand
-// sides, the persistent kernel) is captured once into a HIP graph and replayed.
+// Size-bucketed (the default; FP64 or mixed).  Units are grouped by their
+// number of tile rows Nv; a group's units run through the same step kernels
+// as pl_profile_loglik in passes of many units at once, each unit with its
+// own order n, locations and right-hand sides (UnitInfo), so one launch of
+// a step kernel covers the units of one pass whatever their datasets.  The
+// passes are spread over a few streams (largest first, to the least loaded
+// stream); each stream reuses its own workspace region pass after pass.
+// The whole sequence -- omega tables, Box-Cox right-hand sides of every
+// dataset, then every stream's passes, forked from and joined back to the
+// caller's stream -- is captured once into a HIP graph and replayed.
+//
+// Persistent (FP64, on request).  A unit's work is cut into tile tasks
+// grouped in phases that must run in order (bordering + covariance tiles;
+// then, per block column J, the left-looking updates, the diagonal factor,
+// the panel solves; the final Schur tile; the p x p stage).  The host lists
+// all tasks so that every task depends only on tasks listed before it; one
+// persistent kernel (grid = the number of resident workgroups) pops tasks
+// from an atomic queue, waits until its unit has completed the earlier
+// phases (a per-unit completion counter), runs the task and counts it done.
+// A task popped earlier is held by a running workgroup whose own
+// dependencies were listed earlier still, so the queue drains.  Units
+// recycle a pool of matrix slabs: a unit's first phase also waits for the
+// previous user of its slab.  Every wait is bounded by wall time (the
+// device's constant-rate counter): a wait that outlives its limit sets an
+// error flag, after which every wait returns at once and every task skips
+// its work, so the kernel always drains and terminates.
 #include <string.h>
 
 #include <algorithm>
@@ -234,6 +245,13 @@ __global__ void k_zero_i32(int32_t* p, int64_t n) {
 using namespace plk;
 
 // ---- host side -------------------------------------------------------------------
+// One pass of the size-bucketed schedule: units [u0, u0 + cnt) of the sorted
+// unit list (one group, so one Nv), run on stream `lane`.
+struct BPass {
+  int32_t u0, cnt, lane, nmax;
+  double cost;
+};
+
 struct pl_batch {
   // inputs (host copies)
   std::vector<BDataset> ds;
@@ -241,15 +259,26 @@ struct pl_batch {
   std::vector<BTask> tasks;
   std::vector<MaternParams> params;
   std::vector<double> lam;
+  std::vector<double> omega;     // natural omega of every unit, record order (K x 5)
   int32_t p = 0, M = 0, q = 0, TB = 0;
-  int32_t wait_us = 0;  // limit of one task wait
+  bool persistent = false, mixed = false, fallback = true;
+  int32_t flush = MX_FLUSH, refine = 1;
+  int32_t wait_us = 0;  // persistent: limit of one task wait
   int64_t n_omega = 0, nslabs = 0, slab_stride = 0, w_off = 0;
+  // size-bucketed schedule: units sorted by Nv (descending), their records
+  std::vector<UnitInfo> uinfo;   // sorted order; locs pointers, rhs offsets, record index
+  std::vector<int32_t> order;    // sorted position -> record (unit) index
+  std::vector<BPass> passes;
+  int32_t lanes = 0;
+  size_t region = 0;             // workspace bytes of one stream
   // workspace layout (bytes)
   size_t off_tasks, off_units, off_ds, off_mp, off_nodes, off_tables, off_lam, off_rhs, off_jac,
-      off_yflags, off_done, off_ctl, off_logdet, off_info, off_slabs, total;
+      off_yflags, off_done, off_ctl, off_logdet, off_info, off_slabs, off_uinfo, off_lanes, total;
   int64_t rhs_elems = 0;
   // graph state
   hipStream_t cap = nullptr;
+  std::vector<hipStream_t> lane_s;
+  std::vector<hipEvent_t> ev;
   hipGraphExec_t exec = nullptr;
   void* g_work = nullptr;
   pl_result* g_out = nullptr;
@@ -261,6 +290,8 @@ namespace {
 
 constexpr size_t BALIGN = 256;
 inline size_t balign(size_t x) { return (x + BALIGN - 1) / BALIGN * BALIGN; }
+constexpr size_t PASS_BYTES = (size_t)4 << 30;  // default workspace of one pass
+constexpr int DEFAULT_LANES = 4;
 
 bool omega_ok_b(const double* om) {
   for (int i = 0; i < 5; ++i)
@@ -312,62 +343,14 @@ bool validate(const std::vector<BTask>& tasks, const std::vector<BUnit>& units,
   return true;
 }
 
-}  // namespace
-
-extern "C" {
-
-int pl_batch_create(const pl_dataset* datasets, int64_t D, int64_t p, const double* lambda,
-                    int64_t M, const pl_opts* opts, pl_batch** plan) {
-  if (!datasets) return -1;
-  if (D < 1 || D > (1 << 22)) return -2;
-  if (p < 1 || p > PL_MAX_P) return -3;
-  if (!lambda) return -4;
-  if (M < 1 || M > PL_MAX_M) return -5;
-  for (int64_t m = 0; m < M; ++m)
-    if (!std::isfinite(lambda[m])) return -4;
-  if (opts && (opts->precision != PL_FP64 || opts->chunk < 0 || opts->wait_us < 0)) return -6;
-  if (!plan) return -7;
-  pl_batch* b = new pl_batch();
-  b->p = (int32_t)p;
-  b->M = (int32_t)M;
-  b->q = (int32_t)(M + p);
-  b->TB = (int32_t)((b->q + 15) / 16 * 16);
-  b->lam.assign(lambda, lambda + M);
-  b->wait_us = (opts && opts->wait_us > 0) ? opts->wait_us : PL_BATCH_WAIT_US;
-  int64_t rhs_off = 0, om = 0;
-  int maxNv = 0;
-  for (int64_t d = 0; d < D; ++d) {
-    const pl_dataset& s = datasets[d];
-    // tile indices are int16_t in the task list: at most 32767 tile rows
-    if (!s.locs || !s.y || !s.X || s.n < 2 || s.n <= p || s.n > (int64_t)32767 * T || !s.omega ||
-        s.K < 1) {
-      delete b;
-      return -1;
-    }
-    for (int64_t k = 0; k < s.K; ++k)
-      if (!omega_ok_b(s.omega + 5 * k)) {
-        delete b;
-        return -1;
-      }
-    BDataset bd{s.locs, s.y, s.X, (int32_t)s.n, (int32_t)om, rhs_off};
-    b->ds.push_back(bd);
-    const int Nv = (int)((s.n + T - 1) / T);
-    maxNv = std::max(maxNv, Nv);
-    for (int64_t k = 0; k < s.K; ++k) {
-      b->params.push_back(make_matern_params(s.omega + 5 * k));
-      b->units.push_back({(int32_t)d, (int32_t)(om + k), Nv, 0, -1, 0});
-    }
-    om += s.K;
-    rhs_off += s.n * b->TB;
-  }
-  b->n_omega = om;
-  b->rhs_elems = rhs_off;
-  const int64_t U = (int64_t)b->units.size();
+// Persistent schedule: slab pool, task list, workspace layout.
+int plan_persistent(pl_batch* b, int64_t chunk, int maxNv) {
+  const int64_t U = (int64_t)b->units.size(), D = (int64_t)b->ds.size();
   // slab pool: one slab holds the largest unit's packed matrix and its W tile
   const int64_t mat = packed_stride(maxNv, b->TB);
   b->w_off = (mat + 31) / 32 * 32;
   b->slab_stride = b->w_off + (int64_t)T * T;
-  int64_t S = (opts && opts->chunk > 0) ? opts->chunk : std::min<int64_t>(U, 2048);
+  int64_t S = chunk > 0 ? chunk : std::min<int64_t>(U, 2048);
   b->nslabs = std::max<int64_t>(1, std::min(S, U));
 
   // order units by decreasing size (largest first), waves of nslabs units;
@@ -382,18 +365,13 @@ int pl_batch_create(const pl_dataset* datasets, int64_t D, int64_t p, const doub
   std::vector<std::vector<std::vector<BTask>>> unit_ph(U);
   for (int64_t u = 0; u < U; ++u) {
     unit_phases(b->units[u].Nv, ph);
-    int32_t cnt = 0;
-    for (auto& v : ph) {
-      for (auto& t : v) {
-        t.unit = (int32_t)u;
-        t.wait = cnt;
-      }
-      cnt += (int32_t)v.size();
-    }
     // waits: a task waits for all tasks of earlier phases of its unit
     int32_t before = 0;
     for (auto& v : ph) {
-      for (auto& t : v) t.wait = before;
+      for (auto& t : v) {
+        t.unit = (int32_t)u;
+        t.wait = before;
+      }
       before += (int32_t)v.size();
     }
     total[u] = before;
@@ -420,11 +398,8 @@ int pl_batch_create(const pl_dataset* datasets, int64_t D, int64_t p, const doub
           for (const BTask& t : up[f]) b->tasks.push_back(t);
       }
   }
-  if (b->tasks.size() > (size_t)INT32_MAX || !validate(b->tasks, b->units, total)) {
-    delete b;
+  if (b->tasks.size() > (size_t)INT32_MAX || !validate(b->tasks, b->units, total))
     return PL_E_UNSUPPORTED;
-  }
-  // workspace layout
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -434,11 +409,11 @@ int pl_batch_create(const pl_dataset* datasets, int64_t D, int64_t p, const doub
   b->off_tasks = take(b->tasks.size() * sizeof(BTask));
   b->off_units = take(U * sizeof(BUnit));
   b->off_ds = take(D * sizeof(BDataset));
-  b->off_mp = take(om * sizeof(MaternParams));
-  b->off_nodes = take((size_t)om * TABLE * sizeof(double));
-  b->off_tables = take((size_t)om * TABLE * sizeof(double));
-  b->off_lam = take(M * sizeof(double));
-  b->off_rhs = take((size_t)rhs_off * sizeof(double));
+  b->off_mp = take(b->n_omega * sizeof(MaternParams));
+  b->off_nodes = take((size_t)b->n_omega * TABLE * sizeof(double));
+  b->off_tables = take((size_t)b->n_omega * TABLE * sizeof(double));
+  b->off_lam = take(b->M * sizeof(double));
+  b->off_rhs = take((size_t)b->rhs_elems * sizeof(double));
   b->off_jac = take(D * sizeof(double));
   b->off_yflags = take(D * sizeof(int32_t));
   b->off_done = take(U * sizeof(int32_t));
@@ -447,6 +422,174 @@ int pl_batch_create(const pl_dataset* datasets, int64_t D, int64_t p, const doub
   b->off_info = take(U * sizeof(int32_t));
   b->off_slabs = take((size_t)b->nslabs * b->slab_stride * sizeof(double));
   b->total = off;
+  return PL_OK;
+}
+
+// Size-bucketed schedule: groups by Nv, passes, streams, workspace layout.
+int plan_bucketed(pl_batch* b, int64_t chunk, int lanes) {
+  const int64_t U = (int64_t)b->units.size(), D = (int64_t)b->ds.size();
+  std::vector<int32_t>& order = b->order;
+  order.resize(U);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t x, int32_t y) { return b->units[x].Nv > b->units[y].Nv; });
+  b->uinfo.resize(U);
+  for (int64_t i = 0; i < U; ++i) {
+    const BUnit& u = b->units[order[i]];
+    const BDataset& d = b->ds[u.d];
+    b->uinfo[i] = UnitInfo{d.n, u.d, d.locs, d.rhs_off, (int64_t)u.om};
+  }
+  // passes: a group's units in chunks that fit the pass budget
+  b->lanes = std::max(1, lanes);
+  size_t region = 0;
+  for (int64_t g0 = 0; g0 < U;) {
+    const int Nv = b->units[order[g0]].Nv;
+    int64_t g1 = g0;
+    while (g1 < U && b->units[order[g1]].Nv == Nv) ++g1;
+    const Lay lay = packed_layout((int64_t)Nv * T, b->q);
+    const size_t per = pass_bytes(lay, b->mixed, 1);
+    int64_t cap = chunk > 0 ? chunk : std::max<int64_t>(1, (int64_t)(PASS_BYTES / per));
+    cap = std::min<int64_t>(cap, 1 << 20);
+    const int64_t cnt = g1 - g0, np = (cnt + cap - 1) / cap;
+    for (int64_t j = 0; j < np; ++j) {
+      const int64_t a = g0 + cnt * j / np, e = g0 + cnt * (j + 1) / np;
+      BPass ps{(int32_t)a, (int32_t)(e - a), 0, 0, 0.0};
+      for (int64_t i = a; i < e; ++i) {
+        const double n = b->uinfo[i].n;
+        ps.nmax = std::max<int32_t>(ps.nmax, b->uinfo[i].n);
+        ps.cost += n * n * n / 3.0 + 2e3 * n * n;  // factorisation and covariance build
+      }
+      ps.cost += 3.0 * Nv * 5e9;                     // launch latencies of the pass
+      region = std::max(region, pass_bytes(lay, b->mixed, e - a));
+      b->passes.push_back(ps);
+    }
+    g0 = g1;
+  }
+  // largest passes first, each to the least loaded stream
+  std::vector<int32_t> po(b->passes.size());
+  std::iota(po.begin(), po.end(), 0);
+  std::stable_sort(po.begin(), po.end(),
+                   [&](int32_t x, int32_t y) { return b->passes[x].cost > b->passes[y].cost; });
+  std::vector<double> load(b->lanes, 0.0);
+  std::vector<BPass> sorted;
+  for (int32_t i : po) {
+    BPass ps = b->passes[i];
+    ps.lane = (int32_t)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[ps.lane] += ps.cost;
+    sorted.push_back(ps);
+  }
+  b->passes = sorted;
+  // a mixed-form breakdown is redone in FP64 in stream 0's region afterwards
+  if (b->mixed) {
+    int nbig = 0;
+    for (const BDataset& d : b->ds) nbig = std::max(nbig, d.n);
+    pl_opts o{};
+    o.precision = PL_FP64;
+    size_t fb = 0;
+    if (pl_workspace_size(nbig, b->p, 1, b->M, &o, &fb) != PL_OK) return PL_E_UNSUPPORTED;
+    region = std::max(region, fb);
+  }
+  b->region = balign(region);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += balign(bytes);
+    return o;
+  };
+  b->off_ds = take(D * sizeof(BDataset));
+  b->off_mp = take(U * sizeof(MaternParams));
+  b->off_nodes = take((size_t)U * TABLE * sizeof(double));
+  b->off_tables = take((size_t)U * TABLE * sizeof(double));
+  b->off_lam = take(b->M * sizeof(double));
+  b->off_rhs = take((size_t)b->rhs_elems * sizeof(double));
+  b->off_jac = take(D * sizeof(double));
+  b->off_yflags = take(D * sizeof(int32_t));
+  b->off_uinfo = take(U * sizeof(UnitInfo));
+  b->off_info = take(U * sizeof(int32_t));
+  b->off_lanes = take((size_t)b->lanes * b->region);
+  b->total = off;
+  return PL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pl_batch_create(const pl_dataset* datasets, int64_t D, int64_t p, const double* lambda,
+                    int64_t M, const pl_opts* opts, pl_batch** plan) {
+  if (!datasets) return -1;
+  if (D < 1 || D > (1 << 22)) return -2;
+  if (p < 1 || p > PL_MAX_P) return -3;
+  if (!lambda) return -4;
+  if (M < 1 || M > PL_MAX_M) return -5;
+  for (int64_t m = 0; m < M; ++m)
+    if (!std::isfinite(lambda[m])) return -4;
+  const bool persistent = opts && (opts->flags & PL_OPT_BATCH_PERSISTENT);
+  const bool mixed = opts && opts->precision == PL_MIXED;
+  if (opts) {
+    if (opts->precision != PL_FP64 && opts->precision != PL_MIXED) return -6;
+    if (opts->chunk < 0 || opts->wait_us < 0 || opts->lanes < 0 || opts->lanes > 16) return -6;
+    if (opts->refine < 0 || opts->refine > 1) return -6;
+    if (opts->flush != 0 && opts->flush != 1 && opts->flush != 2 && opts->flush != 4) return -6;
+    if (persistent && mixed) return -6;  // the persistent kernel carries FP64 tasks only
+  }
+  if (!plan) return -7;
+  if (mixed && M + p > 32) return PL_E_UNSUPPORTED;
+  pl_batch* b = new pl_batch();
+  b->p = (int32_t)p;
+  b->M = (int32_t)M;
+  b->q = (int32_t)(M + p);
+  b->TB = (int32_t)((b->q + 15) / 16 * 16);
+  b->lam.assign(lambda, lambda + M);
+  b->persistent = persistent;
+  b->mixed = mixed;
+  if (opts) {
+    b->refine = opts->refine;
+    b->fallback = !(opts->flags & PL_OPT_NO_FALLBACK);
+    if (opts->flush) b->flush = opts->flush;
+  }
+  b->wait_us = (opts && opts->wait_us > 0) ? opts->wait_us : PL_BATCH_WAIT_US;
+  int64_t rhs_off = 0, om = 0;
+  int maxNv = 0;
+  for (int64_t d = 0; d < D; ++d) {
+    const pl_dataset& s = datasets[d];
+    // tile indices are int16_t in the persistent task list: at most 32767 tile rows
+    if (!s.locs || !s.y || !s.X || s.n < 2 || s.n <= p || s.n > (int64_t)32767 * T || !s.omega ||
+        s.K < 1 || s.K > (1 << 24)) {
+      delete b;
+      return -1;
+    }
+    for (int64_t k = 0; k < s.K; ++k)
+      if (!omega_ok_b(s.omega + 5 * k)) {
+        delete b;
+        return -1;
+      }
+    BDataset bd{s.locs, s.y, s.X, (int32_t)s.n, (int32_t)om, rhs_off};
+    b->ds.push_back(bd);
+    const int Nv = (int)((s.n + T - 1) / T);
+    maxNv = std::max(maxNv, Nv);
+    for (int64_t k = 0; k < s.K; ++k) {
+      b->params.push_back(make_matern_params(s.omega + 5 * k));
+      b->units.push_back({(int32_t)d, (int32_t)(om + k), Nv, 0, -1, 0});
+      b->omega.insert(b->omega.end(), s.omega + 5 * k, s.omega + 5 * k + 5);
+    }
+    om += s.K;
+    rhs_off += s.n * b->TB;
+    if (om > INT32_MAX / 2) {
+      delete b;
+      return -2;
+    }
+  }
+  b->n_omega = om;
+  b->rhs_elems = rhs_off;
+  const int rc = persistent
+                     ? plan_persistent(b, opts ? opts->chunk : 0, maxNv)
+                     : plan_bucketed(b, opts ? opts->chunk : 0,
+                                     (opts && opts->lanes > 0) ? opts->lanes : DEFAULT_LANES);
+  if (rc != PL_OK) {
+    delete b;
+    return rc;
+  }
   *plan = b;
   return PL_OK;
 }
@@ -461,10 +604,116 @@ int pl_batch_workspace_size(const pl_batch* plan, size_t* bytes) {
 int pl_batch_stats(const pl_batch* plan, int64_t* units, int64_t* tasks, int64_t* slabs) {
   if (!plan) return -1;
   if (units) *units = (int64_t)plan->units.size();
-  if (tasks) *tasks = (int64_t)plan->tasks.size();
-  if (slabs) *slabs = plan->nslabs;
+  if (tasks) *tasks = plan->persistent ? (int64_t)plan->tasks.size() : (int64_t)plan->passes.size();
+  if (slabs) *slabs = plan->persistent ? plan->nslabs : plan->lanes;
   return PL_OK;
 }
+
+namespace {
+
+// Capture of the persistent schedule's launch sequence (after the upload).
+hipError_t capture_persistent(pl_batch* b, char* w, pl_result* out, double* beta_hat) {
+  int dev = 0, cus = 0, per_cu = 0, clock_khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+      clock_khz <= 0 ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_persistent, 256, 0) !=
+          hipSuccess)
+    return hipErrorUnknown;
+  b->grid = std::max(1, cus * std::max(1, per_cu));
+  const int64_t U = (int64_t)b->units.size(), D = (int64_t)b->ds.size();
+  BatchArgs a{};
+  a.tasks = (const BTask*)(w + b->off_tasks);
+  a.ntasks = (int32_t)b->tasks.size();
+  a.head = (int32_t*)(w + b->off_ctl);
+  a.err = (int32_t*)(w + b->off_ctl) + 1;
+  a.done = (int32_t*)(w + b->off_done);
+  a.units = (const BUnit*)(w + b->off_units);
+  a.ds = (const BDataset*)(w + b->off_ds);
+  a.mp = (const MaternParams*)(w + b->off_mp);
+  a.tables = (const double*)(w + b->off_tables);
+  a.rhs = (const double*)(w + b->off_rhs);
+  a.jac = (const double*)(w + b->off_jac);
+  a.yflags = (const int32_t*)(w + b->off_yflags);
+  a.lam = (const double*)(w + b->off_lam);
+  a.slabs = (double*)(w + b->off_slabs);
+  a.slab_stride = b->slab_stride;
+  a.w_off = b->w_off;
+  a.logdet = (double*)(w + b->off_logdet);
+  a.info = (int32_t*)(w + b->off_info);
+  a.p = b->p;
+  a.M = b->M;
+  a.q = b->q;
+  a.TB = b->TB;
+  a.out = out;
+  a.beta = beta_hat;
+  a.wait_ticks = (int64_t)b->wait_us * clock_khz / 1000;
+  hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((U + 255) / 256)), dim3(256), 0, b->cap, a.done, U);
+  hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((U + 255) / 256)), dim3(256), 0, b->cap, a.info, U);
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, b->cap, a.head, (int64_t)2);
+  (void)launch_fill(a.logdet, 0.0, U, b->cap);
+  (void)launch_cheb_tables(a.mp, (double*)(w + b->off_nodes), (double*)a.tables, (int)b->n_omega,
+                           b->cap);
+  hipLaunchKernelGGL(k_batch_boxcox, dim3((unsigned)D), dim3(256), 0, b->cap, a.ds, a.lam, b->p,
+                     b->M, b->TB, (double*)a.rhs, (double*)a.jac, (int32_t*)a.yflags);
+  hipLaunchKernelGGL(k_batch_persistent, dim3(b->grid), dim3(256), 0, b->cap, a);
+  return hipGetLastError();
+}
+
+// Capture of the size-bucketed schedule: prologue on the capture stream, the
+// passes on the stream lanes forked from it, joined back at the end.
+hipError_t capture_bucketed(pl_batch* b, char* w, pl_result* out, double* beta_hat) {
+  const int64_t U = (int64_t)b->units.size(), D = (int64_t)b->ds.size();
+  const BDataset* ds = (const BDataset*)(w + b->off_ds);
+  const MaternParams* mp = (const MaternParams*)(w + b->off_mp);
+  double* tables = (double*)(w + b->off_tables);
+  double* rhs = (double*)(w + b->off_rhs);
+  double* jac = (double*)(w + b->off_jac);
+  int32_t* yflags = (int32_t*)(w + b->off_yflags);
+  const double* lam = (const double*)(w + b->off_lam);
+  const UnitInfo* ui = (const UnitInfo*)(w + b->off_uinfo);
+  int32_t* info = (int32_t*)(w + b->off_info);
+  hipError_t e = launch_cheb_tables(mp, (double*)(w + b->off_nodes), tables, (int)U, b->cap);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_batch_boxcox, dim3((unsigned)D), dim3(256), 0, b->cap, ds, lam, b->p, b->M,
+                     b->TB, rhs, jac, yflags);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = hipEventRecord(b->ev[0], b->cap)) != hipSuccess) return e;
+  for (int l = 0; l < b->lanes; ++l)
+    if ((e = hipStreamWaitEvent(b->lane_s[l], b->ev[0], 0)) != hipSuccess) return e;
+  PassArgs pa{};
+  pa.mixed = b->mixed;
+  pa.flush = b->flush;
+  pa.refine = b->refine;
+  pa.locs = nullptr;  // each unit's own (UnitInfo)
+  pa.rhs = rhs;
+  pa.jac = jac;
+  pa.yflags = yflags;
+  pa.lam = lam;
+  pa.p = b->p;
+  pa.M = b->M;
+  pa.out = out;
+  pa.beta = beta_hat;
+  pa.xvx = nullptr;
+  for (const BPass& ps : b->passes) {
+    pa.lay = packed_layout(ps.nmax, b->q);
+    pa.lay.units = ui + ps.u0;
+    pa.mp = mp + ps.u0;
+    pa.tables = tables + (int64_t)ps.u0 * TABLE;
+    pa.info_out = info + ps.u0;
+    const PassBufs pb = carve_pass(w + b->off_lanes + (size_t)ps.lane * b->region, pa.lay,
+                                   b->mixed, ps.cnt);
+    if ((e = run_pass(pa, pb, ps.cnt, b->lane_s[ps.lane])) != hipSuccess) return e;
+  }
+  for (int l = 0; l < b->lanes; ++l) {
+    if ((e = hipEventRecord(b->ev[1 + l], b->lane_s[l])) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(b->cap, b->ev[1 + l], 0)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
 
 int pl_batch_run(pl_batch* b, pl_result* out, double* beta_hat, void* work, size_t work_bytes,
                  void* stream) {
@@ -482,69 +731,50 @@ int pl_batch_run(pl_batch* b, pl_result* out, double* beta_hat, void* work, size
     }
     if (!b->cap && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
       return PL_E_HIP;
+    if (!b->persistent && b->lane_s.empty()) {
+      b->lane_s.assign(b->lanes, nullptr);
+      b->ev.assign(b->lanes + 1, nullptr);
+      for (auto& ls : b->lane_s)
+        if (hipStreamCreateWithFlags(&ls, hipStreamNonBlocking) != hipSuccess) return PL_E_HIP;
+      for (auto& ev : b->ev)
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return PL_E_HIP;
+    }
     // the plan's tables go to the workspace once (outside the graph)
     auto up = [&](size_t off, const void* src, size_t bytes) {
       return bytes == 0 ? hipSuccess
                         : hipMemcpyAsync(w + off, src, bytes, hipMemcpyHostToDevice, b->cap);
     };
-    if (up(b->off_tasks, b->tasks.data(), b->tasks.size() * sizeof(BTask)) != hipSuccess ||
-        up(b->off_units, b->units.data(), b->units.size() * sizeof(BUnit)) != hipSuccess ||
+    std::vector<MaternParams> mps;
+    if (!b->persistent) {  // parameters in the sorted unit order
+      mps.resize(b->order.size());
+      for (size_t i = 0; i < b->order.size(); ++i) mps[i] = b->params[b->order[i]];
+    }
+    const std::vector<MaternParams>& mpv = b->persistent ? b->params : mps;
+    if ((b->persistent &&
+         (up(b->off_tasks, b->tasks.data(), b->tasks.size() * sizeof(BTask)) != hipSuccess ||
+          up(b->off_units, b->units.data(), b->units.size() * sizeof(BUnit)) != hipSuccess)) ||
+        (!b->persistent &&
+         up(b->off_uinfo, b->uinfo.data(), b->uinfo.size() * sizeof(UnitInfo)) != hipSuccess) ||
         up(b->off_ds, b->ds.data(), b->ds.size() * sizeof(BDataset)) != hipSuccess ||
-        up(b->off_mp, b->params.data(), b->params.size() * sizeof(MaternParams)) != hipSuccess ||
+        up(b->off_mp, mpv.data(), mpv.size() * sizeof(MaternParams)) != hipSuccess ||
         up(b->off_lam, b->lam.data(), b->lam.size() * sizeof(double)) != hipSuccess ||
         hipStreamSynchronize(b->cap) != hipSuccess)
       return PL_E_HIP;
-    int dev = 0, cus = 0, per_cu = 0, clock_khz = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
-        clock_khz <= 0 ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_persistent, 256, 0) !=
-            hipSuccess)
-      return PL_E_HIP;
-    b->grid = std::max(1, cus * std::max(1, per_cu));
-    const int64_t U = (int64_t)b->units.size(), D = (int64_t)b->ds.size();
-    BatchArgs a{};
-    a.tasks = (const BTask*)(w + b->off_tasks);
-    a.ntasks = (int32_t)b->tasks.size();
-    a.head = (int32_t*)(w + b->off_ctl);
-    a.err = (int32_t*)(w + b->off_ctl) + 1;
-    a.done = (int32_t*)(w + b->off_done);
-    a.units = (const BUnit*)(w + b->off_units);
-    a.ds = (const BDataset*)(w + b->off_ds);
-    a.mp = (const MaternParams*)(w + b->off_mp);
-    a.tables = (const double*)(w + b->off_tables);
-    a.rhs = (const double*)(w + b->off_rhs);
-    a.jac = (const double*)(w + b->off_jac);
-    a.yflags = (const int32_t*)(w + b->off_yflags);
-    a.lam = (const double*)(w + b->off_lam);
-    a.slabs = (double*)(w + b->off_slabs);
-    a.slab_stride = b->slab_stride;
-    a.w_off = b->w_off;
-    a.logdet = (double*)(w + b->off_logdet);
-    a.info = (int32_t*)(w + b->off_info);
-    a.p = b->p;
-    a.M = b->M;
-    a.q = b->q;
-    a.TB = b->TB;
-    a.out = out;
-    a.beta = beta_hat;
-    a.wait_ticks = (int64_t)b->wait_us * clock_khz / 1000;
+    // per-kernel-class event timing is not recorded inside the graph
+    (void)profiling_pause(true);
     hipGraph_t graph = nullptr;
-    if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)profiling_pause(false);
       return PL_E_HIP;
-    hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((U + 255) / 256)), dim3(256), 0, b->cap, a.done, U);
-    hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((U + 255) / 256)), dim3(256), 0, b->cap, a.info, U);
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, b->cap, a.head, (int64_t)2);
-    (void)launch_fill(a.logdet, 0.0, U, b->cap);
-    (void)launch_cheb_tables(a.mp, (double*)(w + b->off_nodes), (double*)a.tables, (int)b->n_omega,
-                             b->cap);
-    hipLaunchKernelGGL(k_batch_boxcox, dim3((unsigned)D), dim3(256), 0, b->cap, a.ds, a.lam, b->p,
-                       b->M, b->TB, (double*)a.rhs, (double*)a.jac, (int32_t*)a.yflags);
-    hipLaunchKernelGGL(k_batch_persistent, dim3(b->grid), dim3(256), 0, b->cap, a);
-    const hipError_t le = hipGetLastError();
+    }
+    const hipError_t le = b->persistent ? capture_persistent(b, w, out, beta_hat)
+                                        : capture_bucketed(b, w, out, beta_hat);
     const hipError_t ce = hipStreamEndCapture(b->cap, &graph);
-    if (le != hipSuccess || ce != hipSuccess) return PL_E_HIP;
+    (void)profiling_pause(false);
+    if (le != hipSuccess || ce != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return PL_E_HIP;
+    }
     const hipError_t ie = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (ie != hipSuccess) return PL_E_HIP;
@@ -553,6 +783,30 @@ int pl_batch_run(pl_batch* b, pl_result* out, double* beta_hat, void* work, size
     b->g_beta = beta_hat;
   }
   if (hipGraphLaunch(b->exec, s) != hipSuccess) return PL_E_HIP;
+  if (b->mixed && b->fallback) {
+    // units whose FP32 factorisation broke down: redone with the FP64 form
+    // (their dataset alone) into their own records, then flagged
+    const size_t U = b->units.size();
+    std::vector<int32_t> hinfo(U);
+    if (hipMemcpyAsync(hinfo.data(), w + b->off_info, U * sizeof(int32_t), hipMemcpyDeviceToHost,
+                       s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return PL_E_HIP;
+    pl_opts o64{};
+    o64.precision = PL_FP64;
+    o64.chunk = 1;
+    for (size_t i = 0; i < U; ++i) {
+      if (hinfo[i] <= 0) continue;
+      const BUnit& u = b->units[b->order[i]];
+      const BDataset& d = b->ds[u.d];
+      const int rc = pl_profile_loglik(d.locs, d.y, d.X, d.n, b->p, &b->omega[5 * (size_t)u.om], 1,
+                                       b->lam.data(), b->M, out + (int64_t)u.om * b->M,
+                                       beta_hat ? beta_hat + (int64_t)u.om * b->M * b->p : nullptr,
+                                       nullptr, &o64, w + b->off_lanes, b->region, stream);
+      if (rc != PL_OK) return rc;
+      if (launch_mark_fallback(out + (int64_t)u.om * b->M, b->M, s) != hipSuccess) return PL_E_HIP;
+    }
+  }
   return PL_OK;
 }
 
@@ -560,6 +814,8 @@ int pl_batch_error(const pl_batch* b, void* work, int32_t* err) {
   if (!b) return -1;
   if (!work) return -2;
   if (!err) return -3;
+  *err = 0;
+  if (!b->persistent) return PL_OK;  // no waits in the size-bucketed schedule
   if (hipMemcpy(err, (char*)work + b->off_ctl + sizeof(int32_t), sizeof(int32_t),
                 hipMemcpyDeviceToHost) != hipSuccess)
     return PL_E_HIP;
@@ -570,6 +826,10 @@ void pl_batch_destroy(pl_batch* b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->cap) (void)hipStreamDestroy(b->cap);
+  for (auto ls : b->lane_s)
+    if (ls) (void)hipStreamDestroy(ls);
+  for (auto ev : b->ev)
+    if (ev) (void)hipEventDestroy(ev);
   delete b;
 }
 

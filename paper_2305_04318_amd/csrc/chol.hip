@@ -46,7 +46,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_col(Lay lay, double* __restrict
   const int k = wg / nI;
   const int I = J + wg % nI;
   if (info[k] != 0) return;  // uniform for the workgroup
-  dev_gemm_col<VEC>(lay, mats + (int64_t)k * lay.mstride, J, I, reinterpret_cast<double*>(lds_raw));
+  dev_gemm_col<VEC>(lay_of(lay, k), mats + (int64_t)k * lay.mstride, J, I,
+                    reinterpret_cast<double*>(lds_raw));
 }
 
 // Mixed form.  Off-diagonal tiles: FP32 storage, FP32 MFMA whose partial
@@ -151,14 +152,14 @@ __global__ __launch_bounds__(256, 2) void k_col_update_mx(Lay lay, float* __rest
   const int b = blockIdx.x;
   if (b < K) {
     if (info[b] != 0) return;  // uniform for the workgroup
-    dev_diag_mx<true, true>(lay, m32, m64, m64stride, dscratch, b, J, lds);
+    dev_diag_mx<true, true>(lay_of(lay, b), m32, m64, m64stride, dscratch, b, J, lds);
     return;
   }
   const int G = K * nOff;
   const int wg = xcd_remap(b - K, G);
   const int k = wg / nOff, r = wg % nOff;
   if (info[k] != 0) return;
-  dev_col_mx<true, FLUSH>(lay, m32, m64, m64stride, k, J + 1 + r, J, lds);
+  dev_col_mx<true, FLUSH>(lay_of(lay, k), m32, m64, m64stride, k, J + 1 + r, J, lds);
 }
 
 // Mixed form on a plain column-major FP32 matrix (pl_chol_batched with
@@ -268,11 +269,12 @@ __global__ __launch_bounds__(256) void k_potrf(Lay lay, double* __restrict__ mat
   __shared__ double smem[POTRF_SMEM_DOUBLES];
   const int k = blockIdx.x;
   if (info[k] != 0) return;
+  const Lay L = lay_of(lay, k);
   if (MODE == 0)
-    dev_potrf<0>(lay, mats + (int64_t)k * lay.mstride + lay.tile_off(J, J), lay.tile_ld(J),
+    dev_potrf<0>(L, mats + (int64_t)k * lay.mstride + lay.tile_off(J, J), lay.tile_ld(J),
                  Wbuf + (int64_t)k * T * T, nullptr, logdet + k, info + k, J, smem);
   else
-    dev_potrf<1>(lay, Wbuf + (int64_t)k * T * T, T, nullptr,
+    dev_potrf<1>(L, Wbuf + (int64_t)k * T * T, T, nullptr,
                  W32 + ((int64_t)k * lay.Nv + J) * T * T, logdet + k, info + k, J, smem);
 }
 
@@ -330,8 +332,9 @@ __global__ __launch_bounds__(256, 2) void k_col_update(Lay lay, double* __restri
   const int k = wg / (nOff + 1), r = wg % (nOff + 1);
   if (info[k] != 0) return;  // uniform for the workgroup
   double* base = mats + (int64_t)k * lay.mstride;
-  if (r == 0) dev_gemm_diag_border<VEC>(lay, base, J, border != 0, lds);
-  else dev_gemm_col<VEC>(lay, base, J, J + r, lds);
+  const Lay L = lay_of(lay, k);
+  if (r == 0) dev_gemm_diag_border<VEC>(L, base, J, border != 0, lds);
+  else dev_gemm_col<VEC>(L, base, J, J + r, lds);
 }
 
 hipError_t launch_col_update(const Lay& lay, double* mats, const int32_t* info, int J, int K,
@@ -374,7 +377,7 @@ __global__ __launch_bounds__(256) void k_border_block(Lay lay, double* __restric
   double* C = base + lay.tile_off(lay.Nv, lay.Nv);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  const int n = lay.n, q = lay.q;
+  const int n = lay.units ? lay.units[k].n : lay.n, q = lay.q;
   const int64_t ld = lay.TB;
   d4 acc[NB][NB];
 #pragma unroll
@@ -444,8 +447,8 @@ __global__ __launch_bounds__(256, 2) void k_trsm(Lay lay, TS* __restrict__ mats,
   const int k = wg / nI;
   const int I = J + 1 + wg % nI;
   if (info[k] != 0) return;  // uniform for the workgroup
-  dev_trsm<TS, VEC, MX_FLUSH>(lay, mats + (int64_t)k * lay.mstride, Wbuf + (int64_t)k * wstride, J, I,
-                              reinterpret_cast<TS*>(lds_raw));
+  dev_trsm<TS, VEC, MX_FLUSH>(lay_of(lay, k), mats + (int64_t)k * lay.mstride,
+                              Wbuf + (int64_t)k * wstride, J, I, reinterpret_cast<TS*>(lds_raw));
 }
 
 hipError_t launch_trsm(const Lay& lay, double* mats, const double* W, const int32_t* info, int J,
@@ -608,11 +611,13 @@ __global__ __launch_bounds__(256, TB == 16 ? 3 : 2) void k_qform(Lay lay, const 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = wave >> 1, wc = wave & 1;
   const int q = lay.q;
-  const int ri = lay.rows(I), rj = lay.rows(J);
-  const double* Xk = X + (int64_t)k * lay.n * TB;
+  const Lay L = lay_of(lay, k);
+  const int ri = L.rows(I), rj = L.rows(J);
+  const double* Xk = X + (int64_t)k * x0_stride(lay);
   double* slot = slots + ((int64_t)k * ntile + t) * TB * TB;
   const double* Xi = Xk + (int64_t)I * T * TB;   // x0_I: element (r, a) at r*TB + a
-  const double* Bi = rhs + (int64_t)I * T * TB;  // B_I, same layout
+  // B_I, same layout (an uneven batch: the unit's dataset's right-hand sides)
+  const double* Bi = rhs + (lay.units ? lay.units[k].rhs : 0) + (int64_t)I * T * TB;
   // LDS after the core: Y = V_IJ x0_J column-major with the odd stride T + 1
   // (the pair loop below reads 16 columns of Y at once), then x0_I.  With
   // TB <= 32 both fit the core's LDS block.

@@ -35,6 +35,18 @@ struct MaternParams {
 // Host: the constants of omega = (phi_X, kappa, nu^2, phi_R, phi_A).
 MaternParams make_matern_params(const double* om);
 
+// One omega of an uneven batch pass (datasets of different n in one launch):
+// its dataset's order, the dataset's index (Jacobian, y check), its
+// locations (n x 2), the element offset of its right-hand sides (n x TB) in
+// the batch's array, and its omega index in the records (record om M + m).
+struct UnitInfo {
+  int32_t n;
+  int32_t ds;
+  const double* locs;
+  int64_t rhs;
+  int64_t om;
+};
+
 // Addressing of the per-omega matrices.
 //  kind 0: packed lower tiles, each T x T column-major, tile (I,J) of the V
 //          part at (I(I+1)/2 + J) T^2; below them a bordered tile row of
@@ -51,6 +63,9 @@ struct Lay {
   int pad;
   int64_t ld;      // kind 1 leading dimension
   int64_t mstride; // elements per matrix
+  // uneven batches: per-omega data of the pass, null otherwise.  n is then
+  // the unit's own order inside a kernel (lay_of) and every unit shares Nv.
+  const UnitInfo* units;
 
   __host__ __device__ int64_t tile_off(int I, int J) const {
     if (kind == 1) return (int64_t)J * T * ld + (int64_t)I * T;
@@ -66,6 +81,18 @@ struct Lay {
     return q;
   }
 };
+
+// The layout of omega k of a launch: its own order n in an uneven batch.
+__device__ __forceinline__ Lay lay_of(const Lay& lay, int k) {
+  Lay L = lay;
+  if (lay.units) L.n = lay.units[k].n;
+  return L;
+}
+
+// Elements per omega of the mixed form's x0 (rows of TB values, Nv T rows).
+__host__ __device__ inline int64_t x0_stride(const Lay& lay) {
+  return (int64_t)lay.Nv * T * lay.TB;
+}
 
 __host__ inline int64_t packed_stride(int Nv, int TB) {
   return (int64_t)Nv * (Nv + 1) / 2 * (T * T) + (int64_t)Nv * TB * T + (int64_t)TB * TB;
@@ -155,6 +182,45 @@ hipError_t launch_qform(const Lay& lay, const double* m64, int64_t stride64, con
                         const double* rhs, const int32_t* info, double* slots, int refine, int K,
                         hipStream_t s);
 hipError_t launch_mark_fallback(pl_result* out, int M, hipStream_t s);
+
+// ---- one device pass of Step 3 over omega points sharing a layout ----------------
+struct PassBufs {
+  double* mats;                  // FP64: packed bordered matrices
+  double* W;                     // FP64: W_J per omega
+  float* m32;                    // mixed: FP32 packed factor
+  double* m64;                   // mixed: FP64 copy of V
+  float* W32;                    // mixed: every W_J in FP32
+  double* dscr;                  // mixed: FP64 diagonal tile / reduced slots
+  double* x0;                    // mixed: x0 = V^-1 [Y'|X]
+  double* slots;                 // mixed: refined cross-product slots
+  double* logdet;
+  int32_t* info;
+  size_t bytes;                  // bytes carved
+};
+struct PassArgs {
+  Lay lay;                       // lay.units set for an uneven batch
+  bool mixed;
+  int flush, refine;
+  const double* locs;            // the dataset's (or the batch's) locations
+  const double* rhs;             // its Box-Cox right-hand sides (n x TB)
+  const MaternParams* mp;        // this pass's omega constants and tables
+  const double* tables;
+  const double* jac;
+  const int32_t* yflags;
+  const double* lam;             // device, M values
+  int p, M;
+  pl_result* out;                // records of the pass's first omega (batch: all records)
+  double* beta;
+  double* xvx;
+  int32_t* info_out;             // per-omega info copy, or null
+};
+PassBufs carve_pass(char* base, const Lay& lay, bool mixed, int64_t kc);
+size_t pass_bytes(const Lay& lay, bool mixed, int64_t kc);
+hipError_t run_pass(const PassArgs& a, const PassBufs& b, int kk, hipStream_t s);
+// Suspends (pause = true) or resumes the per-kernel-class event timing;
+// returns whether it was on before the call.
+bool profiling_pause(bool pause);
+Lay packed_layout(int64_t n, int64_t q);
 hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int n, hipStream_t s);
 
 }  // namespace plk

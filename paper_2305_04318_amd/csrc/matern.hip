@@ -120,8 +120,10 @@ __global__ __launch_bounds__(256) void k_matern(Lay lay, double* __restrict__ ma
   const int64_t off = lay.tile_off(I, J);
   double* C = (MODE != 3) ? mats + (int64_t)k * stride64 + off : nullptr;
   float* C32 = (MODE == 2 || MODE == 3) ? m32 + (int64_t)k * stride32 + off : nullptr;
-  dev_matern_tile<MODE>(lay, mp[k], tables + (int64_t)k * TABLE, locs, I, J, C, lay.tile_ld(I),
-                        C32, smem);
+  // an uneven batch: the unit's own order and locations
+  const double* lk = lay.units ? lay.units[k].locs : locs;
+  dev_matern_tile<MODE>(lay_of(lay, k), mp[k], tables + (int64_t)k * TABLE, lk, I, J, C,
+                        lay.tile_ld(I), C32, smem);
 }
 
 hipError_t launch_matern_packed(const Lay& lay, double* mats, const double* locs,

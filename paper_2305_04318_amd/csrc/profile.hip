@@ -85,27 +85,35 @@ hipError_t launch_boxcox_rhs(const double* y, const double* X, const double* lam
 }
 
 // Copy the right-hand sides into each omega's bordered tile row (column i of
-// the bordered panel is rhs row i) and clear the final TB x TB tile.
+// the bordered panel is rhs row i) and clear the final TB x TB tile.  In an
+// uneven batch each omega takes its dataset's right-hand sides and order;
+// columns at or beyond n are not written (never read as data).
+__host__ __device__ inline int64_t border_span(const Lay& lay) {
+  return (int64_t)lay.Nv * T * lay.TB + (int64_t)lay.TB * lay.TB;
+}
+
 template <typename TS>
 __global__ void k_border_init(Lay lay, TS* __restrict__ mats, const double* __restrict__ rhs,
                               int K) {
-  const int64_t per = (int64_t)lay.n * lay.TB + (int64_t)lay.TB * lay.TB;
+  const int64_t per = border_span(lay);
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= per * K) return;
   const int k = (int)(idx / per);
   const int64_t e = idx % per;
   TS* base = mats + (int64_t)k * lay.mstride;
-  if (e < (int64_t)lay.n * lay.TB) {
-    base[lay.tile_off(lay.Nv, 0) + e] = (TS)rhs[e];
+  const int64_t panel = (int64_t)lay.Nv * T * lay.TB;
+  if (e < panel) {
+    const int n = lay.units ? lay.units[k].n : lay.n;
+    if (e < (int64_t)n * lay.TB)
+      base[lay.tile_off(lay.Nv, 0) + e] = (TS)rhs[(lay.units ? lay.units[k].rhs : 0) + e];
   } else {
-    base[lay.tile_off(lay.Nv, lay.Nv) + (e - (int64_t)lay.n * lay.TB)] = (TS)0;
+    base[lay.tile_off(lay.Nv, lay.Nv) + (e - panel)] = (TS)0;
   }
 }
 
 hipError_t launch_border_init(const Lay& lay, double* mats, const double* rhs, int K,
                               hipStream_t s) {
-  const int64_t per = (int64_t)lay.n * lay.TB + (int64_t)lay.TB * lay.TB;
-  const int64_t total = per * K;
+  const int64_t total = border_span(lay) * K;
   hipLaunchKernelGGL(k_border_init<double>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
                      lay, mats, rhs, K);
   return hipGetLastError();
@@ -113,8 +121,7 @@ hipError_t launch_border_init(const Lay& lay, double* mats, const double* rhs, i
 
 hipError_t launch_border_init_f32(const Lay& lay, float* mats, const double* rhs, int K,
                                   hipStream_t s) {
-  const int64_t per = (int64_t)lay.n * lay.TB + (int64_t)lay.TB * lay.TB;
-  const int64_t total = per * K;
+  const int64_t total = border_span(lay) * K;
   hipLaunchKernelGGL(k_border_init<float>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
                      lay, mats, rhs, K);
   return hipGetLastError();
@@ -134,13 +141,16 @@ static_assert(T * (T + 1) % 4 == 0, "right-hand sides follow the tile in LDS, 16
 
 __global__ void k_bs_init(Lay lay, const float* __restrict__ m32, const int32_t* __restrict__ info,
                           double* __restrict__ X, int K) {
-  const int64_t per = (int64_t)lay.n * lay.TB;
+  const int64_t per = x0_stride(lay);
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= per * K) return;
   const int k = (int)(idx / per);
   const int64_t e = idx % per;
-  // bordered panel: element (a, i) at i*TB + a, the same index as x0 row i, column a
-  X[idx] = (double)m32[(int64_t)k * lay.mstride + lay.tile_off(lay.Nv, 0) + e];
+  const int n = lay.units ? lay.units[k].n : lay.n;
+  // bordered panel: element (a, i) at i*TB + a, the same index as x0 row i,
+  // column a; rows at or beyond n are never read
+  if (e < (int64_t)n * lay.TB)
+    X[idx] = (double)m32[(int64_t)k * lay.mstride + lay.tile_off(lay.Nv, 0) + e];
 }
 
 // Ls[c][r] (stride T + 1) = G[c][r] for the T x T column-major tile G, rows
@@ -261,8 +271,8 @@ __global__ __launch_bounds__(256) void k_bs_diag(Lay lay, const float* __restric
   const int k = blockIdx.x;
   if (info[k] != 0) return;
   const int tid = threadIdx.x, r = tid & (T - 1), h = tid >> 7;
-  const int ri = lay.rows(I);
-  double* Xi = X + (int64_t)k * lay.n * TB + (int64_t)I * T * TB;
+  const int ri = lay_of(lay, k).rows(I);
+  double* Xi = X + (int64_t)k * x0_stride(lay) + (int64_t)I * T * TB;
   stage_tile_t(Ls, W32 + ((int64_t)k * lay.Nv + I) * T * T, T);
   stage_rhs<TB>(Xs, Xi, ri);
   __syncthreads();
@@ -291,9 +301,9 @@ __global__ __launch_bounds__(256) void k_bs_update(Lay lay, const float* __restr
   const int J = blockIdx.x % I;
   if (info[k] != 0) return;
   const int tid = threadIdx.x, r = tid & 63, q = tid >> 6;
-  const int ri = lay.rows(I);
-  const double* Xi = X + (int64_t)k * lay.n * TB + (int64_t)I * T * TB;
-  double* Xj = X + (int64_t)k * lay.n * TB + (int64_t)J * T * TB;
+  const int ri = lay_of(lay, k).rows(I);
+  const double* Xi = X + (int64_t)k * x0_stride(lay) + (int64_t)I * T * TB;
+  double* Xj = X + (int64_t)k * x0_stride(lay) + (int64_t)J * T * TB;
   // tile (I, J): rows in block I (the contraction index), columns in block J
   const float* G = m32 + (int64_t)k * lay.mstride + lay.tile_off(I, J);
   stage_rhs<TB>(Xs, Xi, ri);
@@ -330,7 +340,7 @@ static void backsolve_sweep(const Lay& lay, const float* m32, const float* W32, 
 hipError_t launch_backsolve(const Lay& lay, const float* m32, const float* W32,
                             const int32_t* info, double* X, int K, hipStream_t s) {
   if (lay.TB != 16 && lay.TB != 32) return hipErrorInvalidValue;
-  const int64_t total = (int64_t)lay.n * lay.TB * K;
+  const int64_t total = x0_stride(lay) * K;
   hipLaunchKernelGGL(k_bs_init, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, lay, m32,
                      info, X, K);
   if (lay.TB == 16) backsolve_sweep<16>(lay, m32, W32, info, X, K, s);
@@ -388,6 +398,8 @@ hipError_t launch_slot_reduce(const Lay& lay, const double* slots, double* red,
 // ---- p x p stage (dev_finalize) -----------------------------------------------------
 // One wave per omega.  S: the Schur tile of the bordered FP64 factorisation, or
 // (mixed form, sred non-null) the reduced cross products of k_slot_reduce.
+// An uneven batch takes each omega's order, Jacobian, y check and record
+// index from its UnitInfo (out, beta and xvi are then the batch's arrays).
 __global__ __launch_bounds__(64) void k_finalize(Lay lay, const double* __restrict__ mats,
                                                  const double* __restrict__ sred,
                                                  int64_t sred_stride,
@@ -404,9 +416,11 @@ __global__ __launch_bounds__(64) void k_finalize(Lay lay, const double* __restri
   const int TB = lay.TB;
   const double* S = sred ? sred + (int64_t)k * sred_stride
                          : mats + (int64_t)k * lay.mstride + lay.tile_off(lay.Nv, lay.Nv);
-  dev_finalize(S, TB, logdet[k], info[k], jac[0], flags[0] != 0, lam, n, p, M,
-               out + (int64_t)k * M, beta ? beta + (int64_t)k * M * p : nullptr,
-               xvi ? xvi + (int64_t)k * p * p : nullptr, smem);
+  const int ds = lay.units ? lay.units[k].ds : 0;
+  const int64_t om = lay.units ? lay.units[k].om : k;
+  dev_finalize(S, TB, logdet[k], info[k], jac[ds], flags[ds] != 0, lam,
+               lay.units ? lay.units[k].n : n, p, M, out + om * M,
+               beta ? beta + om * M * p : nullptr, xvi ? xvi + om * p * p : nullptr, smem);
 }
 
 hipError_t launch_finalize(const Lay& lay, const double* mats, const double* sred,

@@ -91,6 +91,7 @@ static void batch_planner() {
   for (int64_t slabs : {0, 1, 3, 64}) {
     pl_opts o{};
     o.chunk = slabs;
+    o.flags = PL_OPT_BATCH_PERSISTENT;
     pl_batch* b = nullptr;
     CHECK(pl_batch_create(ds.data(), D, 2, lam, 3, &o, &b) == 0 && b);
     int64_t units = 0, tasks = 0, ns = 0;
@@ -99,6 +100,22 @@ static void batch_planner() {
     CHECK(pl_batch_workspace_size(b, &ws) == 0 && ws > 0);
     pl_batch_destroy(b);
   }
+  // the size-bucketed schedule, both forms, several pass sizes and streams
+  for (int prec = 0; prec < 2; ++prec)
+    for (int64_t chunk : {0, 1, 5}) {
+      pl_opts o{};
+      o.precision = prec;
+      o.chunk = chunk;
+      o.lanes = (int32_t)(1 + chunk % 4);
+      pl_batch* b = nullptr;
+      CHECK(pl_batch_create(ds.data(), D, 2, lam, 3, &o, &b) == 0 && b);
+      int64_t units = 0, passes = 0, lanes = 0;
+      size_t ws = 0;
+      CHECK(pl_batch_stats(b, &units, &passes, &lanes) == 0 && units > 0 && passes >= 1 &&
+            lanes == o.lanes);
+      CHECK(pl_batch_workspace_size(b, &ws) == 0 && ws > 0);
+      pl_batch_destroy(b);
+    }
   pl_batch* b = nullptr;
   CHECK(pl_batch_create(ds.data(), 0, 2, lam, 3, nullptr, &b) == -2);
   ds[3].n = 1;
