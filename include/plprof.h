@@ -54,6 +54,7 @@ extern "C" {
 #define PL_E_UNSUPPORTED 3   /* size outside the compiled limits                */
 #define PL_E_SCRATCH     4   /* pl_profile_loglik_noalloc: one omega needs more
                                 than PL_NOALLOC_SCRATCH_BYTES                   */
+#define PL_TUNE_MISS     5   /* pl_tune_lookup: no stored choice (not an error) */
 
 /* per-record info codes */
 #define PL_INFO_RANK     (-1)        /* X^T V^-1 X not positive definite        */
@@ -484,7 +485,11 @@ int pl_chisq_quantile(int dof, double upper, double* q);
  * and flags are used as given).  Mixed candidates are skipped when M + p > 32.
  *   report  host, 8 doubles or NULL: per candidate (FP64, mixed flush 4, 2,
  *           1) the measured milliseconds per omega point, then the max
- *           |delta loglik| against FP64 (0 for FP64 itself, -1 if skipped).
+ *           |delta loglik| against FP64 (0 for FP64 itself, -1 if skipped;
+ *           -2 throughout when the choice came from the tuning cache).
+ * With a tuning cache set (pl_tune_cache_set), a choice stored for the same
+ * device architecture, floor(log2 n), M + p and tol is returned without
+ * timing anything; a new choice is stored.
  *   work    device workspace of pl_autotune_workspace_size bytes (same
  *           sample).
  * The call synchronises `stream` (it reads the records back).
@@ -597,6 +602,64 @@ void pl_batch_destroy(pl_batch* plan);
 #define PL_KC_COUNT  6
 int pl_profiling_enable(int on);
 int pl_profiling_read(double* ms, double* alg_flops, int64_t* launches, int nclass);
+
+/*
+ * Autotuner of the uneven batch (Section 4's hand-set launch sizes --
+ * parameter sets per iteration, global and local work sizes -- measured
+ * instead).  Candidates of pl_batch_create on the caller's datasets: the
+ * size-bucketed schedule in FP64 with 2, 4 and 8 streams and the default
+ * pass size, with 4 streams and passes of at most 256 units; the persistent
+ * kernel (FP64); the mixed form, 4 streams, flush 4 and 2 (skipped when
+ * M + p > 32).  Each candidate's plan runs once (graph capture), then twice
+ * timed with HIP events on `stream`; its records are compared with the first
+ * (FP64) candidate's.  The fastest whose largest |delta loglik| is <= tol is
+ * written to opts (precision, flush, lanes, chunk and the
+ * PL_OPT_BATCH_PERSISTENT bit; the other fields are used as given), ready for
+ * pl_batch_create.  With a tuning cache set, a choice stored for the same
+ * architecture, floor(log2 of the largest n), floor(log2 of the number of
+ * units), M + p and tol is returned without timing; a new one is stored.
+ *   datasets, D, p, lambda, M   as pl_batch_create
+ *   report  host, 14 doubles or NULL: per candidate (in the order above)
+ *           milliseconds per replay (-1 if skipped), then the max |delta
+ *           loglik| against FP64; -2 throughout for a cached choice
+ *   work    device, pl_batch_autotune_workspace_size bytes
+ * The call synchronises `stream`.  Errors: those of pl_batch_create for the
+ * datasets and options, -6 tol not finite or < 0, -7 opts NULL, -9/-10
+ * workspace NULL or too small; PL_E_UNSUPPORTED if no candidate ran.
+ */
+int pl_batch_autotune_workspace_size(const pl_dataset* datasets, int64_t D, int64_t p,
+                                     const double* lambda, int64_t M, size_t* bytes);
+int pl_batch_autotune(const pl_dataset* datasets, int64_t D, int64_t p, const double* lambda,
+                      int64_t M, double tol, pl_opts* opts, double* report, void* work,
+                      size_t work_bytes, void* stream);
+
+/*
+ * Tuning cache: the choices of pl_autotune (kind 0) and pl_batch_autotune
+ * (kind 1), keyed by (device architecture, kind, floor(log2 n) -- of the
+ * largest n for a batch --, floor(log2 units) for a batch, M + p, tol printed
+ * with 6 significant digits).  Process-wide and thread-safe; host code.
+ * pl_tune_cache_set(path): clears the table and loads `path`, a text file of
+ *   one line per choice (created on the first store; later lines of a key
+ *   win), to which every new choice is then appended; "" keeps the table in
+ *   memory only.  Until the first call, and after a call with NULL, the
+ *   autotuners neither consult nor fill the table (every call measures).
+ *   -1 if the file cannot be opened for writing.
+ * pl_tune_store / pl_tune_lookup: store or look up a choice directly (arch
+ *   NULL or "": the current device's).  Lookup returns PL_TUNE_MISS (no
+ *   change to opts) when nothing is stored; on a hit it writes precision,
+ *   flush, chunk, lanes and the PL_OPT_BATCH_PERSISTENT bit.  Errors: -2 kind,
+ *   -3 n < 2, -4 units < 1 for kind 1, -5 q out of range, -6 tol, -7 opts
+ *   NULL, -1 file write failure (store), PL_E_HIP when the architecture is
+ *   needed and no device is usable.
+ * pl_tune_cache_stats: entries, hits and misses (NULL to skip) since the last
+ *   pl_tune_cache_set.
+ */
+int pl_tune_cache_set(const char* path);
+int pl_tune_store(const char* arch, int kind, int64_t n, int64_t units, int64_t q, double tol,
+                  const pl_opts* opts, double ms);
+int pl_tune_lookup(const char* arch, int kind, int64_t n, int64_t units, int64_t q, double tol,
+                   pl_opts* opts);
+int pl_tune_cache_stats(int64_t* entries, int64_t* hits, int64_t* misses);
 
 #ifdef __cplusplus
 }

@@ -20,7 +20,10 @@ EXPORTS = ("pl_version", "pl_error_string", "pl_workspace_size", "pl_matern_work
            "pl_mle", "pl_hessian_workspace_size", "pl_hessian", "pl_config_points",
            "pl_sphere_points", "pl_lambda_grid", "pl_chisq_quantile", "pl_batch_create",
            "pl_batch_workspace_size", "pl_batch_stats", "pl_batch_run", "pl_batch_error",
-           "pl_batch_destroy", "pl_profile_loglik_noalloc")
+           "pl_batch_destroy", "pl_profile_loglik_noalloc", "pl_batch_autotune_workspace_size",
+           "pl_batch_autotune", "pl_tune_cache_set", "pl_tune_store", "pl_tune_lookup",
+           "pl_tune_cache_stats")
+PL_TUNE_MISS = 5
 KERNEL_CLASSES = ("tables", "matern", "gemm", "potrf", "trsm", "other")
 
 
@@ -160,6 +163,23 @@ def load(path: str = None):
     lib.pl_batch_error.argtypes = [_P, _P, ctypes.POINTER(ctypes.c_int32)]
     lib.pl_batch_destroy.restype = None
     lib.pl_batch_destroy.argtypes = [_P]
+    lib.pl_batch_autotune_workspace_size.restype = ctypes.c_int
+    lib.pl_batch_autotune_workspace_size.argtypes = [ctypes.POINTER(PlDataset), _I64, _I64, _P,
+                                                     _I64, ctypes.POINTER(_SZ)]
+    lib.pl_batch_autotune.restype = ctypes.c_int
+    lib.pl_batch_autotune.argtypes = [ctypes.POINTER(PlDataset), _I64, _I64, _P, _I64,
+                                      ctypes.c_double, ctypes.POINTER(PlOpts), _P, _P, _SZ, _P]
+    lib.pl_tune_cache_set.restype = ctypes.c_int
+    lib.pl_tune_cache_set.argtypes = [ctypes.c_char_p]
+    lib.pl_tune_store.restype = ctypes.c_int
+    lib.pl_tune_store.argtypes = [ctypes.c_char_p, ctypes.c_int, _I64, _I64, _I64, ctypes.c_double,
+                                  ctypes.POINTER(PlOpts), ctypes.c_double]
+    lib.pl_tune_lookup.restype = ctypes.c_int
+    lib.pl_tune_lookup.argtypes = [ctypes.c_char_p, ctypes.c_int, _I64, _I64, _I64,
+                                   ctypes.c_double, ctypes.POINTER(PlOpts)]
+    lib.pl_tune_cache_stats.restype = ctypes.c_int
+    lib.pl_tune_cache_stats.argtypes = [ctypes.POINTER(_I64), ctypes.POINTER(_I64),
+                                        ctypes.POINTER(_I64)]
     if path is None:
         _lib = lib
     return lib

@@ -280,6 +280,12 @@ def profile_param(res, omega, lam, which, drop=1.92):
 AUTOTUNE_CANDIDATES = (("fp64", 0), ("mixed", 4), ("mixed", 2), ("mixed", 1))
 
 
+class TuneReport(dict):
+    """Per-candidate measurements of an autotuner; `cached` is True when the
+    choice came from the tuning cache (nothing was timed)."""
+    cached = False
+
+
 def autotune(locs, y, X, omega, lam, tol=1e-3, sample=0, device="cuda", stream=None,
              inputs=None):
     """pl_autotune: the fastest form whose |delta loglik| against FP64 on the
@@ -304,9 +310,52 @@ def autotune(locs, y, X, omega, lam, tol=1e-3, sample=0, device="cuda", stream=N
                          _ptr(work), work.numel(), _stream_ptr(stream))
     check(rc, "pl_autotune")
     choice = {"precision": "mixed" if o.precision == _lib.PL_MIXED else "fp64", "flush": o.flush}
-    report = {f"{pr}" + (f"/flush{f}" if f else ""): {"ms_per_omega": rep[i], "max_abs_dl": rep[4 + i]}
-              for i, (pr, f) in enumerate(AUTOTUNE_CANDIDATES)}
+    report = TuneReport({f"{pr}" + (f"/flush{f}" if f else ""):
+                         {"ms_per_omega": rep[i], "max_abs_dl": rep[4 + i]}
+                         for i, (pr, f) in enumerate(AUTOTUNE_CANDIDATES)})
+    report.cached = bool(rep[0] == -2.0)
     return choice, report
+
+
+def tune_cache_set(path=None):
+    """pl_tune_cache_set: the autotuners reuse and persist their choices in the
+    file `path` ("" : in memory only; None: no cache, every call measures)."""
+    check(load().pl_tune_cache_set(None if path is None else path.encode()), "pl_tune_cache_set")
+
+
+def _choice(o):
+    return {"precision": "mixed" if o.precision == _lib.PL_MIXED else "fp64", "flush": o.flush,
+            "chunk": int(o.chunk), "lanes": int(o.lanes),
+            "schedule": "persistent" if o.flags & _lib.PL_OPT_BATCH_PERSISTENT else "bucketed"}
+
+
+def tune_lookup(n, q, tol, kind=0, units=0, arch=None):
+    """pl_tune_lookup: the stored choice for this key as a dict, or None."""
+    o = _opts()
+    rc = load().pl_tune_lookup(arch.encode() if arch else None, int(kind), int(n), int(units),
+                               int(q), float(tol), ctypes.byref(o))
+    if rc == _lib.PL_TUNE_MISS:
+        return None
+    check(rc, "pl_tune_lookup")
+    return _choice(o)
+
+
+def tune_store(choice, n, q, tol, kind=0, units=0, arch=None, ms=0.0):
+    """pl_tune_store: store `choice` (a dict as tune_lookup returns) for this key."""
+    o = _opts(choice.get("precision", "fp64"), choice.get("chunk", 0), 1, True,
+              choice.get("flush", 0))
+    o.lanes = int(choice.get("lanes", 0))
+    if choice.get("schedule") == "persistent":
+        o.flags |= _lib.PL_OPT_BATCH_PERSISTENT
+    check(load().pl_tune_store(arch.encode() if arch else None, int(kind), int(n), int(units),
+                               int(q), float(tol), ctypes.byref(o), float(ms)), "pl_tune_store")
+
+
+def tune_stats():
+    e, h, m = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    check(load().pl_tune_cache_stats(ctypes.byref(e), ctypes.byref(h), ctypes.byref(m)),
+          "pl_tune_cache_stats")
+    return {"entries": e.value, "hits": h.value, "misses": m.value}
 
 
 PARAM_NAMES_INTERNAL = ("gamma1", "shape~", "nu", "gamma2", "gamma3")

@@ -10,7 +10,7 @@ import torch
 
 from . import _lib
 from ._lib import PlDataset, check, load
-from .api import Inputs, _host_f64, _opts, _stream_ptr, unpack_records
+from .api import Inputs, TuneReport, _host_f64, _opts, _stream_ptr, unpack_records
 
 
 class Batch:
@@ -98,3 +98,47 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# candidates of pl_batch_autotune, in the order of its report
+BATCH_CANDIDATES = ("fp64/bucketed/lanes2", "fp64/bucketed/lanes4", "fp64/bucketed/lanes8",
+                    "fp64/bucketed/lanes4/chunk256", "fp64/persistent", "mixed/flush4/lanes4",
+                    "mixed/flush2/lanes4")
+
+
+def autotune(problems, lam, tol=1e-3, device="cuda", inputs=None, stream=None):
+    """pl_batch_autotune on these datasets: returns (choice, report); choice is
+    a dict of Batch keyword arguments (precision, flush, lanes, chunk,
+    schedule), report per candidate {"ms", "max_abs_dl"} (report.cached: the
+    choice came from the tuning cache)."""
+    lib = load()
+    inputs = inputs if inputs is not None else [Inputs(pr.locs, pr.y, pr.X, device)
+                                                for pr in problems]
+    omegas = [_host_f64(pr.omega, 5) for pr in problems]
+    lam = _host_f64(lam).reshape(-1)
+    p = inputs[0].p
+    D = len(inputs)
+    arr = (PlDataset * D)()
+    for i, (inp, om) in enumerate(zip(inputs, omegas)):
+        arr[i] = PlDataset(inp.locs.data_ptr(), inp.y.data_ptr(), inp.Xc.data_ptr(), inp.n,
+                           om.ctypes.data, om.shape[0])
+    sz = ctypes.c_size_t(0)
+    check(lib.pl_batch_autotune_workspace_size(arr, D, p, lam.ctypes.data_as(ctypes.c_void_p),
+                                               lam.shape[0], ctypes.byref(sz)),
+          "pl_batch_autotune_workspace_size")
+    work = torch.empty(sz.value, dtype=torch.uint8, device=device)
+    o = _opts()
+    rep = (ctypes.c_double * (2 * len(BATCH_CANDIDATES)))()
+    check(lib.pl_batch_autotune(arr, D, p, lam.ctypes.data_as(ctypes.c_void_p), lam.shape[0],
+                                float(tol), ctypes.byref(o), rep,
+                                ctypes.c_void_p(work.data_ptr()), work.numel(), _stream_ptr(stream)),
+          "pl_batch_autotune")
+    del work
+    choice = {"precision": "mixed" if o.precision == _lib.PL_MIXED else "fp64",
+              "flush": int(o.flush), "lanes": int(o.lanes), "chunk": int(o.chunk),
+              "schedule": "persistent" if o.flags & _lib.PL_OPT_BATCH_PERSISTENT else "bucketed"}
+    nc = len(BATCH_CANDIDATES)
+    report = TuneReport({c: {"ms": rep[i], "max_abs_dl": rep[nc + i]}
+                         for i, c in enumerate(BATCH_CANDIDATES)})
+    report.cached = bool(rep[0] == -2.0)
+    return choice, report

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libplprof.so")
 SOURCES = ["api.hip", "matern.hip", "chol.hip", "profile.hip", "batch.hip", "curves.hip", "extract.hip", "mle.hip", "config.hip",
-           "noalloc.hip"]
+           "noalloc.hip", "tune.hip"]
 
 
 def hipcc():

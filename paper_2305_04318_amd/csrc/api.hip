@@ -607,6 +607,11 @@ int pl_autotune(const double* locs, const double* y, const double* X, int64_t n,
   if (!std::isfinite(tol) || tol < 0.0) return -11;
   if (!opts) return -12;
   if (!work) return -14;
+  if (tune_cache_find(0, n, 0, M + p, tol, opts)) {
+    if (report)
+      for (int c = 0; c < 2 * TUNE_NCAND; ++c) report[c] = -2.0;  // cached: nothing timed
+    return PL_OK;
+  }
   const int64_t S = std::min<int64_t>(K, sample > 0 ? sample : TUNE_SAMPLE);
   const bool with_mixed = M + p <= 32;
   const size_t call_bytes = tune_call_bytes(n, p, S, M, with_mixed);
@@ -680,6 +685,7 @@ int pl_autotune(const double* locs, const double* y, const double* X, int64_t n,
     if (ms_per[c] >= 0.0 && err[c] >= 0.0 && err[c] <= tol && ms_per[c] < ms_per[best]) best = c;
   opts->precision = best == 0 ? PL_FP64 : PL_MIXED;
   opts->flush = kTuneFlush[best];
+  tune_cache_put(0, n, 0, M + p, tol, *opts, ms_per[best] * S);
   if (report) {
     for (int c = 0; c < TUNE_NCAND; ++c) {
       report[c] = ms_per[c];

@@ -220,6 +220,12 @@ hipError_t run_pass(const PassArgs& a, const PassBufs& b, int kk, hipStream_t s)
 // Suspends (pause = true) or resumes the per-kernel-class event timing;
 // returns whether it was on before the call.
 bool profiling_pause(bool pause);
+
+// Tuning cache (tune.hip): kind 0 pl_autotune, 1 pl_batch_autotune; a hit
+// writes the stored choice into opts.
+bool tune_cache_find(int kind, int64_t n, int64_t units, int64_t q, double tol, pl_opts* opts);
+void tune_cache_put(int kind, int64_t n, int64_t units, int64_t q, double tol, const pl_opts& o,
+                    double ms);
 Lay packed_layout(int64_t n, int64_t q);
 hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int n, hipStream_t s);
 

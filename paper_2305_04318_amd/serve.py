@@ -48,7 +48,7 @@ class Request:
     X: np.ndarray
     omega: np.ndarray
     lam: np.ndarray
-    precision: str = "fp64"
+    precision: str = "fp64"          # "fp64", "mixed" or "auto" (tuning cache)
     deadline: float = float("inf")   # admission deadline, seconds after arrival
     # filled in by the server
     admitted: float = float("nan")
@@ -250,7 +250,7 @@ class GpuExecutor:
     `hbm_budget` bytes allocated up front."""
 
     def __init__(self, hbm_budget: int, slots: int = 4, device: str = "cuda",
-                 max_request_work: int = 16 << 30):
+                 max_request_work: int = 16 << 30, tune_tol: float = 1e-3):
         import concurrent.futures as cf
 
         import torch
@@ -260,15 +260,31 @@ class GpuExecutor:
         self.device = device
         self.slots = int(slots)
         self.max_request_work = int(max_request_work)
+        self.tune_tol = float(tune_tol)
+        self._forms = {}
         self.arena = Arena(hbm_budget)
         self.buf = torch.empty(self.arena.size, dtype=torch.uint8, device=device)
         self.streams = [torch.cuda.Stream(device=device) for _ in range(self.slots)]
         self.pool = cf.ThreadPoolExecutor(max_workers=self.slots)
 
+    # -- form of one request ----------------------------------------------
+    def form(self, req):
+        """(precision, flush) of a request: as given, or for precision "auto"
+        the tuning cache's choice for its size (pl_tune_lookup with the
+        executor's budget `tune_tol`), FP64 when nothing is stored."""
+        if req.precision != "auto":
+            return req.precision, 0
+        key = (req.n, req.p + req.M)
+        if key not in self._forms:
+            c = self.api.tune_lookup(req.n, req.p + req.M, self.tune_tol)
+            self._forms[key] = (c["precision"], c["flush"]) if c else ("fp64", 0)
+        return self._forms[key]
+
     # -- memory plan of one request ----------------------------------------
     def plan(self, req):
         """(chunk, [(name, bytes)]) for the request's carve-out."""
-        n, p, K, M, prec = req.n, req.p, req.K, req.M, req.precision
+        n, p, K, M = req.n, req.p, req.K, req.M
+        prec = self.form(req)[0]
         chunk = 0
         work = self.api.workspace_size(n, p, K, M, prec, 0)
         if work > self.max_request_work:
@@ -322,8 +338,9 @@ class GpuExecutor:
             inp = _ArenaInputs(locs, y, Xc, n, p, self.device)
             out = views["out"].view(torch.float64).view(K, M, 10)
             beta = views["beta"].view(torch.float64).view(K, M, p)
+            prec, flush = self.form(req)
             res = self.api.profile_loglik(None, None, None, req.omega, req.lam,
-                                          precision=req.precision, chunk=chunk,
+                                          precision=prec, flush=flush, chunk=chunk,
                                           return_beta=True, out=out, beta=beta,
                                           work=views["work"], stream=s, inputs=inp)
             host = {k: v.to("cpu", non_blocking=False).numpy() for k, v in res.items()}

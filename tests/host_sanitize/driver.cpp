@@ -7,6 +7,7 @@
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
+#include <unistd.h>
 
 #include <vector>
 
@@ -198,7 +199,31 @@ static void step4_extraction() {
   }
 }
 
+static void tuning_cache() {
+  char path[] = "/tmp/plprof_tune_XXXXXX";
+  const int fd = mkstemp(path);
+  CHECK(fd >= 0);
+  if (fd < 0) return;
+  close(fd);
+  CHECK(pl_tune_cache_set(path) == 0);
+  pl_opts o{};
+  o.precision = PL_MIXED;
+  o.flush = 2;
+  o.lanes = 4;
+  CHECK(pl_tune_store("gfx950", 0, 2000, 0, 12, 1e-3, &o, 1.0) == 0);
+  CHECK(pl_tune_store("gfx950", 1, 1500, 32768, 4, 1e-3, &o, 2.0) == 0);
+  pl_opts g{};
+  CHECK(pl_tune_lookup("gfx950", 0, 1500, 0, 12, 1e-3, &g) == 0 && g.flush == 2);
+  CHECK(pl_tune_lookup("gfx950", 0, 4000, 0, 12, 1e-3, &g) == PL_TUNE_MISS);
+  CHECK(pl_tune_cache_set(path) == 0);  // reload
+  int64_t entries = 0;
+  CHECK(pl_tune_cache_stats(&entries, nullptr, nullptr) == 0 && entries == 2);
+  CHECK(pl_tune_cache_set(nullptr) == 0);
+  unlink(path);
+}
+
 int main() {
+  tuning_cache();
   workspace_sizes();
   batch_planner();
   step2_and_params();

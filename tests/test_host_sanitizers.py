@@ -14,10 +14,10 @@ from concurrent.futures import ThreadPoolExecutor
 
 import pytest
 
+from paper_2305_04318_amd.build import SOURCES  # every source of the library
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2305_04318_amd", "csrc")
-SOURCES = ["api.hip", "matern.hip", "chol.hip", "profile.hip", "batch.hip", "curves.hip",
-           "extract.hip", "mle.hip", "config.hip", "noalloc.hip"]
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = ["-std=c++17", "-O1", "-g", "--offload-arch=gfx950",
          "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
