@@ -64,6 +64,7 @@ extern "C" {
 /* compiled limits */
 #define PL_MAX_P      32     /* covariates                                      */
 #define PL_MAX_M      64     /* Box-Cox values per call                         */
+#define PL_MAX_Q_MIXED 64    /* PL_MIXED: M + p (bordered right-hand sides)      */
 #define PL_MIN_SHAPE  0.05
 #define PL_MAX_SHAPE  100.0
 
@@ -196,7 +197,7 @@ int pl_chol_batched(void* V, int64_t n, int64_t K, int64_t ld, int precision,
  * -6 omega NULL or out of domain (as pl_matern_cov); -7 K < 1;
  * -8 lambda NULL or not finite; -9 M < 1 or M > PL_MAX_M; -10 out NULL;
  * -13 bad option; -14/-15 workspace NULL or too small; PL_E_UNSUPPORTED for
- * PL_MIXED with M + p > 32.
+ * PL_MIXED with M + p > PL_MAX_Q_MIXED.
  * y <= 0 is detected on the device: every record then carries PL_INFO_BAD_Y.
  *
  * PL_MIXED: V is factored in FP32 (FP32 MFMA off-diagonal updates and panel
@@ -229,7 +230,8 @@ int pl_profile_loglik(const double* locs, const double* y, const double* X,
  * stream must belong to the current device.
  * Limits: PL_E_SCRATCH when one omega's workspace exceeds the array: FP64
  * n above about 8,050 (M + p <= 16) or 7,900 (M + p <= 32); PL_MIXED n above
- * about 6,400 (M + p <= 16) or 6,250 (M + p <= 32).
+ * about 6,400 (M + p <= 16), 6,250 (M + p <= 32) or somewhat less for taller
+ * borders (M + p <= 64).
  * Calls that overlap on one GPU (different streams or host threads without
  * ordering between them) share the array and race; serialise them.
  */
@@ -345,7 +347,7 @@ int pl_from_internal(const double* internal, int64_t K, int shape_transform, dou
  * step, capped at 2) or halves its steps; a start stops when its largest step
  * is below tol.  Steps start at 0.5.  lambda is maximised over the M values
  * of every call; after the search, the best start is re-evaluated on a fine
- * lambda set (its value plus min(64, 32 - p for PL_MIXED) - 1 evenly spaced
+ * lambda set (its value plus min(64, PL_MAX_Q_MIXED - p for PL_MIXED) - 1 evenly spaced
  * values between the neighbouring caller values) and polished by a second
  * search (initial step min(0.5, 16 tol)) on that set.
  *   omega0     host, starts x 5 natural starting points (shape in
@@ -368,7 +370,7 @@ int pl_from_internal(const double* internal, int64_t K, int shape_transform, dou
  * -9 M out of range; -10 fixed_mask outside [0, 31]; -11 reml not 0 or 1;
  * -12 tol out of range; -13 max_iter < 1; -14..-16 output NULL; -18 bad
  * option; -19/-20 workspace NULL or too small; PL_E_UNSUPPORTED for PL_MIXED
- * with M + p > 32 or when no start has a usable record.
+ * with M + p > PL_MAX_Q_MIXED or when no start has a usable record.
  * pl_mle_workspace_size: -1/-2 as pl_workspace_size, -3 starts out of range,
  * -4 M out of range, -5 bad option, -6 bytes NULL.
  */
@@ -482,7 +484,8 @@ int pl_chisq_quantile(int dof, double upper, double* q);
  * points the caller will evaluate per call.  The fastest candidate whose
  * largest |delta loglik| over the sampled records is <= tol is written to
  * opts->precision and opts->flush (FP64 always qualifies; opts->refine, chunk
- * and flags are used as given).  Mixed candidates are skipped when M + p > 32.
+ * and flags are used as given).  Mixed candidates are skipped when
+ * M + p > PL_MAX_Q_MIXED.
  *   report  host, 8 doubles or NULL: per candidate (FP64, mixed flush 4, 2,
  *           1) the measured milliseconds per omega point, then the max
  *           |delta loglik| against FP64 (0 for FP64 itself, -1 if skipped;
@@ -546,7 +549,7 @@ typedef struct pl_batch pl_batch;
  * NULL, K < 1, omega out of domain), -2 D out of range, -3 p out of range,
  * -4 lambda NULL or not finite, -5 M out of range, -6 bad option (including
  * PL_MIXED with the persistent schedule), -7 plan NULL; PL_E_UNSUPPORTED if
- * the task list cannot be built or PL_MIXED has M + p > 32.
+ * the task list cannot be built or PL_MIXED has M + p > PL_MAX_Q_MIXED.
  */
 int pl_batch_create(const pl_dataset* datasets, int64_t D, int64_t p, const double* lambda,
                     int64_t M, const pl_opts* opts, pl_batch** plan);
@@ -610,7 +613,7 @@ int pl_profiling_read(double* ms, double* alg_flops, int64_t* launches, int ncla
  * size-bucketed schedule in FP64 with 2, 4 and 8 streams and the default
  * pass size, with 4 streams and passes of at most 256 units; the persistent
  * kernel (FP64); the mixed form, 4 streams, flush 4 and 2 (skipped when
- * M + p > 32).  Each candidate's plan runs once (graph capture), then twice
+ * M + p > PL_MAX_Q_MIXED).  Each candidate's plan runs once (graph capture), then twice
  * timed with HIP events on `stream`; its records are compared with the first
  * (FP64) candidate's.  The fastest whose largest |delta loglik| is <= tol is
  * written to opts (precision, flush, lanes, chunk and the

@@ -430,7 +430,7 @@ int pl_workspace_size(int64_t n, int64_t p, int64_t K, int64_t M, const pl_opts*
   if (!bytes) return -6;
   if (opts && opts->precision != PL_FP64 && opts->precision != PL_MIXED) return -5;
   const bool mixed = opts && opts->precision == PL_MIXED;
-  if (mixed && M + p > 32) return PL_E_UNSUPPORTED;
+  if (mixed && M + p > PL_MAX_Q_MIXED) return PL_E_UNSUPPORTED;
   const Lay lay = packed_layout(n, M + p);
   int64_t kc = K;
   if (opts && opts->chunk > 0) kc = std::min<int64_t>(kc, opts->chunk);
@@ -470,7 +470,7 @@ int pl_profile_loglik(const double* locs, const double* y, const double* X, int6
     if (flush != 1 && flush != 2 && flush != 4) return -13;
   }
   const bool mixed = precision == PL_MIXED;
-  if (mixed && M + p > 32) return PL_E_UNSUPPORTED;
+  if (mixed && M + p > PL_MAX_Q_MIXED) return PL_E_UNSUPPORTED;
   if (!work) return -14;
   hipStream_t s = (hipStream_t)stream;
 
@@ -582,7 +582,7 @@ int pl_autotune_workspace_size(int64_t n, int64_t p, int64_t K, int64_t M, int64
   if (sample < 0) return -5;
   if (!bytes) return -6;
   const int64_t S = std::min<int64_t>(K, sample > 0 ? sample : TUNE_SAMPLE);
-  *bytes = tune_call_bytes(n, p, S, M, M + p <= 32) + 2 * tune_records_bytes(S, M);
+  *bytes = tune_call_bytes(n, p, S, M, M + p <= PL_MAX_Q_MIXED) + 2 * tune_records_bytes(S, M);
   return PL_OK;
 }
 
@@ -613,7 +613,7 @@ int pl_autotune(const double* locs, const double* y, const double* X, int64_t n,
     return PL_OK;
   }
   const int64_t S = std::min<int64_t>(K, sample > 0 ? sample : TUNE_SAMPLE);
-  const bool with_mixed = M + p <= 32;
+  const bool with_mixed = M + p <= PL_MAX_Q_MIXED;
   const size_t call_bytes = tune_call_bytes(n, p, S, M, with_mixed);
   const size_t rec_bytes = tune_records_bytes(S, M);
   if (call_bytes == 0 || work_bytes < call_bytes + 2 * rec_bytes) return -15;

@@ -534,7 +534,7 @@ int pl_batch_create(const pl_dataset* datasets, int64_t D, int64_t p, const doub
     if (persistent && mixed) return -6;  // the persistent kernel carries FP64 tasks only
   }
   if (!plan) return -7;
-  if (mixed && M + p > 32) return PL_E_UNSUPPORTED;
+  if (mixed && M + p > PL_MAX_Q_MIXED) return PL_E_UNSUPPORTED;
   pl_batch* b = new pl_batch();
   b->p = (int32_t)p;
   b->M = (int32_t)M;

@@ -140,7 +140,7 @@ __device__ __forceinline__ void dev_diag_mx(const Lay& lay, float* __restrict__ 
 // as an FP32 tile) are dispatched first, the off-diagonal tiles (FP32 MFMA
 // with FP64 folds) after them, so the diagonal work overlaps the bulk of the
 // update instead of running as a launch of K workgroups of its own.
-template <int FLUSH>
+template <int FLUSH, bool BORDER>
 __global__ __launch_bounds__(256, 2) void k_col_update_mx(Lay lay, float* __restrict__ m32,
                                                           const double* __restrict__ m64,
                                                           int64_t m64stride,
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(256, 2) void k_col_update_mx(Lay lay, float* __rest
   const int b = blockIdx.x;
   if (b < K) {
     if (info[b] != 0) return;  // uniform for the workgroup
-    dev_diag_mx<true, true>(lay_of(lay, b), m32, m64, m64stride, dscratch, b, J, lds);
+    dev_diag_mx<true, BORDER>(lay_of(lay, b), m32, m64, m64stride, dscratch, b, J, lds);
     return;
   }
   const int G = K * nOff;
@@ -203,28 +203,28 @@ hipError_t launch_gemm_col(const Lay& lay, double* mats, const int32_t* info, in
 hipError_t launch_gemm_col_mx(const Lay& lay, float* m32, const double* m64, int64_t m64stride,
                               double* dscratch, const int32_t* info, int J, int nI, int K,
                               int flush, hipStream_t s) {
-  // nI counts the tile rows from J down (the diagonal tile included).  The
-  // mixed form has M + p <= 32, so the bordered row (the last of the nI rows
-  // when J > 0) is always folded into the diagonal tile's workgroup.
-  if (!(lay.kind == 0 && lay.q > 0 && lay.TB <= 32)) return hipErrorInvalidValue;
-  const int nOff = (J > 0) ? nI - 2 : 0;  // V tiles strictly below the diagonal
+  // nI counts the tile rows from J down (the diagonal tile included).  A
+  // bordered row of at most 32 rows (the last of the nI rows when J > 0) is
+  // folded into the diagonal tile's workgroup; a taller one (M + p up to 64)
+  // is updated as one more off-diagonal tile row.
+  if (!(lay.kind == 0 && lay.q > 0 && lay.TB <= 64)) return hipErrorInvalidValue;
+  const bool border = lay.TB <= 32;
+  const int nOff = (J > 0) ? nI - (border ? 2 : 1) : 0;  // tiles strictly below the diagonal
   const int G = K * (nOff + 1);
-  switch (flush) {
-    case 1:
-      hipLaunchKernelGGL(k_col_update_mx<1>, dim3(G), dim3(256), 0, s, lay, m32, m64, m64stride,
-                         dscratch, info, J, nOff, K);
-      break;
-    case 2:
-      hipLaunchKernelGGL(k_col_update_mx<2>, dim3(G), dim3(256), 0, s, lay, m32, m64, m64stride,
-                         dscratch, info, J, nOff, K);
-      break;
-    case 4:
-      hipLaunchKernelGGL(k_col_update_mx<4>, dim3(G), dim3(256), 0, s, lay, m32, m64, m64stride,
-                         dscratch, info, J, nOff, K);
-      break;
+#define PL_MX_LAUNCH(F, B)                                                                     \
+  hipLaunchKernelGGL((k_col_update_mx<F, B>), dim3(G), dim3(256), 0, s, lay, m32, m64, m64stride, \
+                     dscratch, info, J, nOff, K)
+  switch (flush * 2 + (border ? 1 : 0)) {
+    case 3: PL_MX_LAUNCH(1, true); break;
+    case 2: PL_MX_LAUNCH(1, false); break;
+    case 5: PL_MX_LAUNCH(2, true); break;
+    case 4: PL_MX_LAUNCH(2, false); break;
+    case 9: PL_MX_LAUNCH(4, true); break;
+    case 8: PL_MX_LAUNCH(4, false); break;
     default:
       return hipErrorInvalidValue;
   }
+#undef PL_MX_LAUNCH
   return hipGetLastError();
 }
 
@@ -509,8 +509,8 @@ __device__ __forceinline__ void wg_gemm_rhs(d4 (&acc)[4][4], double* lds,
                                             int kmax, bool do_mfma, int ni) {
   constexpr int N = 2, KC = 16, PPC = T / N;
   constexpr int BR = 16 * NB, LB = BR + 4, BPPC = BR / N, BPIECES = KC * BPPC;
+  constexpr int BQ = (BPIECES + 255) / 256;  // B pieces per thread
   constexpr int STAGE = KC * (LROW + LB);
-  static_assert(BPIECES <= 256, "one B piece per thread");
   typedef dbl2 V;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1;
@@ -518,7 +518,7 @@ __device__ __forceinline__ void wg_gemm_rhs(d4 (&acc)[4][4], double* lds,
   if (nchunks <= 0) return;
   ni = __builtin_amdgcn_readfirstlane(ni);
   do_mfma = __builtin_amdgcn_readfirstlane((int)do_mfma) != 0;
-  V ra[2][4], rb[2];
+  V ra[2][4], rb[2][BQ];
   auto fetch = [&](int k0, auto setc) {
     constexpr int S = decltype(setc)::value;
 #pragma unroll
@@ -527,9 +527,13 @@ __device__ __forceinline__ void wg_gemm_rhs(d4 (&acc)[4][4], double* lds,
       const int col = idx / PPC, row = (idx % PPC) * N;
       ra[S][q] = fetch_piece<double, true>(A, lda, arows, k0 + col, kmax, row);
     }
-    if (tid < BPIECES) {
-      const int col = tid / BPPC, row = (tid % BPPC) * N;
-      rb[S] = fetch_piece<double, true>(B, ldb, brows, k0 + col, kmax, row);
+#pragma unroll
+    for (int q = 0; q < BQ; ++q) {
+      const int idx = tid + 256 * q;
+      if (idx < BPIECES) {
+        const int col = idx / BPPC, row = (idx % BPPC) * N;
+        rb[S][q] = fetch_piece<double, true>(B, ldb, brows, k0 + col, kmax, row);
+      }
     }
   };
   auto stash = [&](auto setc) {
@@ -542,9 +546,13 @@ __device__ __forceinline__ void wg_gemm_rhs(d4 (&acc)[4][4], double* lds,
       const int col = idx / PPC, row = (idx % PPC) * N;
       *reinterpret_cast<V*>(sa + col * LROW + row) = ra[S][q];
     }
-    if (tid < BPIECES) {
-      const int col = tid / BPPC, row = (tid % BPPC) * N;
-      *reinterpret_cast<V*>(sb + col * LB + row) = rb[S];
+#pragma unroll
+    for (int q = 0; q < BQ; ++q) {
+      const int idx = tid + 256 * q;
+      if (idx < BPIECES) {
+        const int col = idx / BPPC, row = (idx % BPPC) * N;
+        *reinterpret_cast<V*>(sb + col * LB + row) = rb[S][q];
+      }
     }
   };
   using S0 = std::integral_constant<int, 0>;
@@ -593,7 +601,7 @@ constexpr int qform_lds_doubles() {
 }
 
 template <int TB>
-__global__ __launch_bounds__(256, TB == 16 ? 3 : 2) void k_qform(Lay lay, const double* __restrict__ m64,
+__global__ __launch_bounds__(256, TB == 16 ? 3 : (TB == 32 ? 2 : 1)) void k_qform(Lay lay, const double* __restrict__ m64,
                                                   int64_t stride64, const double* __restrict__ X,
                                                   const double* __restrict__ rhs,
                                                   const int32_t* __restrict__ info,
@@ -619,8 +627,8 @@ __global__ __launch_bounds__(256, TB == 16 ? 3 : 2) void k_qform(Lay lay, const 
   // B_I, same layout (an uneven batch: the unit's dataset's right-hand sides)
   const double* Bi = rhs + (lay.units ? lay.units[k].rhs : 0) + (int64_t)I * T * TB;
   // LDS after the core: Y = V_IJ x0_J column-major with the odd stride T + 1
-  // (the pair loop below reads 16 columns of Y at once), then x0_I.  With
-  // TB <= 32 both fit the core's LDS block.
+  // (the pair loop below reads 16 columns of Y at once), then x0_I (the
+  // block is sized for whichever of the two uses is larger).
   constexpr int LY = T + 1;
   double* Ys = lds;
   double* Xs = lds + LY * TB;
@@ -698,6 +706,12 @@ hipError_t launch_qform(const Lay& lay, const double* m64, int64_t stride64, con
                        slots, refine, ntile, G);
   else if (lay.TB == 32)
     hipLaunchKernelGGL(k_qform<32>, dim3(G), dim3(256), 0, s, lay, m64, stride64, X, rhs, info,
+                       slots, refine, ntile, G);
+  else if (lay.TB == 48)
+    hipLaunchKernelGGL(k_qform<48>, dim3(G), dim3(256), 0, s, lay, m64, stride64, X, rhs, info,
+                       slots, refine, ntile, G);
+  else if (lay.TB == 64)
+    hipLaunchKernelGGL(k_qform<64>, dim3(G), dim3(256), 0, s, lay, m64, stride64, X, rhs, info,
                        slots, refine, ntile, G);
   else
     return hipErrorInvalidValue;

@@ -185,8 +185,8 @@ int compass(Evaluator& ev, std::vector<double>& x, const std::vector<int64_t>& i
 }
 
 int64_t fine_columns(int64_t p, const pl_opts* opts) {
-  // the mixed form carries at most 32 bordered columns (M + p)
-  if (opts && opts->precision == PL_MIXED) return std::min<int64_t>(PL_MAX_M, 32 - p);
+  // the mixed form carries at most PL_MAX_Q_MIXED bordered columns (M + p)
+  if (opts && opts->precision == PL_MIXED) return std::min<int64_t>(PL_MAX_M, PL_MAX_Q_MIXED - p);
   return PL_MAX_M;
 }
 

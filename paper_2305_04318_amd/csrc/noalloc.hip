@@ -53,7 +53,7 @@ extern "C" int pl_profile_loglik_noalloc(const double* locs, const double* y, co
   // the largest omega count per call whose workspace fits the array
   size_t need = 0;
   int rc = pl_workspace_size(n, p, 1, M, opts, &need);
-  if (rc > 0) return rc;      // PL_E_UNSUPPORTED: PL_MIXED with M + p > 32
+  if (rc > 0) return rc;      // PL_E_UNSUPPORTED: PL_MIXED with M + p > PL_MAX_Q_MIXED
   if (rc < 0) return -13;     // the sizes were checked above: a bad option
   if (need > cap) return PL_E_SCRATCH;
   int64_t lo = 1, hi = K;

@@ -134,8 +134,8 @@ static_assert(T * (T + 1) % 4 == 0, "right-hand sides follow the tile in LDS, 16
 // (n rows of TB values, FP64) starts as Z and is swept from the bottom tile row:
 //   k_bs_diag(I)   : X_I <- W_I^T X_I           (W_I = L_II^-1, one workgroup per omega)
 //   k_bs_update(I) : X_J <- X_J - L_IJ^T X_I   (J < I, one workgroup per (omega, J))
-// TB (16 or 32: the mixed form takes M + p <= 32) is a template parameter so
-// that the per-thread column loop is straight-line code.  Thread (r, h) owns
+// TB (16, 32, 48 or 64: the mixed form takes M + p <= 64) is a template
+// parameter so that the per-thread column loop is straight-line code.  Thread (r, h) owns
 // row r of the output tile and the contiguous columns h*TB/2 .. h*TB/2+TB/2-1;
 // a wave has one h, so its reads of the right-hand sides are LDS broadcasts.
 
@@ -339,12 +339,16 @@ static void backsolve_sweep(const Lay& lay, const float* m32, const float* W32, 
 
 hipError_t launch_backsolve(const Lay& lay, const float* m32, const float* W32,
                             const int32_t* info, double* X, int K, hipStream_t s) {
-  if (lay.TB != 16 && lay.TB != 32) return hipErrorInvalidValue;
+  if (lay.TB != 16 && lay.TB != 32 && lay.TB != 48 && lay.TB != 64) return hipErrorInvalidValue;
   const int64_t total = x0_stride(lay) * K;
   hipLaunchKernelGGL(k_bs_init, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, lay, m32,
                      info, X, K);
-  if (lay.TB == 16) backsolve_sweep<16>(lay, m32, W32, info, X, K, s);
-  else backsolve_sweep<32>(lay, m32, W32, info, X, K, s);
+  switch (lay.TB) {
+    case 16: backsolve_sweep<16>(lay, m32, W32, info, X, K, s); break;
+    case 32: backsolve_sweep<32>(lay, m32, W32, info, X, K, s); break;
+    case 48: backsolve_sweep<48>(lay, m32, W32, info, X, K, s); break;
+    default: backsolve_sweep<64>(lay, m32, W32, info, X, K, s); break;
+  }
   return hipGetLastError();
 }
 

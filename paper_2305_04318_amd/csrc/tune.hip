@@ -259,7 +259,7 @@ int pl_batch_autotune_workspace_size(const pl_dataset* datasets, int64_t D, int6
   size_t need = 0;
   int64_t U = 0;
   for (int c = 0; c < NBC; ++c) {
-    if (kBatchCand[c].precision == PL_MIXED && M + p > 32) continue;
+    if (kBatchCand[c].precision == PL_MIXED && M + p > PL_MAX_Q_MIXED) continue;
     pl_opts o{};
     o.precision = kBatchCand[c].precision;
     o.flush = kBatchCand[c].flush;
@@ -314,7 +314,7 @@ int pl_batch_autotune(const pl_dataset* datasets, int64_t D, int64_t p, const do
   for (int c = 0; c < NBC && rc == PL_OK; ++c) {
     ms[c] = err[c] = -1.0;
     const BatchCand& bc = kBatchCand[c];
-    if (bc.precision == PL_MIXED && M + p > 32) continue;
+    if (bc.precision == PL_MIXED && M + p > PL_MAX_Q_MIXED) continue;
     pl_opts o = *opts;
     o.precision = bc.precision;
     o.flush = bc.flush;

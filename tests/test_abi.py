@@ -219,4 +219,7 @@ def test_noalloc_rejects_problems_beyond_its_scratch():
     assert call(7000, precision=_lib.PL_MIXED) == 4
     assert call(1) == -4 and call(100, p=0) == -5 and call(100, K=0) == -7
     assert call(100, M=0) == -9 and call(100, precision=7) == -13
-    assert call(100, p=30, M=8, precision=_lib.PL_MIXED) == 3
+    assert call(100, p=30, M=35, precision=_lib.PL_MIXED) == 3
+    o = _lib.PlOpts()
+    o.precision = _lib.PL_MIXED
+    assert _ws(100, 30, 1, 34, o)[0] == 0 and _ws(100, 30, 1, 35, o)[0] == 3  # M + p <= 64

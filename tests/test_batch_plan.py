@@ -123,10 +123,10 @@ def test_bucketed_plan_passes_and_streams(chunk, lanes, precision):
 
 
 def test_bucketed_plan_option_checks():
-    # the persistent kernel carries FP64 tasks only; the mixed form takes M + p <= 32
+    # the persistent kernel carries FP64 tasks only; the mixed form takes M + p <= 64
     rc, h, _ = _plan([300], [2], persistent=True, precision=1)
     assert rc == -6
-    rc, h, _ = _plan([300], [2], p=4, M=29, persistent=False, precision=1)
+    rc, h, _ = _plan([300], [2], p=4, M=61, persistent=False, precision=1)
     assert rc == 3
     rc, h, _ = _plan([300], [2], persistent=False, lanes=17)
     assert rc == -6

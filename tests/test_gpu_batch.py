@@ -204,3 +204,20 @@ def test_batch_mixed_redoes_fp32_breakdown_in_fp64(plprof_lib):
         q = probs[i]
         ref = oracle.profile_loglik(q.locs, q.y, q.X, q.omega, lam)
         assert np.max(np.abs(b.records(i)["loglik"].cpu().numpy() - ref["loglik"])) <= 1e-2
+
+
+def test_batch_mixed_tall_border(plprof_lib):
+    """The mixed batch with 44 right-hand sides (a 48-row bordered tile row
+    of its own): equal to the single-dataset mixed path."""
+    pl = plprof_lib
+    probs = [synth.small_problem(n, p=4, K=2, M=40, seed=900 + i)
+             for i, n in enumerate((500, 140, 333))]
+    lam = probs[0].lam
+    print("batch mixed: M + p = 44", flush=True)
+    b = pl.batch.Batch(probs, lam, precision="mixed").run()
+    torch.cuda.synchronize()
+    for i, pr in enumerate(probs):
+        got = b.records(i)["loglik"].cpu().numpy()
+        one = pl.profile_loglik(pr.locs, pr.y, pr.X, pr.omega, lam, precision="mixed")
+        _check_close(got, one["loglik"].cpu().numpy(), pr.n)
+    b.close()

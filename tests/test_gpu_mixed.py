@@ -118,3 +118,24 @@ def test_autotune_respects_error_budget(plprof_lib):
     torch.cuda.synchronize()
     assert np.abs(got["loglik"].cpu().numpy() - ref["loglik"]).max() <= 1e-2
     print("autotune report", rep, "->", choice)
+
+
+# bordered heights above 32: the bordered row is updated as a tile row of its
+# own and the back substitution and refined cross products run at 48 and 64
+# right-hand sides; the shapes of the paper's examples (Swiss rainfall:
+# 34 Box-Cox values and 2 covariates at n = 100; soil mercury: 31 values and
+# 18 covariates at n = 829, Sections 6 and 7) among them
+@pytest.mark.parametrize("n,p,K,M,seed", [(100, 2, 4, 34, 90), (829, 18, 3, 31, 91),
+                                          (300, 2, 3, 36, 92), (420, 4, 3, 60, 93)])
+def test_mixed_tall_border_matches_oracle(plprof_lib, n, p, K, M, seed):
+    pl = plprof_lib
+    pr = synth.small_problem(n, p=p, K=K, M=M, seed=seed)
+    print(f"mixed n={n} M+p={M + p}", flush=True)
+    got = _run(pl, pr, precision="mixed")
+    ref, refb = oracle.profile_loglik(pr.locs, pr.y, pr.X, pr.omega, pr.lam, return_beta=True)
+    assert np.all((got["info"] & ~pl.PL_INFO_FALLBACK) == 0)
+    dll = np.abs(got["loglik"] - ref["loglik"])
+    print(f"  max |dl| = {dll.max():.2e}")
+    assert dll.max() <= TOL_LL
+    assert np.abs(got["loglik_reml"] - ref["loglik_reml"]).max() <= TOL_LL
+    np.testing.assert_allclose(got["beta"], refb, rtol=0, atol=1e-3 * max(1.0, np.abs(refb).max()))
