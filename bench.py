@@ -289,7 +289,7 @@ def _run_batch(pl, probs, runs, **kw):
     return st, rec
 
 
-def bench_uneven(pl, runs):
+def bench_uneven(pl, runs, forms=("tune", "persistent", "calls")):
     import numpy as np
     import torch
 
@@ -310,6 +310,8 @@ def bench_uneven(pl, runs):
     smx.update({"max_abs_dl_vs_fp64": float(d.max()), "p99_abs_dl_vs_fp64": _pct(d, 99)})
     st["mixed"] = smx
     log(f"uneven bucketed mixed: {smx['ms_median']:.0f} ms, max |dl| {d.max():.2e}")
+    if "tune" not in forms:
+        return st
     # the autotuner's choice for this workload (budget 1e-3 against FP64),
     # measured like the others
     t0 = time.perf_counter()
@@ -319,11 +321,15 @@ def bench_uneven(pl, runs):
     stt["max_abs_dl_vs_fp64"] = float(np.max(np.abs(rtt["loglik"][ok] - r64["loglik"][ok])))
     st["tuned"] = {"choice": choice, "candidates": report, **stt}
     log(f"uneven tuned: {stt['ms_median']:.0f} ms")
+    if "persistent" not in forms:
+        return st
     spe, rpe = _run_batch(pl, probs, runs, schedule="persistent")
     spe["max_rel_diff_vs_bucketed"] = float(np.max(
         np.abs(rpe["loglik"][ok] - r64["loglik"][ok]) / np.maximum(np.abs(r64["loglik"][ok]), 1)))
     st["persistent_fp64"] = spe
     log(f"uneven persistent fp64: {spe['ms_median']:.0f} ms")
+    if "calls" not in forms:
+        return st
     pts = st["points"]
     # the same datasets as independent calls on four streams (the serving
     # executor with every request present at the start), in both forms
@@ -450,6 +456,9 @@ def main():
                     help="form of the headline steps (the metric is quoted on fp64)")
     ap.add_argument("--extras", default=",".join(EXTRAS),
                     help=f"comma list from {EXTRAS}, or 'none'")
+    ap.add_argument("--batch-forms", default="tune,persistent,calls",
+                    help="uneven batch extras beyond the bucketed FP64 and mixed runs: comma "
+                         "list of tune, persistent, calls (per-dataset calls), or 'none'")
     ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -637,7 +646,8 @@ def main():
         guarded(key, both)
 
     if "batch" in extras:
-        guarded("uneven_batch", lambda: bench_uneven(pl, max(3, args.steps // 2)))
+        forms = () if args.batch_forms == "none" else tuple(args.batch_forms.split(","))
+        guarded("uneven_batch", lambda: bench_uneven(pl, max(3, args.steps // 2), forms))
     if "serve" in extras:
         guarded("serving", lambda: bench_serving(pl, args.serve_seconds, args.serve_rate, 4, 160))
 
