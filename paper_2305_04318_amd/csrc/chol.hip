@@ -334,7 +334,8 @@ __global__ __launch_bounds__(256, 2) void k_col_update(Lay lay, double* __restri
   double* base = mats + (int64_t)k * lay.mstride;
   const Lay L = lay_of(lay, k);
   if (r == 0) dev_gemm_diag_border<VEC>(L, base, J, border != 0, lds);
-  else dev_gemm_col<VEC>(L, base, J, J + r, lds);
+  else if (VEC && lay.kind == 0 && J + r < lay.Nv) dev_gemm_col_dma(L, base, J, J + r, lds);
+  else dev_gemm_col<VEC>(L, base, J, J + r, lds);  // the bordered row taller than 32
 }
 
 hipError_t launch_col_update(const Lay& lay, double* mats, const int32_t* info, int J, int K,
@@ -447,6 +448,15 @@ __global__ __launch_bounds__(256, 2) void k_trsm(Lay lay, TS* __restrict__ mats,
   const int k = wg / nI;
   const int I = J + 1 + wg % nI;
   if (info[k] != 0) return;  // uniform for the workgroup
+  if constexpr (sizeof(TS) == 8) {
+    // whole packed tiles take the direct-to-LDS core; the bordered row and
+    // the plain column-major layout keep the register-staged one
+    if (VEC && lay.kind == 0 && I < lay.Nv) {
+      dev_trsm_dma(lay_of(lay, k), mats + (int64_t)k * lay.mstride, Wbuf + (int64_t)k * wstride,
+                   J, I, reinterpret_cast<double*>(lds_raw));
+      return;
+    }
+  }
   dev_trsm<TS, VEC, MX_FLUSH>(lay_of(lay, k), mats + (int64_t)k * lay.mstride,
                               Wbuf + (int64_t)k * wstride, J, I, reinterpret_cast<TS*>(lds_raw));
 }

@@ -82,14 +82,29 @@ __device__ __forceinline__ typename Piece<TS>::type fetch_piece(const TS* __rest
 constexpr int LROW = T + 4;         // LDS stride per k column (elements)
 constexpr int GEMM_LDS_BYTES = 2 * 2 * 16 * LROW * 8;
 
-// KSTOP: a wave multiplies only the chunks below kstop (it still loads and
-// stages every chunk for the others); the panel solve's first wave column
-// needs no products past its columns, where W^T is zero.
-template <typename TS, typename TC, bool VEC, int NJ = 4, int DEPTH = 2, bool KSTOP = false>
+// TRI (the panel solve C W^T, W lower triangular): output block column g
+// (16 columns) needs only k < 16 (g + 1).  Wave column wc owns the block
+// columns tri_blk(wc, 0..3) = {0, 1, 6, 7} or {2, 3, 4, 5}, 18 nonzero
+// 16 x 16 x 16 products each, instead of the halves {0..3} and {4..7} (10
+// and 26).  tri_blk grows with j, so the blocks that still need the k from k0
+// on are j >= tri_lo(wc, k0): one scalar branch per MFMA.  Blocks at or
+// beyond brows multiply the zero rows of B and are not stored.
+__device__ __forceinline__ int tri_blk(int wc, int j) { return wc ? j + 2 : (j < 2 ? j : j + 4); }
+
+__device__ __forceinline__ int tri_lo(int wc, int k0) {
+  int jlo = 4;
+#pragma unroll
+  for (int j = 3; j >= 0; --j)
+    if (16 * tri_blk(wc, j) + 16 > k0) jlo = j;
+  return jlo;
+}
+
+template <typename TS, typename TC, bool VEC, int NJ = 4, int DEPTH = 2, bool TRI = false>
 __device__ __forceinline__ void wg_gemm_nt(typename MF<TC>::acc (&acc)[4][4], TS* lds,
                                            const TS* __restrict__ A, int64_t lda, int arows,
                                            const TS* __restrict__ B, int64_t ldb, int brows,
-                                           int kmax, bool do_mfma, int ni, int kstop = 0) {
+                                           int kmax, bool do_mfma, int ni) {
+  static_assert(!TRI || DEPTH > 1, "the column map is built into the two-set pipeline");
   constexpr int N = Piece<TS>::N;
   constexpr int KC = 128 / (int)sizeof(TS);
   constexpr int PPC = T / N;  // pieces per column
@@ -161,14 +176,28 @@ __device__ __forceinline__ void wg_gemm_nt(typename MF<TC>::acc (&acc)[4][4], TS
   // two register sets: chunk c + 2 is fetched while chunk c is multiplied and
   // chunk c + 1 (fetched a chunk earlier) waits in registers for its LDS stage
   V ra[2][4], rb[2][4];
+  // whole-tile panels and a chunk inside kmax need no bounds checks: one
+  // scalar branch per chunk instead of per-piece exec masks
+  const bool full = VEC && __builtin_amdgcn_readfirstlane((int)(arows >= T && brows >= T)) != 0;
+  kmax = __builtin_amdgcn_readfirstlane(kmax);
   auto fetch = [&](int k0, auto setc) {
     constexpr int S = decltype(setc)::value;
+    if (full && k0 + KC <= kmax) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = tid + 256 * q;
-      const int col = idx / PPC, row = (idx % PPC) * N;
-      ra[S][q] = fetch_piece<TS, VEC>(A, lda, arows, k0 + col, kmax, row);
-      rb[S][q] = fetch_piece<TS, VEC>(B, ldb, brows, k0 + col, kmax, row);
+      for (int q = 0; q < 4; ++q) {
+        const int idx = tid + 256 * q;
+        const int col = idx / PPC, row = (idx % PPC) * N;
+        ra[S][q] = *reinterpret_cast<const V*>(A + (int64_t)(k0 + col) * lda + row);
+        rb[S][q] = *reinterpret_cast<const V*>(B + (int64_t)(k0 + col) * ldb + row);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int idx = tid + 256 * q;
+        const int col = idx / PPC, row = (idx % PPC) * N;
+        ra[S][q] = fetch_piece<TS, VEC>(A, lda, arows, k0 + col, kmax, row);
+        rb[S][q] = fetch_piece<TS, VEC>(B, ldb, brows, k0 + col, kmax, row);
+      }
     }
   };
   auto stash = [&](auto setc) {
@@ -192,13 +221,19 @@ __device__ __forceinline__ void wg_gemm_nt(typename MF<TC>::acc (&acc)[4][4], TS
   const int lr = lane & 15, lk = lane >> 4;
   // chunk c (even: set/stage 0, odd: 1): fetch c + 2 into its own set, run
   // its MFMAs from LDS stage c & 1, then move chunk c + 1 to the other stage
-  if constexpr (KSTOP) kstop = __builtin_amdgcn_readfirstlane(kstop);
+  // the column map is per wave: scalar registers, scalar branches
+  const int wcu = TRI ? __builtin_amdgcn_readfirstlane(wc) : wc;
   auto step = [&](int c, auto setc, auto other) {
     constexpr int S = decltype(setc)::value;
     if (c + 2 < nchunks) fetch((c + 2) * KC, setc);
-    if (do_mfma && (!KSTOP || c * KC < kstop)) {
+    const int jlo = TRI ? tri_lo(wcu, c * KC) : 0;
+    if (do_mfma && jlo < NJ) {
       const TS* sa = lds + (S * 2 + 0) * KC * LROW + 64 * wr + lr;
-      const TS* sb = lds + (S * 2 + 1) * KC * LROW + 64 * wc + lr;
+      const TS* sb = lds + (S * 2 + 1) * KC * LROW + (TRI ? 0 : 64 * wc) + lr;
+      // every block row runs (rows at or beyond arows multiply the zeros the
+      // fetch put there and are never stored): a wave with fewer valid rows
+      // only occurs in a tile's last row block, beside a full wave that sets
+      // the workgroup's pace, and a branch-free MFMA stream schedules better
 #pragma unroll
       for (int s4 = 0; s4 < KC / 4; ++s4) {
         const int kk = 4 * s4 + lk;
@@ -206,13 +241,14 @@ __device__ __forceinline__ void wg_gemm_nt(typename MF<TC>::acc (&acc)[4][4], TS
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           a[i] = (TC)sa[kk * LROW + 16 * i];
-          b[i] = (TC)sb[kk * LROW + 16 * i];
+          b[i] = (TC)sb[kk * LROW + 16 * (TRI ? tri_blk(wcu, i) : i)];
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           if (i < ni) {
 #pragma unroll
-            for (int j = 0; j < NJ; ++j) acc[i][j] = MF<TC>::op(b[j], a[i], acc[i][j]);
+            for (int j = 0; j < NJ; ++j)
+              if (!TRI || j >= jlo) acc[i][j] = MF<TC>::op(b[j], a[i], acc[i][j]);
           }
         }
       }
@@ -229,15 +265,17 @@ __device__ __forceinline__ void wg_gemm_nt(typename MF<TC>::acc (&acc)[4][4], TS
 // FP32 MFMA whose partial sums are flushed into FP64 accumulators every
 // FLUSH k-steps (FLUSH * 4 products): the FP32 rounding then only touches short
 // partial sums instead of the long running sums that cancel in the Schur
-// complements of an ill-conditioned V.  Same LDS pipeline as wg_gemm_nt,
-// and the same KSTOP (skipped chunks leave the pending partials untouched; the
-// final fold adds them).
-template <int FLUSH, bool KSTOP = false>
+// complements of an ill-conditioned V.  Same LDS pipeline as wg_gemm_nt.
+// HALF (the panel solve, W lower triangular): wave column 0 holds output
+// columns 0..63 and needs no products past k = 64, so it skips those chunks
+// whole (the pending partials are folded at the end); a per-block map as in
+// wg_gemm_nt's TRI makes this core spill.
+template <int FLUSH, bool HALF = false>
 __device__ __forceinline__ void wg_gemm_nt_f32x64(d4 (&acc)[4][4], float* lds,
                                                   const float* __restrict__ A, int64_t lda,
                                                   int arows, const float* __restrict__ B,
                                                   int64_t ldb, int brows, int kmax, bool do_mfma,
-                                                  int ni, int kstop = 0) {
+                                                  int ni) {
   constexpr int N = 4;
   constexpr int KC = 32;
   constexpr int PPC = T / N;
@@ -278,11 +316,11 @@ __device__ __forceinline__ void wg_gemm_nt_f32x64(d4 (&acc)[4][4], float* lds,
   f4 pp[4];  // FP32 partials of the block row that is folded in next
 #pragma unroll
   for (int j = 0; j < 4; ++j) pp[j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-  if constexpr (KSTOP) kstop = __builtin_amdgcn_readfirstlane(kstop);
+  const int wcu = HALF ? __builtin_amdgcn_readfirstlane(wc) : wc;
   for (int c = 0; c < nchunks; ++c) {
     const bool more = c + 1 < nchunks;
     if (more) fetch((c + 1) * KC);
-    if (do_mfma && (!KSTOP || c * KC < kstop)) {
+    if (do_mfma && (!HALF || wcu == 1 || c * KC < 64)) {
       const float* sa = lds + ((c & 1) * 2 + 0) * KC * LROW + 64 * wr + lr;
       const float* sb = lds + ((c & 1) * 2 + 1) * KC * LROW + 64 * wc + lr;
       // rolled: only one group's fragments and partial sums are live at a time
@@ -448,6 +486,77 @@ __device__ __forceinline__ void sub_store_border(TO* C, int64_t ldc, const d4 (&
 
 __device__ __forceinline__ int nblk(int rows) { return rows <= 0 ? 0 : min(4, (rows + 15) >> 4); }
 
+// ---- workgroup GEMM core, direct-to-LDS form -------------------------------------
+// acc += A[0:128, 0:kmax] B[0:128, 0:kmax]^T for whole 128-row panels with
+// leading dimension T (the packed tiles and the inverse buffer: every row of
+// every column is allocated).  Same wave grid, chunk width (KC = 16) and LDS
+// layout as wg_gemm_nt, but the chunks travel from global memory straight
+// into LDS (global_load_lds_dwordx4: lane l carries rows 2l, 2l+1 of one
+// column, 1 KB per instruction, the LDS column base set per instruction), so
+// no registers stage the prefetch and no LDS stores are issued.  Two stages:
+// chunk c + 1 is requested right after the barrier that publishes chunk c
+// (every wave has then left chunk c - 1, whose stage it refills) and lands
+// while chunk c is multiplied; the next __syncthreads waits for it (its
+// workgroup-scope release waits for the wave's outstanding loads).  kmax must
+// be a multiple of KC; every block row is multiplied (rows a tile does not
+// hold are never stored).  TRI as in wg_gemm_nt.
+typedef __attribute__((address_space(3))) void lds_void;
+
+template <bool TRI>
+__device__ __forceinline__ void wg_gemm_nt_dma(d4 (&acc)[4][4], double* lds,
+                                               const double* __restrict__ A,
+                                               const double* __restrict__ B, int kmax,
+                                               bool do_mfma) {
+  constexpr int KC = 16, STG = 2 * KC * LROW, CPW = 2 * KC / 4;  // columns per wave
+  static_assert(2 * STG * 8 <= GEMM_LDS_BYTES, "two stages in the GEMM LDS");
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wr = wave >> 1, wc = wave & 1;
+  const int nchunks = __builtin_amdgcn_readfirstlane(kmax) / KC;
+  if (nchunks <= 0) return;
+  do_mfma = __builtin_amdgcn_readfirstlane((int)do_mfma) != 0;
+  // wave w moves columns CPW w .. CPW w + CPW - 1 of the chunk's 2 KC (A, then B)
+  auto request = [&](int c, int stage) {
+#pragma unroll
+    for (int h = 0; h < CPW; ++h) {
+      const int col = CPW * wave + h;
+      const bool isb = col >= KC;
+      const double* src = (isb ? B : A) + (int64_t)(c * KC + col - (isb ? KC : 0)) * T + 2 * lane;
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src),
+                                       (lds_void*)(lds + stage * STG + col * LROW),
+                                       16, 0, 0);
+    }
+  };
+  request(0, 0);
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int c = 0; c < nchunks; ++c) {
+    const int stage = c & 1;
+    __syncthreads();  // chunk c in LDS; chunk c - 1's stage free
+    if (c + 1 < nchunks) request(c + 1, stage ^ 1);
+    const int jlo = TRI ? tri_lo(wc, c * KC) : 0;
+    if (do_mfma && jlo < 4) {
+      const double* sa = lds + stage * STG + 64 * wr + lr;
+      const double* sb = lds + stage * STG + KC * LROW + (TRI ? 0 : 64 * wc) + lr;
+#pragma unroll
+      for (int s4 = 0; s4 < KC / 4; ++s4) {
+        const int kk = 4 * s4 + lk;
+        double a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          a[i] = sa[kk * LROW + 16 * i];
+          b[i] = sb[kk * LROW + 16 * (TRI ? tri_blk(wc, i) : i)];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (!TRI || j >= jlo) acc[i][j] = MF<double>::op(b[j], a[i], acc[i][j]);
+      }
+    }
+  }
+  __syncthreads();  // the last stage is read before the caller reuses LDS
+}
+
 // ---- tile tasks -------------------------------------------------------------------
 
 // Left-looking update of tile (I, J), I >= J: C_IJ -= L_I,0:J L_J,0:J^T (FP64 MFMA).
@@ -473,31 +582,107 @@ __device__ __forceinline__ void dev_gemm_col(const Lay& lay, double* base, int J
   }
 }
 
+// dev_gemm_col on the direct-to-LDS core: tile (I, J) with I < Nv of the
+// packed layout (whole T x T tiles; L_I,0:J and L_J,0:J are column-major
+// panels of leading dimension T).
+__device__ __forceinline__ void dev_gemm_col_dma(const Lay& lay, double* base, int J, int I,
+                                                 double* lds) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int arows = lay.rows(I), brows = lay.rows(J);
+  if (arows <= 0 || brows <= 0) return;  // a tile past an uneven unit's order (uniform)
+  const int war = arows - 64 * wr, wbr = brows - 64 * wc;
+  const bool act = war > 0 && wbr > 0;
+  d4 acc[4][4];
+  zero_acc<double>(acc);
+  wg_gemm_nt_dma<false>(acc, lds, base + lay.tile_off(I, 0), base + lay.tile_off(J, 0),
+                        min(J * T, lay.n), act);
+  if (act) {
+    double* C = base + lay.tile_off(I, J) + 64 * wr + 64 * wc * T;
+    store64<double, true, double, double>(C, T, C, T, acc, war, wbr, lane);
+  }
+}
+
+// L_IJ = C_IJ W^T (FP64, TRI column map) on the direct-to-LDS core: tile
+// (I, J) with I < Nv of the packed layout.
+__device__ __forceinline__ void dev_trsm_dma(const Lay& lay, double* base, const double* W, int J,
+                                             int I, double* lds) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int arows = lay.rows(I), brows = lay.rows(J);
+  if (arows <= 0 || brows <= 0) return;  // a tile past an uneven unit's order (uniform)
+  const int war = arows - 64 * wr;
+  const bool act = war > 0 && 16 * tri_blk(wc, 0) < brows;
+  double* Ct = base + lay.tile_off(I, J);
+  d4 acc[4][4];
+  zero_acc<double>(acc);
+  // the core's barriers order every read of C_IJ before the overwrite
+  wg_gemm_nt_dma<true>(acc, lds, Ct, W, T, act);
+  if (!act) return;
+  const int lr = lane & 15, lg = lane >> 4;
+  double* Cw = Ct + 64 * wr;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = 16 * i + lr;
+    if (r >= war) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int cb = 16 * tri_blk(wc, j);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = cb + MF<double>::col(lg, e);
+        if (c < brows) Cw[(int64_t)c * T + r] = acc[i][j][e];
+      }
+    }
+  }
+}
+
 // Panel solve of tile (I, J), I > J: L_IJ = C_IJ W^T with W = L_JJ^-1 (ld T).
+// The FP64 two-set pipeline (step kernels) uses the TRI column map; the FP32
+// form skips the chunks its first wave column does not need (HALF); the
+// persistent batch kernel's one-set pipeline keeps the plain halves.
 template <typename TS, bool VEC, int FLUSH, int DEPTH = 2>
 __device__ __forceinline__ void dev_trsm(const Lay& lay, TS* base, const TS* W, int J, int I, TS* lds) {
+  constexpr bool TRI = sizeof(TS) == 8 && DEPTH > 1;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wr = wave >> 1, wc = wave & 1;
   const int arows = lay.rows(I), brows = lay.rows(J);
   const int war = arows - 64 * wr, wbr = brows - 64 * wc;
-  const int ni = nblk(war), nj = nblk(wbr);
-  const bool act = ni > 0 && nj > 0;
+  const int ni = nblk(war);
+  const bool act = ni > 0 && (TRI ? 16 * tri_blk(wc, 0) < brows : wbr > 0);
   TS* Ct = base + lay.tile_off(I, J);
   const int64_t ldc = lay.tile_ld(I);
-  TS* Co = Ct + 64 * wr + 64 * wc * ldc;
   d4 acc[4][4];
   zero_acc<double>(acc);
   // the core's final barrier orders every read of C_IJ before the overwrite
   if constexpr (sizeof(TS) == 8) {
-    // W is lower triangular: output columns 64 wc .. 64 wc + 63 need k < 64 (wc + 1)
-    // (two-set pipeline only: the persistent batch kernel keeps its code)
-    wg_gemm_nt<TS, TS, VEC, 4, DEPTH, (DEPTH > 1)>(acc, lds, Ct, ldc, arows, W, T, brows, brows,
-                                                   act, ni, DEPTH > 1 ? 64 * (wc + 1) : 0);
-    if (act) store64<double, false>(Co, ldc, Co, ldc, acc, war, wbr, lane);
+    wg_gemm_nt<TS, TS, VEC, 4, DEPTH, TRI>(acc, lds, Ct, ldc, arows, W, T, brows, brows, act, ni);
   } else {
-    wg_gemm_nt_f32x64<FLUSH, true>(acc, lds, Ct, ldc, arows, W, T, brows, brows, act, ni,
-                                   64 * (wc + 1));
-    if (act) store64_l<float, false>(Co, ldc, Co, ldc, acc, war, wbr, lane);
+    wg_gemm_nt_f32x64<FLUSH, true>(acc, lds, Ct, ldc, arows, W, T, brows, brows, act, ni);
+  }
+  if (!act) return;
+  if constexpr (TRI) {
+    // block (i, j) of the wave is rows 64 wr + 16 i, columns 16 tri_blk(wc, j)
+    const int lr = lane & 15, lg = lane >> 4;
+    TS* Cw = Ct + 64 * wr;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = 16 * i + lr;
+      if (r >= war) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int cb = 16 * tri_blk(wc, j);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int c = cb + MF<double>::col(lg, e);
+          if (c < brows) Cw[(int64_t)c * ldc + r] = acc[i][j][e];
+        }
+      }
+    }
+  } else {
+    TS* Co = Ct + 64 * wr + 64 * wc * ldc;
+    if constexpr (sizeof(TS) == 8) store64<double, false>(Co, ldc, Co, ldc, acc, war, wbr, lane);
+    else store64_l<float, false>(Co, ldc, Co, ldc, acc, war, wbr, lane);
   }
 }
 
