@@ -436,41 +436,72 @@ hipError_t launch_border_block(const Lay& lay, double* mats, const int32_t* info
   return hipGetLastError();
 }
 
-// ---- panel solve L_IJ = C_IJ W_J^T for the nI tile rows below J -----------
+// ---- panel solve L_IJ = C_IJ W_J^T for nI tile rows from I0 down -----------
 // TS double: W from Wbuf[k]; TS float: W from slot J of the omega's table.
 template <typename TS, bool VEC>
 __global__ __launch_bounds__(256, 2) void k_trsm(Lay lay, TS* __restrict__ mats,
                                                  const TS* __restrict__ Wbuf,
-                                                 const int32_t* __restrict__ info, int J, int nI,
-                                                 int G, int64_t wstride) {
+                                                 const int32_t* __restrict__ info, int J, int I0,
+                                                 int nI, int G, int64_t wstride) {
   __shared__ __attribute__((aligned(16))) char lds_raw[GEMM_LDS_BYTES];
   const int wg = xcd_remap(blockIdx.x, G);
   const int k = wg / nI;
-  const int I = J + 1 + wg % nI;
+  const int I = I0 + wg % nI;
   if (info[k] != 0) return;  // uniform for the workgroup
-  if constexpr (sizeof(TS) == 8) {
-    // whole packed tiles take the direct-to-LDS core; the bordered row and
-    // the plain column-major layout keep the register-staged one
-    if (VEC && lay.kind == 0 && I < lay.Nv) {
-      dev_trsm_dma(lay_of(lay, k), mats + (int64_t)k * lay.mstride, Wbuf + (int64_t)k * wstride,
-                   J, I, reinterpret_cast<double*>(lds_raw));
-      return;
-    }
-  }
   dev_trsm<TS, VEC, MX_FLUSH>(lay_of(lay, k), mats + (int64_t)k * lay.mstride,
                               Wbuf + (int64_t)k * wstride, J, I, reinterpret_cast<TS*>(lds_raw));
 }
 
+// FP64 panel solve of the packed layout (tile rows J + 1 .. J + nI): whole
+// tiles on the direct-to-LDS core, chunks of 8 columns in three stages
+// (49.5 KB of LDS) and no staging registers, so three workgroups share a CU
+// (each tile is only 128 columns deep; the extra workgroups hide the load
+// latency); the bordered row's tile (tile row Nv) on dev_trsm_border.
+constexpr int TRSM_KC = 8, TRSM_NST = 3;
+__global__ __launch_bounds__(256, 3) void k_trsm_dma(Lay lay, double* __restrict__ mats,
+                                                     const double* __restrict__ Wbuf,
+                                                     const int32_t* __restrict__ info, int J,
+                                                     int nI, int G) {
+  __shared__ __attribute__((aligned(16))) char lds_raw[dma_lds_bytes<TRSM_KC, TRSM_NST>()];
+  const int wg = xcd_remap(blockIdx.x, G);
+  const int k = wg / nI;
+  const int I = J + 1 + wg % nI;
+  if (info[k] != 0) return;  // uniform for the workgroup
+  const Lay L = lay_of(lay, k);
+  double* base = mats + (int64_t)k * lay.mstride;
+  const double* W = Wbuf + (int64_t)k * T * T;
+  if (I < lay.Nv) {
+    dev_trsm_dma<TRSM_KC, TRSM_NST>(L, base, W, J, I, reinterpret_cast<double*>(lds_raw));
+    return;
+  }
+  if (lay.q <= 0) return;  // no bordered row: nothing below the last tile row
+  switch (lay.TB) {
+    case 16: dev_trsm_border<1>(L, base, W, J); break;
+    case 32: dev_trsm_border<2>(L, base, W, J); break;
+    case 48: dev_trsm_border<3>(L, base, W, J); break;
+    default: dev_trsm_border<4>(L, base, W, J); break;
+  }
+}
+
 hipError_t launch_trsm(const Lay& lay, double* mats, const double* W, const int32_t* info, int J,
                        int nI, int K, hipStream_t s) {
-  const int G = K * nI;
   const int64_t ws = (int64_t)T * T;
-  if (vec_ok(lay, mats) && (reinterpret_cast<uintptr_t>(W) & 15) == 0)
-    hipLaunchKernelGGL((k_trsm<double, true>), dim3(G), dim3(256), 0, s, lay, mats, W, info, J, nI,
-                       G, ws);
-  else
-    hipLaunchKernelGGL((k_trsm<double, false>), dim3(G), dim3(256), 0, s, lay, mats, W, info, J,
-                       nI, G, ws);
+  const bool vec = vec_ok(lay, mats) && (reinterpret_cast<uintptr_t>(W) & 15) == 0;
+  const int I0 = J + 1;
+  if (vec && lay.kind == 0 && (lay.q == 0 || lay.TB <= 64)) {
+    if (nI > 0) {
+      const int G = K * nI;
+      hipLaunchKernelGGL(k_trsm_dma, dim3(G), dim3(256), 0, s, lay, mats, W, info, J, nI, G);
+    }
+  } else if (nI > 0) {
+    const int G = K * nI;
+    if (vec)
+      hipLaunchKernelGGL((k_trsm<double, true>), dim3(G), dim3(256), 0, s, lay, mats, W, info, J,
+                         I0, nI, G, ws);
+    else
+      hipLaunchKernelGGL((k_trsm<double, false>), dim3(G), dim3(256), 0, s, lay, mats, W, info, J,
+                         I0, nI, G, ws);
+  }
   return hipGetLastError();
 }
 
@@ -479,7 +510,7 @@ hipError_t launch_trsm_mx(const Lay& lay, float* m32, const float* W32, const in
   const int G = K * nI;
   const int64_t ws = (int64_t)lay.Nv * T * T;
   hipLaunchKernelGGL((k_trsm<float, true>), dim3(G), dim3(256), 0, s, lay, m32,
-                     W32 + (int64_t)J * T * T, info, J, nI, G, ws);
+                     W32 + (int64_t)J * T * T, info, J, J + 1, nI, G, ws);
   return hipGetLastError();
 }
 
@@ -490,8 +521,8 @@ hipError_t launch_trsm_mx_plain(const Lay& lay, float* m32, const float* W32,
   const int nI = lay.Nv - J - 1;
   if (nI <= 0) return hipSuccess;
   const int G = K * nI;
-  hipLaunchKernelGGL((k_trsm<float, true>), dim3(G), dim3(256), 0, s, lay, m32, W32, info, J, nI,
-                     G, (int64_t)T * T);
+  hipLaunchKernelGGL((k_trsm<float, true>), dim3(G), dim3(256), 0, s, lay, m32, W32, info, J,
+                     J + 1, nI, G, (int64_t)T * T);
   return hipGetLastError();
 }
 

@@ -493,22 +493,35 @@ __device__ __forceinline__ int nblk(int rows) { return rows <= 0 ? 0 : min(4, (r
 // layout as wg_gemm_nt, but the chunks travel from global memory straight
 // into LDS (global_load_lds_dwordx4: lane l carries rows 2l, 2l+1 of one
 // column, 1 KB per instruction, the LDS column base set per instruction), so
-// no registers stage the prefetch and no LDS stores are issued.  Two stages:
-// chunk c + 1 is requested right after the barrier that publishes chunk c
-// (every wave has then left chunk c - 1, whose stage it refills) and lands
-// while chunk c is multiplied; the next __syncthreads waits for it (its
-// workgroup-scope release waits for the wave's outstanding loads).  kmax must
-// be a multiple of KC; every block row is multiplied (rows a tile does not
-// hold are never stored).  TRI as in wg_gemm_nt.
+// no registers stage the prefetch and no LDS stores are issued.  NST stages
+// of KC columns: chunk c + NST - 1 is requested right after the barrier that
+// publishes chunk c (every wave has then left chunk c - 1, whose stage it
+// refills) and lands while chunks c .. c + NST - 2 are multiplied.  With two
+// stages the barrier is a __syncthreads (its workgroup-scope release waits
+// for all of the wave's loads: only chunk c's are outstanding); with three,
+// each wave waits for all but the next chunk's loads (vmcnt) and LDS reads,
+// then s_barrier, in one asm statement that the compiler cannot move memory
+// accesses across.  kmax must be a multiple of KC; every block row is
+// multiplied (rows a tile does not hold are never stored).  TRI as in
+// wg_gemm_nt.
 typedef __attribute__((address_space(3))) void lds_void;
 
-template <bool TRI>
+template <int N>
+__device__ __forceinline__ void vmcnt_barrier() {
+  asm volatile("s_waitcnt vmcnt(%0)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+
+template <int KC, int NST>
+constexpr int dma_lds_bytes() { return NST * 2 * KC * LROW * 8; }
+
+template <bool TRI, int KC = 16, int NST = 2>
 __device__ __forceinline__ void wg_gemm_nt_dma(d4 (&acc)[4][4], double* lds,
                                                const double* __restrict__ A,
                                                const double* __restrict__ B, int kmax,
                                                bool do_mfma) {
-  constexpr int KC = 16, STG = 2 * KC * LROW, CPW = 2 * KC / 4;  // columns per wave
-  static_assert(2 * STG * 8 <= GEMM_LDS_BYTES, "two stages in the GEMM LDS");
+  constexpr int STG = 2 * KC * LROW, CPW = 2 * KC / 4;  // columns per wave and chunk
+  static_assert(NST == 2 || NST == 3, "two or three stages");
+  static_assert(KC % 8 == 0 && CPW <= 15, "whole k-steps; vmcnt holds one chunk");
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wr = wave >> 1, wc = wave & 1;
@@ -527,12 +540,20 @@ __device__ __forceinline__ void wg_gemm_nt_dma(d4 (&acc)[4][4], double* lds,
                                        16, 0, 0);
     }
   };
-  request(0, 0);
+#pragma unroll
+  for (int p = 0; p < NST - 1; ++p)
+    if (p < nchunks) request(p, p);
   const int lr = lane & 15, lk = lane >> 4;
+  int stage = 0;
   for (int c = 0; c < nchunks; ++c) {
-    const int stage = c & 1;
-    __syncthreads();  // chunk c in LDS; chunk c - 1's stage free
-    if (c + 1 < nchunks) request(c + 1, stage ^ 1);
+    // chunk c in LDS; chunk c - 1's stage free
+    if constexpr (NST == 2) {
+      __syncthreads();
+    } else {
+      if (c + 1 < nchunks) vmcnt_barrier<CPW>();
+      else vmcnt_barrier<0>();
+    }
+    if (c + NST - 1 < nchunks) request(c + NST - 1, stage == 0 ? NST - 1 : stage - 1);
     const int jlo = TRI ? tri_lo(wc, c * KC) : 0;
     if (do_mfma && jlo < 4) {
       const double* sa = lds + stage * STG + 64 * wr + lr;
@@ -553,6 +574,7 @@ __device__ __forceinline__ void wg_gemm_nt_dma(d4 (&acc)[4][4], double* lds,
             if (!TRI || j >= jlo) acc[i][j] = MF<double>::op(b[j], a[i], acc[i][j]);
       }
     }
+    if (++stage == NST) stage = 0;
   }
   __syncthreads();  // the last stage is read before the caller reuses LDS
 }
@@ -605,6 +627,7 @@ __device__ __forceinline__ void dev_gemm_col_dma(const Lay& lay, double* base, i
 
 // L_IJ = C_IJ W^T (FP64, TRI column map) on the direct-to-LDS core: tile
 // (I, J) with I < Nv of the packed layout.
+template <int KC, int NST>
 __device__ __forceinline__ void dev_trsm_dma(const Lay& lay, double* base, const double* W, int J,
                                              int I, double* lds) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -617,7 +640,7 @@ __device__ __forceinline__ void dev_trsm_dma(const Lay& lay, double* base, const
   d4 acc[4][4];
   zero_acc<double>(acc);
   // the core's barriers order every read of C_IJ before the overwrite
-  wg_gemm_nt_dma<true>(acc, lds, Ct, W, T, act);
+  wg_gemm_nt_dma<true, KC, NST>(acc, lds, Ct, W, T, act);
   if (!act) return;
   const int lr = lane & 15, lg = lane >> 4;
   double* Cw = Ct + 64 * wr;
@@ -632,6 +655,65 @@ __device__ __forceinline__ void dev_trsm_dma(const Lay& lay, double* base, const
       for (int e = 0; e < 4; ++e) {
         const int c = cb + MF<double>::col(lg, e);
         if (c < brows) Cw[(int64_t)c * T + r] = acc[i][j][e];
+      }
+    }
+  }
+}
+
+// L_NvJ = C_NvJ W^T for the bordered row's tile (q valid rows of TB = 16 NBR,
+// leading dimension TB) without LDS: wave w computes the output block
+// columns w and 7 - w (w + 1 and 8 - w nonzero k-blocks of W^T: the same
+// count for every wave) over all NBR block rows, with fragments loaded
+// straight from global memory (16 lanes read 16 consecutive rows of one
+// column), four k-steps per batch of loads.  One barrier separates the last
+// read of C from the first write of L (the waves read columns that others
+// write).
+template <int NBR>
+__device__ __forceinline__ void dev_trsm_border(const Lay& lay, double* base, const double* W,
+                                                int J) {
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lr = lane & 15, lk = lane >> 4;
+  double* C = base + lay.tile_off(lay.Nv, J);
+  const int64_t ld = lay.TB;
+  const int q = lay.q, brows = lay.rows(J);
+  const int g0 = w, g1 = 7 - w;         // g1 > g0: the longer k range
+  const int nsteps = 4 * (g1 + 1);      // 4-deep k-steps up to k = 16 (g1 + 1)
+  d4 acc[NBR][2];
+#pragma unroll
+  for (int ib = 0; ib < NBR; ++ib) acc[ib][0] = acc[ib][1] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int s0 = 0; s0 < nsteps; s0 += 4) {
+    double a[4][NBR], b[4][2];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = 4 * (s0 + u) + lk;
+#pragma unroll
+      for (int ib = 0; ib < NBR; ++ib) a[u][ib] = C[(int64_t)kk * ld + 16 * ib + lr];
+      b[u][0] = W[(int64_t)kk * T + 16 * g0 + lr];
+      b[u][1] = W[(int64_t)kk * T + 16 * g1 + lr];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool first = 4 * (s0 + u) < 16 * (g0 + 1);  // uniform
+#pragma unroll
+      for (int ib = 0; ib < NBR; ++ib) {
+        if (first) acc[ib][0] = MF<double>::op(b[u][0], a[u][ib], acc[ib][0]);
+        acc[ib][1] = MF<double>::op(b[u][1], a[u][ib], acc[ib][1]);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int ib = 0; ib < NBR; ++ib) {
+    const int r = 16 * ib + lr;
+    if (r >= q) continue;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int cb = 16 * (h ? g1 : g0);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = cb + MF<double>::col(lk, e);
+        if (c < brows) C[(int64_t)c * ld + r] = acc[ib][h][e];
       }
     }
   }

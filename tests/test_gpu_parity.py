@@ -95,10 +95,12 @@ def test_matern_close_points_and_duplicates(plprof_lib):
 
 
 # M + p up to 16 and to 32 (the bordered row folded into the diagonal tile's
-# workgroup, one or two block rows) and beyond 32 (bordered tiles of their own)
+# workgroup, one or two block rows) and beyond 32 (bordered tiles of their
+# own), up to 60 (four block rows in the bordered row's panel solve)
 @pytest.mark.parametrize("n,p,K,M,seed", [(50, 1, 3, 1, 0), (128, 2, 4, 3, 1), (300, 3, 5, 4, 2),
                                           (700, 4, 4, 8, 3), (257, 6, 3, 5, 4),
-                                          (400, 5, 3, 20, 5), (300, 4, 2, 40, 6)])
+                                          (400, 5, 3, 20, 5), (300, 4, 2, 40, 6),
+                                          (270, 4, 2, 56, 7)])
 def test_profile_loglik_parity(plprof_lib, n, p, K, M, seed):
     pl = plprof_lib
     pr = synth.small_problem(n, p=p, K=K, M=M, seed=seed)
