@@ -266,16 +266,16 @@ __global__ __launch_bounds__(256) void k_potrf(Lay lay, double* __restrict__ mat
                                                double* __restrict__ Wbuf, float* __restrict__ W32,
                                                double* __restrict__ logdet,
                                                int32_t* __restrict__ info, int J) {
-  __shared__ double smem[POTRF_SMEM_DOUBLES];
+  __shared__ double smem[POTRF_BLK_SMEM_DOUBLES];
   const int k = blockIdx.x;
   if (info[k] != 0) return;
   const Lay L = lay_of(lay, k);
   if (MODE == 0)
-    dev_potrf<0>(L, mats + (int64_t)k * lay.mstride + lay.tile_off(J, J), lay.tile_ld(J),
-                 Wbuf + (int64_t)k * T * T, nullptr, logdet + k, info + k, J, smem);
+    dev_potrf_blk<0>(L, mats + (int64_t)k * lay.mstride + lay.tile_off(J, J), lay.tile_ld(J),
+                     Wbuf + (int64_t)k * T * T, nullptr, logdet + k, info + k, J, smem);
   else
-    dev_potrf<1>(L, Wbuf + (int64_t)k * T * T, T, nullptr,
-                 W32 + ((int64_t)k * lay.Nv + J) * T * T, logdet + k, info + k, J, smem);
+    dev_potrf_blk<1>(L, Wbuf + (int64_t)k * T * T, T, nullptr,
+                     W32 + ((int64_t)k * lay.Nv + J) * T * T, logdet + k, info + k, J, smem);
 }
 
 hipError_t launch_potrf(const Lay& lay, double* mats, double* W, double* logdet, int32_t* info,
@@ -292,10 +292,10 @@ __global__ __launch_bounds__(256) void k_potrf_mx_plain(Lay lay, float* __restri
                                                         float* __restrict__ W32,
                                                         double* __restrict__ logdet,
                                                         int32_t* __restrict__ info, int J) {
-  __shared__ double smem[POTRF_SMEM_DOUBLES];
+  __shared__ double smem[POTRF_BLK_SMEM_DOUBLES];
   const int k = blockIdx.x;
   if (info[k] != 0) return;
-  dev_potrf<2>(lay, dscratch + (int64_t)k * T * T, T, nullptr, W32 + (int64_t)k * T * T,
+  dev_potrf_blk<2>(lay, dscratch + (int64_t)k * T * T, T, nullptr, W32 + (int64_t)k * T * T,
                logdet + k, info + k, J, smem, m32 + (int64_t)k * lay.mstride + lay.tile_off(J, J),
                lay.tile_ld(J));
 }

@@ -1085,4 +1085,353 @@ __device__ __forceinline__ void dev_potrf(const Lay& lay, double* C, int64_t ld,
   }
 }
 
+// ---- diagonal tile, 2 x 2 blocked: factor and invert -----------------------------
+// The tile (identity-padded beyond nv) splits into 64 x 64 blocks
+//   [A11 .  ]   [L11  0 ] [L11^T L21^T]        W = L^-1 = [W11  0 ]
+//   [A21 A22] = [L21 L22] [ 0    L22^T],                  [W21 W22]
+// with L21 = A21 W11^T, L22 L22^T = A22 - L21 L21^T, W21 = -W22 (L21 W11).
+// Each diagonal block is factored and inverted by one wave alone in registers
+// (wave64_chol_inv: lane (bi, bj) owns the 8 x 8 block at rows 8 bi, columns
+// 8 bj; one column or row is broadcast through LDS per step; the wave's LDS
+// operations complete in order, so no barrier is needed).  The three
+// off-diagonal products run on FP64 MFMA, wave w taking block row or column
+// w, operands in LDS.  256 threads; results, outputs and failure semantics as
+// dev_potrf (the first non-positive pivot sets *info_k; the workgroup then
+// returns uniformly).  smem: at least POTRF_BLK_SMEM_DOUBLES.
+constexpr int PB_LS = 65;  // LDS column stride of a 64 x 64 block
+constexpr int POTRF_BLK_SMEM_DOUBLES = 2 * 64 * PB_LS + 4 * 64 + 8;
+
+// LDS hand-off between the lanes of one wave: its LDS operations execute in
+// order, so only the compiler has to be kept from moving or forwarding
+// accesses across this point (a wavefront-scope fence).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+}
+
+// 1 / sqrt(d) for d > 0: the hardware estimate (v_rsq_f64) refined by two
+// Newton-Raphson steps y <- y (3 - d y^2) / 2, each squaring the relative
+// error: a few ulps, with a short dependent chain (the correctly rounded
+// division and square root take about 30 dependent instructions).
+__device__ __forceinline__ double rsqrt_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  y = y * fma(-0.5 * d * y, y, 1.5);
+  y = y * fma(-0.5 * d * y, y, 1.5);
+  return y;
+}
+
+// Factor (and then invert) the 64 x 64 block held in a[8][8] by the 64 lanes
+// of one wave.  nvb: valid order of the block (rows at or beyond it are the
+// identity).  On return a holds W = L^-1 (lower, garbage above the diagonal)
+// and Lout receives L through put_l(r, c, v) for every valid r >= c; sl gets
+// the sum of log L_jj over valid j.  Returns the first failing column + 1
+// (0: success).
+template <typename PutL>
+__device__ __forceinline__ int wave64_chol_inv(double (&a)[8][8], int nvb, double* colbuf,
+                                               double* rowbuf, double* dinv, double& sl,
+                                               PutL put_l) {
+  const int lane = threadIdx.x & 63, bi = lane >> 3, bj = lane & 7;
+  const bool low = bi >= bj;
+  for (int jb = 0; jb < 8; ++jb) {
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) {
+      const int j = 8 * jb + jj;
+      if (bj == jb) {
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr) colbuf[8 * bi + rr] = a[rr][jj];
+      }
+      wave_lds_sync();
+      const double d = colbuf[j];  // the same value in every lane
+      if (!(d > 0.0)) return j + 1;
+      const double rs = rsqrt_nr(d);  // 1 / L_jj
+      if (lane == 0) dinv[j] = rs;
+      if (low && bj >= jb) {
+        const double invd = rs * rs;
+        double cr[8], cc8[8];
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr) cr[rr] = colbuf[8 * bi + rr] * invd;
+#pragma unroll
+        for (int c8 = 0; c8 < 8; ++c8) cc8[c8] = (bj > jb || c8 > jj) ? colbuf[8 * bj + c8] : 0.0;
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr)
+#pragma unroll
+          for (int c8 = 0; c8 < 8; ++c8) a[rr][c8] = fma(-cr[rr], cc8[c8], a[rr][c8]);
+        if (bj == jb) {
+#pragma unroll
+          for (int rr = 0; rr < 8; ++rr)
+            if (bi > jb || rr >= jj) a[rr][jj] *= rs;
+        }
+      }
+      wave_lds_sync();  // this step's reads before the next step's writes
+    }
+  }
+  // L is final (dinv holds 1 / L_jj): hand it out, log L_jj
+  sl = 0.0;
+  if (low) {
+#pragma unroll
+    for (int rr = 0; rr < 8; ++rr)
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc) {
+        const int r = 8 * bi + rr, c = 8 * bj + cc;
+        if (r < nvb && c < nvb && r >= c) put_l(r, c, a[rr][cc]);
+      }
+  }
+  if (bi == bj) {
+#pragma unroll
+    for (int rr = 0; rr < 8; ++rr)
+      if (8 * bi + rr < nvb) sl += log(a[rr][rr]);
+  }
+  wave_lds_sync();
+  // inverse, row by row (as dev_potrf's second phase)
+  for (int mb = 0; mb < 8; ++mb) {
+#pragma unroll
+    for (int mm = 0; mm < 8; ++mm) {
+      const int m = 8 * mb + mm;
+      if (low && bj == mb) {
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr) colbuf[8 * bi + rr] = a[rr][mm];
+      }
+      if (low && bi == mb) {
+        const double dm = dinv[m];
+#pragma unroll
+        for (int c8 = 0; c8 < 8; ++c8) {
+          if (bj < mb || c8 < mm) a[mm][c8] *= dm;
+          rowbuf[8 * bj + c8] = a[mm][c8];
+        }
+      }
+      wave_lds_sync();
+      const double wmm = dinv[m];
+      if (low && bi >= mb && bj <= mb) {
+        double lr[8], wv[8];
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr) lr[rr] = (bi > mb || rr > mm) ? colbuf[8 * bi + rr] : 0.0;
+#pragma unroll
+        for (int c8 = 0; c8 < 8; ++c8) wv[c8] = (bj < mb || c8 < mm) ? rowbuf[8 * bj + c8] : 0.0;
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr)
+#pragma unroll
+          for (int c8 = 0; c8 < 8; ++c8) a[rr][c8] = fma(-lr[rr], wv[c8], a[rr][c8]);
+        if (bj == mb) {
+#pragma unroll
+          for (int rr = 0; rr < 8; ++rr)
+            if (bi > mb || rr > mm) a[rr][mm] = -lr[rr] * wmm;
+          if (bi == mb) a[mm][mm] = wmm;
+        }
+      }
+      wave_lds_sync();
+    }
+  }
+  return 0;
+}
+
+template <int MODE>
+__device__ __forceinline__ void dev_potrf_blk(const Lay& lay, double* C, int64_t ld, double* Wd,
+                                              float* W32, double* logdet_k, int32_t* info_k,
+                                              int J, double* smem, float* L32 = nullptr,
+                                              int64_t ld32 = 0) {
+  double* P = smem;                  // W11, then X^T = (L21 W11)^T
+  double* Q = smem + 64 * PB_LS;     // L21, then A22 - L21 L21^T, then W22
+  double* colbuf = smem + 2 * 64 * PB_LS;
+  double* rowbuf = colbuf + 64;
+  double* dinv = rowbuf + 64;
+  double* red = dinv + 64;
+  volatile int* flag = reinterpret_cast<volatile int*>(red + 64);
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lr = lane & 15, lk = lane >> 4;
+  const int nv = lay.rows(J);
+  // the wave that factors the diagonal blocks varies with the workgroup index
+  // (differently for neighbours 1 and 256 apart), so that co-resident
+  // workgroups are likely to run their serial phases on different SIMDs
+  const int ws = (int)((blockIdx.x + (blockIdx.x >> 8)) & 3);
+  // element (r, c) of the identity-padded tile, r >= c
+  auto tile = [&](int r, int c) -> double {
+    if (r < nv && c < nv) return C[(int64_t)c * ld + r];
+    return r == c ? 1.0 : 0.0;
+  };
+  auto put_w = [&](int r, int c, double v) {
+    if (MODE == 0) Wd[c * T + r] = v;
+    else W32[c * T + r] = (float)v;
+  };
+  auto put_l = [&](int r, int c, double v) {  // r, c < nv, r >= c
+    if (MODE == 0) C[(int64_t)c * ld + r] = v;
+    if (MODE == 2) L32[(int64_t)c * ld32 + r] = (float)v;
+  };
+  double sl_total = 0.0;
+
+  // ---- A11 = L11 L11^T, W11 (wave ws) -> P
+  if (w == ws) {
+    if (lane == 0) *flag = 0;  // read by every wave after the next barrier
+    const int bi = lane >> 3, bj = lane & 7;
+    double a[8][8];
+#pragma unroll
+    for (int rr = 0; rr < 8; ++rr)
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc) {
+        const int r = 8 * bi + rr, c = 8 * bj + cc;
+        a[rr][cc] = r >= c ? tile(r, c) : 0.0;
+      }
+    double sl;
+    const int bad = wave64_chol_inv(a, min(nv, 64), colbuf, rowbuf, dinv, sl,
+                                    [&](int r, int c, double v) { put_l(r, c, v); });
+    if (bad) {
+      if (lane == 0) {
+        *info_k = J * T + bad;
+        *flag = 1;
+      }
+    } else {
+      sl_total = sl;
+#pragma unroll
+      for (int rr = 0; rr < 8; ++rr)
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) {
+          const int r = 8 * bi + rr, c = 8 * bj + cc;
+          const double v = (bi >= bj && r >= c) ? a[rr][cc] : 0.0;
+          P[c * PB_LS + r] = v;
+          put_w(r, c, v);
+        }
+    }
+  }
+  __syncthreads();
+  if (*flag) return;
+
+  // ---- L21 = A21 W11^T (wave w: block row w) -> Q and the output
+  {
+    d4 acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
+    const int R = 64 + 16 * w + lr;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int kk = 4 * s + lk;
+      const double av = (R < nv && kk < nv) ? C[(int64_t)kk * ld + R] : 0.0;
+#pragma unroll
+      for (int j = s >> 2; j < 4; ++j)  // W11 row 16 j + lr is zero past column 16 j + 15
+        acc[j] = MF<double>::op(P[kk * PB_LS + 16 * j + lr], av, acc[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = 16 * j + MF<double>::col(lk, e), r = 16 * w + lr;
+        Q[c * PB_LS + r] = acc[j][e];
+        if (64 + r < nv && c < nv) put_l(64 + r, c, acc[j][e]);
+      }
+  }
+  __syncthreads();
+
+  // ---- X^T = W11^T L21^T (wave w: block row w of X^T), then into P
+  {
+    d4 acc[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) acc[m] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int s = 4 * w; s < 16; ++s) {  // W11 column 16 w + lr is zero above row 16 w
+      const int kk = 4 * s + lk;
+      const double av = P[(16 * w + lr) * PB_LS + kk];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) acc[m] = MF<double>::op(Q[kk * PB_LS + 16 * m + lr], av, acc[m]);
+    }
+    __syncthreads();  // every read of W11 done
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) P[(16 * m + MF<double>::col(lk, e)) * PB_LS + 16 * w + lr] = acc[m][e];
+  }
+
+  // ---- A22 - L21 L21^T (wave w: block row w, blocks j <= w) -> Q
+  {
+    d4 acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int kk = 4 * s + lk;
+      const double av = Q[kk * PB_LS + 16 * w + lr];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (j <= w) acc[j] = MF<double>::op(Q[kk * PB_LS + 16 * j + lr], av, acc[j]);
+    }
+    __syncthreads();  // every read of L21 done
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (j > w) continue;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = 16 * j + MF<double>::col(lk, e), r = 16 * w + lr;
+        Q[c * PB_LS + r] = r >= c ? tile(64 + r, 64 + c) - acc[j][e] : 0.0;
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- A22' = L22 L22^T, W22 (wave ws) -> Q
+  if (w == ws) {
+    const int bi = lane >> 3, bj = lane & 7;
+    double a[8][8];
+#pragma unroll
+    for (int rr = 0; rr < 8; ++rr)
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc) {
+        const int r = 8 * bi + rr, c = 8 * bj + cc;
+        a[rr][cc] = r >= c ? Q[c * PB_LS + r] : 0.0;
+      }
+    double sl;
+    const int bad = wave64_chol_inv(a, max(nv - 64, 0), colbuf, rowbuf, dinv, sl,
+                                    [&](int r, int c, double v) { put_l(64 + r, 64 + c, v); });
+    if (bad) {
+      if (lane == 0) {
+        *info_k = J * T + 64 + bad;
+        *flag = 1;
+      }
+    } else {
+      sl_total += sl;
+#pragma unroll
+      for (int rr = 0; rr < 8; ++rr)
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) {
+          const int r = 8 * bi + rr, c = 8 * bj + cc;
+          const double v = (bi >= bj && r >= c) ? a[rr][cc] : 0.0;
+          Q[c * PB_LS + r] = v;
+          put_w(64 + r, 64 + c, v);
+        }
+      // log|V| of the tile: 2 sum log L_jj over both blocks
+      red[lane] = sl_total;
+      wave_lds_sync();
+      if (lane == 0) {
+        double t = 0.0;
+        for (int i = 0; i < 64; ++i) t += red[i];
+        *logdet_k += 2.0 * t;
+      }
+    }
+  }
+  __syncthreads();
+  if (*flag) return;
+
+  // ---- W21 = -W22 X (wave w: block column w); W12 = 0
+  {
+    d4 acc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int kk = 4 * s + lk;
+      const double bv = P[kk * PB_LS + 16 * w + lr];  // X^T row 16 w + lr, column kk
+#pragma unroll
+      for (int i = s >> 2; i < 4; ++i)  // W22 row block i is zero past column 16 i + 15
+        acc[i] = MF<double>::op(bv, Q[kk * PB_LS + 16 * i + lr], acc[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = 16 * i + lr, c = 16 * w + MF<double>::col(lk, e);  // acc[i]: (W22 X) block (i, w)
+        put_w(64 + r, c, -acc[i][e]);
+      }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int idx = 64 * t + lane;  // 1024 zeros of block column w of W12
+      put_w(idx & 63, 64 + 16 * w + (idx >> 6), 0.0);
+    }
+  }
+}
+
 }  // namespace plk
