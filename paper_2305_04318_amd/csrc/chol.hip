@@ -57,7 +57,9 @@ __global__ __launch_bounds__(256, 2) void k_gemm_col(Lay lay, double* __restrict
 // The FP32 partial sums span 4 * flush products (flush = FP32 MFMA k-steps per
 // FP64 fold): 1, 2 or 4, chosen by the caller (default MX_FLUSH; pl_autotune
 // measures the speed/accuracy trade-off per workload).
-template <bool VEC, int FLUSH>
+// DMA: whole packed tiles (I < Nv) take the direct-to-LDS core (lds of at
+// least F32_DMA_LDS_BYTES).
+template <bool VEC, int FLUSH, bool DMA = false>
 __device__ __forceinline__ void dev_col_mx(const Lay& lay, float* __restrict__ m32,
                                            const double* __restrict__ m64, int64_t m64stride,
                                            int k, int I, int J, float* lds) {
@@ -71,8 +73,14 @@ __device__ __forceinline__ void dev_col_mx(const Lay& lay, float* __restrict__ m
   const bool act = ni > 0 && nj > 0;
   d4 acc[4][4];
   zero_acc<double>(acc);
-  wg_gemm_nt_f32x64<FLUSH>(acc, lds, base + lay.tile_off(I, 0), lay.tile_ld(I), arows,
-                           base + lay.tile_off(J, 0), lay.tile_ld(J), brows, kmax, act, ni);
+  if (DMA && lay.kind == 0 && I < lay.Nv) {
+    if (arows <= 0 || brows <= 0) return;  // a tile past an uneven unit's order (uniform)
+    wg_gemm_nt_f32x64_dma<FLUSH>(acc, lds, base + lay.tile_off(I, 0), base + lay.tile_off(J, 0),
+                                 kmax, act, ni);
+  } else {
+    wg_gemm_nt_f32x64<FLUSH>(acc, lds, base + lay.tile_off(I, 0), lay.tile_ld(I), arows,
+                             base + lay.tile_off(J, 0), lay.tile_ld(J), brows, kmax, act, ni);
+  }
   if (act) {
     const int64_t ldc = lay.tile_ld(I);
     float* C = base + lay.tile_off(I, J) + 64 * wr + 64 * wc * ldc;
@@ -147,7 +155,8 @@ __global__ __launch_bounds__(256, 2) void k_col_update_mx(Lay lay, float* __rest
                                                           double* __restrict__ dscratch,
                                                           const int32_t* __restrict__ info, int J,
                                                           int nOff, int K) {
-  __shared__ __attribute__((aligned(16))) char lds_raw[GEMM_LDS_BYTES];
+  __shared__ __attribute__((aligned(16)))
+  char lds_raw[F32_DMA_LDS_BYTES > GEMM_LDS_BYTES ? F32_DMA_LDS_BYTES : GEMM_LDS_BYTES];
   float* lds = reinterpret_cast<float*>(lds_raw);
   const int b = blockIdx.x;
   if (b < K) {
@@ -159,7 +168,7 @@ __global__ __launch_bounds__(256, 2) void k_col_update_mx(Lay lay, float* __rest
   const int wg = xcd_remap(b - K, G);
   const int k = wg / nOff, r = wg % nOff;
   if (info[k] != 0) return;
-  dev_col_mx<true, FLUSH>(lay_of(lay, k), m32, m64, m64stride, k, J + 1 + r, J, lds);
+  dev_col_mx<true, FLUSH, true>(lay_of(lay, k), m32, m64, m64stride, k, J + 1 + r, J, lds);
 }
 
 // Mixed form on a plain column-major FP32 matrix (pl_chol_batched with

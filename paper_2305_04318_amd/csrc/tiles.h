@@ -370,6 +370,122 @@ __device__ __forceinline__ void wg_gemm_nt_f32x64(d4 (&acc)[4][4], float* lds,
   }
 }
 
+// LDS pointers for the direct-to-LDS loads (global_load_lds_dwordx4)
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Publish direct-to-LDS loads to the workgroup: wait until at most N of the
+// wave's vector-memory loads are outstanding (they complete in order, so the
+// older ones have written LDS) and for its LDS accesses, then s_barrier; one
+// asm statement with a memory clobber, so the compiler neither moves memory
+// accesses across it nor relies on its own waits (__syncthreads' fence does
+// not reliably wait for these loads).
+template <int N>
+__device__ __forceinline__ void vmcnt_barrier() {
+  asm volatile("s_waitcnt vmcnt(%0)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+
+// FP32 form with direct-to-LDS loads (the fold pipeline of wg_gemm_nt_f32x64,
+// two stages as in wg_gemm_nt_dma).  One instruction carries two 128-float
+// columns (lanes 0-31 and 32-63, 512 B each), so the columns of a pair are
+// stored back to back and pairs F32_PS floats apart; the odd column of a pair
+// holds row r at r ^ 32 (the lanes' source rows are swizzled, in 16-byte
+// pieces), and with F32_PS = 16 mod 64 the 64 lanes of a fragment read (four
+// columns, sixteen rows) touch 64 different banks.  Whole 128-row panels of
+// leading dimension T; kmax a multiple of 32.
+constexpr int F32_PS = 272;
+constexpr int F32_DMA_LDS_BYTES = 2 * 2 * 16 * F32_PS * 4;  // stages x panels x pairs
+
+template <int FLUSH>
+__device__ __forceinline__ void wg_gemm_nt_f32x64_dma(d4 (&acc)[4][4], float* lds,
+                                                      const float* __restrict__ A,
+                                                      const float* __restrict__ B, int kmax,
+                                                      bool do_mfma, int ni) {
+  constexpr int KC = 32, NPAIR = KC / 2, STG = 2 * NPAIR * F32_PS, PPW = 2 * NPAIR / 4;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wr = wave >> 1, wc = wave & 1;
+  const int nchunks = __builtin_amdgcn_readfirstlane(kmax) / KC;
+  if (nchunks <= 0) return;
+  ni = __builtin_amdgcn_readfirstlane(ni);
+  do_mfma = __builtin_amdgcn_readfirstlane((int)do_mfma) != 0;
+  const int half = lane >> 5;                        // even / odd column of a pair
+  const int srow = (4 * (lane & 31)) ^ (32 * half);  // source row of the lane's 16 bytes
+  // wave w moves pairs PPW w .. PPW w + PPW - 1 of the chunk's 2 NPAIR (A, then B)
+  auto request = [&](int c, int stage) {
+#pragma unroll
+    for (int h = 0; h < PPW; ++h) {
+      const int p = PPW * wave + h;
+      const bool isb = p >= NPAIR;
+      const int q = p - (isb ? NPAIR : 0);
+      const float* src = (isb ? B : A) + (int64_t)(c * KC + 2 * q + half) * T + srow;
+      __builtin_amdgcn_global_load_lds(
+          reinterpret_cast<const void*>(src),
+          (lds_void*)(lds + stage * STG + (isb ? NPAIR * F32_PS : 0) + q * F32_PS), 16, 0, 0);
+    }
+  };
+  request(0, 0);
+  const int lr = lane & 15, lk = lane >> 4;
+  // column 4 s + lk of a chunk: pair 2 s + (lk >> 1), half lk & 1
+  const int swz = (lk & 1) ? 32 : 0;
+  const int colbase = (lk >> 1) * F32_PS + (lk & 1) * 128;
+  f4 pp[4];  // FP32 partials of the block row that is folded in next
+#pragma unroll
+  for (int j = 0; j < 4; ++j) pp[j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int c = 0; c < nchunks; ++c) {
+    const int stage = c & 1;
+    vmcnt_barrier<0>();  // chunk c in LDS; chunk c - 1's stage free
+    if (c + 1 < nchunks) request(c + 1, stage ^ 1);
+    if (do_mfma) {
+      const float* sa = lds + stage * STG + colbase;
+      const float* sb = sa + NPAIR * F32_PS;
+      // rolled: only one group's fragments and partial sums are live at a time
+#pragma unroll 1
+      for (int g = 0; g < KC / 4 / FLUSH; ++g) {
+        float b[FLUSH][4];
+#pragma unroll
+        for (int s4 = 0; s4 < FLUSH; ++s4)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            b[s4][j] = sb[2 * (g * FLUSH + s4) * F32_PS + ((64 * wc + 16 * j + lr) ^ swz)];
+        // software pipeline over block rows: issue row i's MFMAs, then fold
+        // the previous row's FP32 partials into FP64 while they run
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          float a[FLUSH];
+#pragma unroll
+          for (int s4 = 0; s4 < FLUSH; ++s4)
+            a[s4] = sa[2 * (g * FLUSH + s4) * F32_PS + ((64 * wr + 16 * i + lr) ^ swz)];
+          f4 pc[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) pc[j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+          if (i < ni) {
+#pragma unroll
+            for (int s4 = 0; s4 < FLUSH; ++s4)
+#pragma unroll
+              for (int j = 0; j < 4; ++j) pc[j] = MF<float>::op(b[s4][j], a[s4], pc[j]);
+          }
+          const int ip = (i + 3) & 3;
+          if (ip < ni) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+              for (int e = 0; e < 4; ++e) acc[ip][j][e] += (double)pp[j][e];
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) pp[j] = pc[j];
+        }
+      }
+    }
+  }
+  __syncthreads();  // the last stage is read before the caller reuses LDS
+  if (do_mfma && 3 < ni) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[3][j][e] += (double)pp[j][e];
+  }
+}
+
 template <typename TC>
 __device__ __forceinline__ void zero_acc(typename MF<TC>::acc (&acc)[4][4]) {
 #pragma unroll
@@ -496,21 +612,12 @@ __device__ __forceinline__ int nblk(int rows) { return rows <= 0 ? 0 : min(4, (r
 // no registers stage the prefetch and no LDS stores are issued.  NST stages
 // of KC columns: chunk c + NST - 1 is requested right after the barrier that
 // publishes chunk c (every wave has then left chunk c - 1, whose stage it
-// refills) and lands while chunks c .. c + NST - 2 are multiplied.  With two
-// stages the barrier is a __syncthreads (its workgroup-scope release waits
-// for all of the wave's loads: only chunk c's are outstanding); with three,
-// each wave waits for all but the next chunk's loads (vmcnt) and LDS reads,
-// then s_barrier, in one asm statement that the compiler cannot move memory
-// accesses across.  kmax must be a multiple of KC; every block row is
+// refills) and lands while chunks c .. c + NST - 2 are multiplied.  Each
+// chunk is published by vmcnt_barrier: with two stages every load of the
+// wave must be done (only chunk c's are outstanding), with three all but the
+// next chunk's.  kmax must be a multiple of KC; every block row is
 // multiplied (rows a tile does not hold are never stored).  TRI as in
 // wg_gemm_nt.
-typedef __attribute__((address_space(3))) void lds_void;
-
-template <int N>
-__device__ __forceinline__ void vmcnt_barrier() {
-  asm volatile("s_waitcnt vmcnt(%0)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
-}
-
 template <int KC, int NST>
 constexpr int dma_lds_bytes() { return NST * 2 * KC * LROW * 8; }
 
@@ -547,12 +654,8 @@ __device__ __forceinline__ void wg_gemm_nt_dma(d4 (&acc)[4][4], double* lds,
   int stage = 0;
   for (int c = 0; c < nchunks; ++c) {
     // chunk c in LDS; chunk c - 1's stage free
-    if constexpr (NST == 2) {
-      __syncthreads();
-    } else {
-      if (c + 1 < nchunks) vmcnt_barrier<CPW>();
-      else vmcnt_barrier<0>();
-    }
+    if (NST == 2 || c + 1 == nchunks) vmcnt_barrier<0>();
+    else vmcnt_barrier<CPW>();
     if (c + NST - 1 < nchunks) request(c + NST - 1, stage == 0 ? NST - 1 : stage - 1);
     const int jlo = TRI ? tri_lo(wc, c * KC) : 0;
     if (do_mfma && jlo < 4) {
