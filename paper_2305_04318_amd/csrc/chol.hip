@@ -452,13 +452,17 @@ __global__ __launch_bounds__(256, 2) void k_trsm(Lay lay, TS* __restrict__ mats,
                                                  const TS* __restrict__ Wbuf,
                                                  const int32_t* __restrict__ info, int J, int I0,
                                                  int nI, int G, int64_t wstride) {
-  __shared__ __attribute__((aligned(16))) char lds_raw[GEMM_LDS_BYTES];
+  // the FP32 form: whole packed tiles on the direct-to-LDS core
+  constexpr bool DMA32 = sizeof(TS) == 4 && VEC;
+  constexpr int LDS = DMA32 && F32_DMA_LDS_BYTES > GEMM_LDS_BYTES ? F32_DMA_LDS_BYTES : GEMM_LDS_BYTES;
+  __shared__ __attribute__((aligned(16))) char lds_raw[LDS];
   const int wg = xcd_remap(blockIdx.x, G);
   const int k = wg / nI;
   const int I = I0 + wg % nI;
   if (info[k] != 0) return;  // uniform for the workgroup
-  dev_trsm<TS, VEC, MX_FLUSH>(lay_of(lay, k), mats + (int64_t)k * lay.mstride,
-                              Wbuf + (int64_t)k * wstride, J, I, reinterpret_cast<TS*>(lds_raw));
+  dev_trsm<TS, VEC, MX_FLUSH, 2, DMA32>(lay_of(lay, k), mats + (int64_t)k * lay.mstride,
+                                        Wbuf + (int64_t)k * wstride, J, I,
+                                        reinterpret_cast<TS*>(lds_raw));
 }
 
 // FP64 panel solve of the packed layout (tile rows J + 1 .. J + nI): whole

@@ -391,11 +391,11 @@ __device__ __forceinline__ void vmcnt_barrier() {
 // holds row r at r ^ 32 (the lanes' source rows are swizzled, in 16-byte
 // pieces), and with F32_PS = 16 mod 64 the 64 lanes of a fragment read (four
 // columns, sixteen rows) touch 64 different banks.  Whole 128-row panels of
-// leading dimension T; kmax a multiple of 32.
+// leading dimension T; kmax a multiple of 32.  HALF as in wg_gemm_nt_f32x64.
 constexpr int F32_PS = 272;
 constexpr int F32_DMA_LDS_BYTES = 2 * 2 * 16 * F32_PS * 4;  // stages x panels x pairs
 
-template <int FLUSH>
+template <int FLUSH, bool HALF = false>
 __device__ __forceinline__ void wg_gemm_nt_f32x64_dma(d4 (&acc)[4][4], float* lds,
                                                       const float* __restrict__ A,
                                                       const float* __restrict__ B, int kmax,
@@ -435,7 +435,7 @@ __device__ __forceinline__ void wg_gemm_nt_f32x64_dma(d4 (&acc)[4][4], float* ld
     const int stage = c & 1;
     vmcnt_barrier<0>();  // chunk c in LDS; chunk c - 1's stage free
     if (c + 1 < nchunks) request(c + 1, stage ^ 1);
-    if (do_mfma) {
+    if (do_mfma && (!HALF || wc == 1 || c * KC < 64)) {
       const float* sa = lds + stage * STG + colbase;
       const float* sb = sa + NPAIR * F32_PS;
       // rolled: only one group's fragments and partial sums are live at a time
@@ -826,7 +826,9 @@ __device__ __forceinline__ void dev_trsm_border(const Lay& lay, double* base, co
 // The FP64 two-set pipeline (step kernels) uses the TRI column map; the FP32
 // form skips the chunks its first wave column does not need (HALF); the
 // persistent batch kernel's one-set pipeline keeps the plain halves.
-template <typename TS, bool VEC, int FLUSH, int DEPTH = 2>
+// DMA32: the FP32 form of whole packed tiles (I < Nv) takes the direct-to-LDS
+// core (lds of at least F32_DMA_LDS_BYTES).
+template <typename TS, bool VEC, int FLUSH, int DEPTH = 2, bool DMA32 = false>
 __device__ __forceinline__ void dev_trsm(const Lay& lay, TS* base, const TS* W, int J, int I, TS* lds) {
   constexpr bool TRI = sizeof(TS) == 8 && DEPTH > 1;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -842,6 +844,8 @@ __device__ __forceinline__ void dev_trsm(const Lay& lay, TS* base, const TS* W, 
   // the core's final barrier orders every read of C_IJ before the overwrite
   if constexpr (sizeof(TS) == 8) {
     wg_gemm_nt<TS, TS, VEC, 4, DEPTH, TRI>(acc, lds, Ct, ldc, arows, W, T, brows, brows, act, ni);
+  } else if (DMA32 && lay.kind == 0 && I < lay.Nv) {
+    wg_gemm_nt_f32x64_dma<FLUSH, true>(acc, lds, Ct, W, T, act, ni);
   } else {
     wg_gemm_nt_f32x64<FLUSH, true>(acc, lds, Ct, ldc, arows, W, T, brows, brows, act, ni);
   }
