@@ -310,24 +310,22 @@ def bench_uneven(pl, runs, forms=("tune", "persistent", "calls")):
     smx.update({"max_abs_dl_vs_fp64": float(d.max()), "p99_abs_dl_vs_fp64": _pct(d, 99)})
     st["mixed"] = smx
     log(f"uneven bucketed mixed: {smx['ms_median']:.0f} ms, max |dl| {d.max():.2e}")
-    if "tune" not in forms:
-        return st
-    # the autotuner's choice for this workload (budget 1e-3 against FP64),
-    # measured like the others
-    t0 = time.perf_counter()
-    choice, report = pl.batch.autotune(probs, probs[0].lam, tol=1e-3)
-    log(f"uneven autotune ({time.perf_counter() - t0:.0f} s): {choice}")
-    stt, rtt = _run_batch(pl, probs, runs, **choice)
-    stt["max_abs_dl_vs_fp64"] = float(np.max(np.abs(rtt["loglik"][ok] - r64["loglik"][ok])))
-    st["tuned"] = {"choice": choice, "candidates": report, **stt}
-    log(f"uneven tuned: {stt['ms_median']:.0f} ms")
-    if "persistent" not in forms:
-        return st
-    spe, rpe = _run_batch(pl, probs, runs, schedule="persistent")
-    spe["max_rel_diff_vs_bucketed"] = float(np.max(
-        np.abs(rpe["loglik"][ok] - r64["loglik"][ok]) / np.maximum(np.abs(r64["loglik"][ok]), 1)))
-    st["persistent_fp64"] = spe
-    log(f"uneven persistent fp64: {spe['ms_median']:.0f} ms")
+    if "tune" in forms:
+        # the autotuner's choice for this workload (budget 1e-3 against FP64),
+        # measured like the others
+        t0 = time.perf_counter()
+        choice, report = pl.batch.autotune(probs, probs[0].lam, tol=1e-3)
+        log(f"uneven autotune ({time.perf_counter() - t0:.0f} s): {choice}")
+        stt, rtt = _run_batch(pl, probs, runs, **choice)
+        stt["max_abs_dl_vs_fp64"] = float(np.max(np.abs(rtt["loglik"][ok] - r64["loglik"][ok])))
+        st["tuned"] = {"choice": choice, "candidates": report, **stt}
+        log(f"uneven tuned: {stt['ms_median']:.0f} ms")
+    if "persistent" in forms:
+        spe, rpe = _run_batch(pl, probs, runs, schedule="persistent")
+        spe["max_rel_diff_vs_bucketed"] = float(np.max(
+            np.abs(rpe["loglik"][ok] - r64["loglik"][ok]) / np.maximum(np.abs(r64["loglik"][ok]), 1)))
+        st["persistent_fp64"] = spe
+        log(f"uneven persistent fp64: {spe['ms_median']:.0f} ms")
     if "calls" not in forms:
         return st
     pts = st["points"]
