@@ -75,6 +75,17 @@ __device__ __forceinline__ void dev_col_mx(const Lay& lay, float* __restrict__ m
   zero_acc<double>(acc);
   if (DMA && lay.kind == 0 && I < lay.Nv) {
     if (arows <= 0 || brows <= 0) return;  // a tile past an uneven unit's order (uniform)
+    if (arows < T) {
+      // the last tile row: column-split plan
+      wg_gemm_nt_f32x64_dma<FLUSH, false, true>(acc, lds, base + lay.tile_off(I, 0),
+                                                base + lay.tile_off(J, 0), kmax, true,
+                                                (arows + 15) >> 4);
+      const double* Cin = m64 ? m64 + (int64_t)k * m64stride + lay.tile_off(I, J) : nullptr;
+      float* C = base + lay.tile_off(I, J);
+      if (Cin) sub_store_split<float>(Cin, T, C, T, acc, wave, arows, brows, lane);
+      else sub_store_split<float>(C, T, C, T, acc, wave, arows, brows, lane);
+      return;
+    }
     wg_gemm_nt_f32x64_dma<FLUSH>(acc, lds, base + lay.tile_off(I, 0), base + lay.tile_off(J, 0),
                                  kmax, act, ni);
   } else {
@@ -95,51 +106,40 @@ __device__ __forceinline__ void dev_col_mx(const Lay& lay, float* __restrict__ m
 }
 
 // Mixed form, diagonal tile J: FP64 MFMA on the FP32 panel, subtracted from V's
-// FP64 tile, written to the FP64 scratch tile that k_potrf reads.  BORDER:
-// the wave whose quadrant lies above the diagonal also updates the bordered
-// row's FP32 tile (FP64 MFMA on the FP32 panels, one rounding to FP32), so
-// the off-diagonal work does not give that 16- or 32-row tile a workgroup of
-// its own.
+// FP64 tile, written to the FP64 scratch tile that k_potrf reads (the blocks
+// on and below the diagonal; k_potrf reads no other).  BORDER: the bordered
+// row's FP32 tile is updated in the same workgroup (FP64 MFMA on the FP32
+// panels, one rounding to FP32), so the off-diagonal work does not give that
+// 16- or 32-row tile a workgroup of its own.  Balanced plan of
+// wg_gemm_diag_border.
 template <bool VEC, bool BORDER>
 __device__ __forceinline__ void dev_diag_mx(const Lay& lay, float* __restrict__ m32,
                                             const double* __restrict__ m64, int64_t m64stride,
                                             double* __restrict__ dscratch, int k, int J,
                                             float* lds) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int rows = lay.rows(J);
-  const int war = rows - 64 * wr, wbr = rows - 64 * wc;
-  const int ni = nblk(war), nj = nblk(wbr);
-  const bool act = ni > 0 && nj > 0 && wc <= wr;
+  if (rows <= 0) return;  // a tile past an uneven unit's order (uniform)
   float* base = m32 + (int64_t)k * lay.mstride;
   const float* P = base + lay.tile_off(J, 0);
   const int kmax = min(J * T, lay.n);
+  // J = 0: no update; V's lower blocks are copied to the scratch tile
+  const int nbr = (BORDER && kmax > 0) ? lay.TB / 16 : 0;
+  const int qrows = nbr > 0 ? lay.q : 0;
   d4 acc[4][4];
   zero_acc<double>(acc);
-  if constexpr (BORDER) {
-    wg_gemm_diag_border<VEC, float>(acc, lds, P, rows, base + lay.tile_off(lay.Nv, 0), lay.TB,
-                                    lay.q, lay.TB / 16, kmax);
-    if (wr == 0 && wc == 1) {
-      if (kmax == 0) return;  // nothing to subtract
-      sub_store_border<float>(base + lay.tile_off(lay.Nv, J), lay.TB, acc, lay.TB / 16, lay.q,
-                              rows, lane);
-      return;
-    }
+  wg_gemm_diag_border<VEC, float, true>(acc, lds, P, rows, base + lay.tile_off(lay.Nv, 0),
+                                        lay.TB, qrows, nbr, kmax, lay.tile_ld(J));
+  double* Cout = dscratch + (int64_t)k * T * T;
+  float* Cb = base + lay.tile_off(lay.Nv, J);
+  if (m64) {
+    const double* Cin = m64 + (int64_t)k * m64stride + lay.tile_off(J, J);
+    sub_store_diag_bal(Cin, T, Cout, T, Cb, lay.TB, acc, wave, rows, qrows, nbr, lane);
   } else {
-    wg_gemm_nt<float, double, VEC>(acc, lds, P, lay.tile_ld(J), rows, P, lay.tile_ld(J), rows,
-                                   kmax, act, ni);
-  }
-  if (act) {
-    double* Cout = dscratch + (int64_t)k * T * T + 64 * wr + 64 * wc * T;
-    if (m64) {
-      const double* Cin = m64 + (int64_t)k * m64stride + lay.tile_off(J, J) + 64 * wr + 64 * wc * T;
-      store64<double, true>(Cin, T, Cout, T, acc, war, wbr, lane);
-    } else {
-      // no FP64 copy (the plain FP32 matrix of pl_chol_batched): V's tile as stored
-      const int64_t ldj = lay.tile_ld(J);
-      const float* Cin = base + lay.tile_off(J, J) + 64 * wr + 64 * wc * ldj;
-      store64<double, true>(Cin, ldj, Cout, T, acc, war, wbr, lane);
-    }
+    // no FP64 copy (the plain FP32 matrix of pl_chol_batched): V's tile as stored
+    sub_store_diag_bal(base + lay.tile_off(J, J), lay.tile_ld(J), Cout, T, Cb, lay.TB, acc, wave,
+                       rows, qrows, nbr, lane);
   }
 }
 

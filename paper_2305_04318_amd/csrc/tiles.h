@@ -392,10 +392,13 @@ __device__ __forceinline__ void vmcnt_barrier() {
 // pieces), and with F32_PS = 16 mod 64 the 64 lanes of a fragment read (four
 // columns, sixteen rows) touch 64 different banks.  Whole 128-row panels of
 // leading dimension T; kmax a multiple of 32.  HALF as in wg_gemm_nt_f32x64.
+// SPLIT: the column-split plan of wg_gemm_nt_dma (ni then counts the valid
+// block rows): the fold pipeline runs over row pairs, slot row i holding
+// block rows 2 i and 2 i + 1 against the wave's block columns 2 w, 2 w + 1.
 constexpr int F32_PS = 272;
 constexpr int F32_DMA_LDS_BYTES = 2 * 2 * 16 * F32_PS * 4;  // stages x panels x pairs
 
-template <int FLUSH, bool HALF = false>
+template <int FLUSH, bool HALF = false, bool SPLIT = false>
 __device__ __forceinline__ void wg_gemm_nt_f32x64_dma(d4 (&acc)[4][4], float* lds,
                                                       const float* __restrict__ A,
                                                       const float* __restrict__ B, int kmax,
@@ -404,10 +407,14 @@ __device__ __forceinline__ void wg_gemm_nt_f32x64_dma(d4 (&acc)[4][4], float* ld
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wr = wave >> 1, wc = wave & 1;
+  static_assert(!(SPLIT && HALF), "one plan");
   const int nchunks = __builtin_amdgcn_readfirstlane(kmax) / KC;
   if (nchunks <= 0) return;
   ni = __builtin_amdgcn_readfirstlane(ni);
   do_mfma = __builtin_amdgcn_readfirstlane((int)do_mfma) != 0;
+  // SPLIT: valid block rows, and slot rows (row pairs) with any of them
+  const int nrb = ni;
+  if (SPLIT) ni = (nrb + 1) >> 1;
   const int half = lane >> 5;                        // even / odd column of a pair
   const int srow = (4 * (lane & 31)) ^ (32 * half);  // source row of the lane's 16 bytes
   // wave w moves pairs PPW w .. PPW w + PPW - 1 of the chunk's 2 NPAIR (A, then B)
@@ -441,6 +448,45 @@ __device__ __forceinline__ void wg_gemm_nt_f32x64_dma(d4 (&acc)[4][4], float* ld
       // rolled: only one group's fragments and partial sums are live at a time
 #pragma unroll 1
       for (int g = 0; g < KC / 4 / FLUSH; ++g) {
+        if constexpr (SPLIT) {
+          float b[FLUSH][2];
+#pragma unroll
+          for (int s4 = 0; s4 < FLUSH; ++s4)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+              b[s4][j] = sb[2 * (g * FLUSH + s4) * F32_PS + ((32 * wave + 16 * j + lr) ^ swz)];
+          // a row pair with one valid block row also multiplies the pair's
+          // second (padding) row block, which is never stored
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            f4 pc[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) pc[j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+            if (i < ni) {
+              float a[FLUSH][2];
+#pragma unroll
+              for (int s4 = 0; s4 < FLUSH; ++s4)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                  a[s4][h] = sa[2 * (g * FLUSH + s4) * F32_PS + ((32 * i + 16 * h + lr) ^ swz)];
+#pragma unroll
+              for (int s4 = 0; s4 < FLUSH; ++s4)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                  pc[j] = MF<float>::op(b[s4][j & 1], a[s4][j >> 1], pc[j]);
+            }
+            const int ip = (i + 3) & 3;
+            if (ip < ni) {
+#pragma unroll
+              for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[ip][j][e] += (double)pp[j][e];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) pp[j] = pc[j];
+          }
+          continue;
+        }
         float b[FLUSH][4];
 #pragma unroll
         for (int s4 = 0; s4 < FLUSH; ++s4)
@@ -618,14 +664,20 @@ __device__ __forceinline__ int nblk(int rows) { return rows <= 0 ? 0 : min(4, (r
 // next chunk's.  kmax must be a multiple of KC; every block row is
 // multiplied (rows a tile does not hold are never stored).  TRI as in
 // wg_gemm_nt.
+// SPLIT: the column-split plan for a tile with fewer than 128 valid rows
+// (the last tile row): wave w takes block columns 2 w and 2 w + 1 and the
+// nrb valid block rows, block (i, j) in acc[i >> 1][2 (i & 1) + j] -- 2 nrb
+// blocks on every wave, where the quadrant plan runs 16 blocks on the waves
+// of the first wave row whatever the valid rows (a compute unit's waves of
+// one index share a SIMD, so those 16 set the tile's time).
 template <int KC, int NST>
 constexpr int dma_lds_bytes() { return NST * 2 * KC * LROW * 8; }
 
-template <bool TRI, int KC = 16, int NST = 2>
+template <bool TRI, int KC = 16, int NST = 2, bool SPLIT = false>
 __device__ __forceinline__ void wg_gemm_nt_dma(d4 (&acc)[4][4], double* lds,
                                                const double* __restrict__ A,
                                                const double* __restrict__ B, int kmax,
-                                               bool do_mfma) {
+                                               bool do_mfma, int nrb = 8) {
   constexpr int STG = 2 * KC * LROW, CPW = 2 * KC / 4;  // columns per wave and chunk
   static_assert(NST == 2 || NST == 3, "two or three stages");
   static_assert(KC % 8 == 0 && CPW <= 15, "whole k-steps; vmcnt holds one chunk");
@@ -635,6 +687,7 @@ __device__ __forceinline__ void wg_gemm_nt_dma(d4 (&acc)[4][4], double* lds,
   const int nchunks = __builtin_amdgcn_readfirstlane(kmax) / KC;
   if (nchunks <= 0) return;
   do_mfma = __builtin_amdgcn_readfirstlane((int)do_mfma) != 0;
+  nrb = __builtin_amdgcn_readfirstlane(nrb);
   // wave w moves columns CPW w .. CPW w + CPW - 1 of the chunk's 2 KC (A, then B)
   auto request = [&](int c, int stage) {
 #pragma unroll
@@ -657,6 +710,26 @@ __device__ __forceinline__ void wg_gemm_nt_dma(d4 (&acc)[4][4], double* lds,
     if (NST == 2 || c + 1 == nchunks) vmcnt_barrier<0>();
     else vmcnt_barrier<CPW>();
     if (c + NST - 1 < nchunks) request(c + NST - 1, stage == 0 ? NST - 1 : stage - 1);
+    if constexpr (SPLIT) {
+      const double* sa = lds + stage * STG + lr;
+      const double* sb = lds + stage * STG + KC * LROW + 32 * wave + lr;
+#pragma unroll
+      for (int s4 = 0; s4 < KC / 4; ++s4) {
+        const int kk = 4 * s4 + lk;
+        double a[8], b[2];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) a[i] = sa[kk * LROW + 16 * i];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = sb[kk * LROW + 16 * j];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            if (i < nrb) acc[i >> 1][2 * (i & 1) + j] = MF<double>::op(b[j], a[i], acc[i >> 1][2 * (i & 1) + j]);
+      }
+      if (++stage == NST) stage = 0;
+      continue;
+    }
     const int jlo = TRI ? tri_lo(wc, c * KC) : 0;
     if (do_mfma && jlo < 4) {
       const double* sa = lds + stage * STG + 64 * wr + lr;
@@ -707,6 +780,42 @@ __device__ __forceinline__ void dev_gemm_col(const Lay& lay, double* base, int J
   }
 }
 
+// C -= acc for the column-split plan of wg_gemm_nt_dma (wave w; rows below
+// arows, columns below brows valid; leading dimension ldc).  The loads of a
+// slot row's four blocks are issued together, as in store64_l.
+template <typename LAYOUT = double, typename TI = double, typename TO = double>
+__device__ __forceinline__ void sub_store_split(const TI* Cin, int64_t ldin, TO* Cout,
+                                                int64_t ldout, const d4 (&acc)[4][4], int w,
+                                                int arows, int brows, int lane) {
+  const int lr = lane & 15, lg = lane >> 4;
+  arows = __builtin_amdgcn_readfirstlane(arows);
+  brows = __builtin_amdgcn_readfirstlane(brows);
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii) {
+    if (32 * ii >= arows) break;
+    double cin[4][4];
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int rc = min(16 * (2 * ii + (jj >> 1)) + lr, arows - 1);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int cc = min(32 * w + 16 * (jj & 1) + MF<LAYOUT>::col(lg, e), brows - 1);
+        cin[jj][e] = (double)Cin[(int64_t)cc * ldin + rc];
+      }
+    }
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int r = 16 * (2 * ii + (jj >> 1)) + lr;
+      if (r >= arows) continue;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = 32 * w + 16 * (jj & 1) + MF<LAYOUT>::col(lg, e);
+        if (c < brows) Cout[(int64_t)c * ldout + r] = (TO)(cin[jj][e] - acc[ii][jj][e]);
+      }
+    }
+  }
+}
+
 // dev_gemm_col on the direct-to-LDS core: tile (I, J) with I < Nv of the
 // packed layout (whole T x T tiles; L_I,0:J and L_J,0:J are column-major
 // panels of leading dimension T).
@@ -716,12 +825,21 @@ __device__ __forceinline__ void dev_gemm_col_dma(const Lay& lay, double* base, i
   const int wr = wave >> 1, wc = wave & 1;
   const int arows = lay.rows(I), brows = lay.rows(J);
   if (arows <= 0 || brows <= 0) return;  // a tile past an uneven unit's order (uniform)
-  const int war = arows - 64 * wr, wbr = brows - 64 * wc;
-  const bool act = war > 0 && wbr > 0;
   d4 acc[4][4];
   zero_acc<double>(acc);
-  wg_gemm_nt_dma<false>(acc, lds, base + lay.tile_off(I, 0), base + lay.tile_off(J, 0),
-                        min(J * T, lay.n), act);
+  const int kmax = min(J * T, lay.n);
+  if (arows < T) {
+    // the last tile row: column-split plan
+    const int nrb = (arows + 15) >> 4;
+    wg_gemm_nt_dma<false, 16, 2, true>(acc, lds, base + lay.tile_off(I, 0),
+                                       base + lay.tile_off(J, 0), kmax, true, nrb);
+    double* C = base + lay.tile_off(I, J);
+    sub_store_split(C, T, C, T, acc, wave, arows, brows, lane);
+    return;
+  }
+  const int war = arows - 64 * wr, wbr = brows - 64 * wc;
+  const bool act = war > 0 && wbr > 0;
+  wg_gemm_nt_dma<false>(acc, lds, base + lay.tile_off(I, 0), base + lay.tile_off(J, 0), kmax, act);
   if (act) {
     double* C = base + lay.tile_off(I, J) + 64 * wr + 64 * wc * T;
     store64<double, true, double, double>(C, T, C, T, acc, war, wbr, lane);
@@ -888,16 +1006,31 @@ __device__ __forceinline__ void dev_trsm(const Lay& lay, TS* base, const TS* W, 
 // make the register allocator spill): a quadrant wave reads the same four
 // B fragments twice, the border wave two halves of P.  Rows at or beyond
 // prows / qrows and columns at or beyond kmax read as zero.
+//
+// BAL: the balanced plan.  The quadrant plan gives one wave the 16 blocks of
+// the lower-left quadrant while the others run 10 (the diagonal quadrants'
+// lower blocks) or 8 NBR, and a compute unit's waves of one index share a
+// SIMD, so the tile takes as long as 16 blocks on every SIMD.  In the
+// balanced plan wave w takes block columns w and 7 - w of the lower
+// triangle and their bordered-row blocks: 9 + 2 NBR blocks on every wave,
+// in fixed accumulator slots (the guards are uniform):
+//   acc[i][j], i < 2 : block (4 i + j, w),    run for 4 i + j >= w
+//   acc[2][j]        : block (4 + j, 7 - w),  run for 4 + j >= 7 - w
+//   acc[3][j]        : bordered block (j & 1, j < 2 ? w : 7 - w)
+// Row blocks at or beyond prows are skipped as well (the last diagonal
+// tile).  Blocks above the diagonal are not updated (nothing reads them).
 constexpr int LQ = 32 + 4;  // LDS stride per k column of the bordered panel
 constexpr int DIAG_LDS_BYTES = 2 * 16 * (LROW + LQ) * 8;
 static_assert(DIAG_LDS_BYTES <= GEMM_LDS_BYTES, "the diagonal core shares the GEMM LDS");
 
-template <bool VEC, typename TS = double>
+template <bool VEC, typename TS = double, bool BAL = false>
 __device__ __forceinline__ void wg_gemm_diag_border(d4 (&acc)[4][4], TS* lds,
                                                     const TS* __restrict__ P, int prows,
                                                     const TS* __restrict__ Q, int64_t ldq,
-                                                    int qrows, int nbr, int kmax) {
+                                                    int qrows, int nbr, int kmax,
+                                                    int64_t ldp = T) {
   // TS: storage of the panels (FP64, or FP32 in the mixed form); the MFMA is FP64
+  // ldp: leading dimension of P (T in the packed layout)
   constexpr int N = Piece<TS>::N, KC = 128 / (int)sizeof(TS), PPC = T / N;
   constexpr int STAGE = KC * (LROW + LQ);
   typedef typename Piece<TS>::type V;
@@ -926,7 +1059,7 @@ __device__ __forceinline__ void wg_gemm_diag_border(d4 (&acc)[4][4], TS* lds,
     for (int q = 0; q < 4; ++q) {
       const int idx = tid + 256 * q;
       const int col = idx / PPC, row = (idx % PPC) * N;
-      rp[S][q] = fetch_piece<TS, VEC>(P, T, prows, k0 + col, kmax, row);
+      rp[S][q] = fetch_piece<TS, VEC>(P, ldp, prows, k0 + col, kmax, row);
     }
     if (tid < qpieces) {
       const int col = tid / qppc, row = (tid % qppc) * N;
@@ -955,10 +1088,42 @@ __device__ __forceinline__ void wg_gemm_diag_border(d4 (&acc)[4][4], TS* lds,
   stash(S0{});
   __syncthreads();
   const int lr = lane & 15, lk = lane >> 4;
+  // balanced plan (uniform): the wave's two block columns, valid row blocks
+  const int c0 = wave, c1 = 7 - wave;
+  const int nrb = __builtin_amdgcn_readfirstlane((min(prows, T) + 15) >> 4);
   auto step = [&](int c, auto setc, auto other) {
     constexpr int S = decltype(setc)::value;
     if (c + 2 < nchunks) fetch((c + 2) * KC, setc);
     const TS* st = lds + S * STAGE + lr;
+    if constexpr (BAL) {
+#pragma unroll
+      for (int s4 = 0; s4 < KC / 4; ++s4) {
+        const int kk = 4 * s4 + lk;
+        double a[8], q[2];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) a[i] = (double)st[kk * LROW + 16 * i];
+        const double b0 = (double)st[kk * LROW + 16 * c0];
+        const double b1 = (double)st[kk * LROW + 16 * c1];
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib) q[ib] = (double)st[KC * LROW + kk * LQ + 16 * ib];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (4 * i + j >= c0 && 4 * i + j < nrb)
+              acc[i][j] = MF<double>::op(b0, a[4 * i + j], acc[i][j]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (4 + j >= c1 && 4 + j < nrb) acc[2][j] = MF<double>::op(b1, a[4 + j], acc[2][j]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if ((j & 1) < nbr && (j < 2 ? c0 : c1) < nrb)
+            acc[3][j] = MF<double>::op(j < 2 ? b0 : b1, q[j & 1], acc[3][j]);
+      }
+      if (c + 1 < nchunks) stash(other);
+      __syncthreads();
+      return;
+    }
 #pragma unroll
     for (int s4 = 0; s4 < KC / 4; ++s4) {
       const int kk = 4 * s4 + lk;
@@ -986,31 +1151,91 @@ __device__ __forceinline__ void wg_gemm_diag_border(d4 (&acc)[4][4], TS* lds,
   }
 }
 
+// C -= acc for the balanced plan of wg_gemm_diag_border (wave w): C the
+// diagonal tile (leading dimension ldc, prows valid rows and columns), Cb the
+// bordered row's tile (leading dimension ldb, qrows valid rows, nbr block
+// rows).  The loads of a slot row's four blocks are issued together, as in
+// store64_l.
+template <typename TI = double, typename TO = double, typename TBR = double>
+__device__ __forceinline__ void sub_store_diag_bal(const TI* Cin, int64_t ldin, TO* Cout,
+                                                   int64_t ldout, TBR* Cb, int64_t ldb,
+                                                   const d4 (&acc)[4][4], int w, int prows,
+                                                   int qrows, int nbr, int lane) {
+  const int lr = lane & 15, lg = lane >> 4;
+  prows = __builtin_amdgcn_readfirstlane(prows);
+  qrows = __builtin_amdgcn_readfirstlane(qrows);
+  nbr = __builtin_amdgcn_readfirstlane(nbr);
+  const int c1 = 7 - w;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double cin[4][4];
+    bool ok[4];
+    int rb[4], cb[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (i < 2) {
+        rb[j] = 4 * i + j;
+        cb[j] = w;
+        ok[j] = rb[j] >= w;
+      } else if (i == 2) {
+        rb[j] = 4 + j;
+        cb[j] = c1;
+        ok[j] = rb[j] >= c1;
+      } else {
+        rb[j] = j & 1;
+        cb[j] = j < 2 ? w : c1;
+        ok[j] = rb[j] < nbr;
+      }
+      const int rmax = i < 3 ? prows : qrows;
+      ok[j] = ok[j] && 16 * rb[j] < rmax && 16 * cb[j] < prows;
+      const int rc = max(min(16 * rb[j] + lr, rmax - 1), 0);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int cc = max(min(16 * cb[j] + MF<double>::col(lg, e), prows - 1), 0);
+        cin[j][e] = 0.0;
+        if (ok[j]) {
+          if (i < 3) cin[j][e] = (double)Cin[(int64_t)cc * ldin + rc];
+          else cin[j][e] = (double)Cb[(int64_t)cc * ldb + rc];
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int rmax = i < 3 ? prows : qrows;
+      const int r = 16 * rb[j] + lr;
+      if (!ok[j] || r >= rmax) continue;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = 16 * cb[j] + MF<double>::col(lg, e);
+        if (c >= prows) continue;
+        const double v = cin[j][e] - acc[i][j][e];
+        if (i < 3) Cout[(int64_t)c * ldout + r] = (TO)v;
+        else Cb[(int64_t)c * ldb + r] = (TBR)v;
+      }
+    }
+  }
+}
+
 // C_JJ -= L_J,0:J L_J,0:J^T and, when `border` (TB <= 32), the bordered row's
-// tile C_NvJ -= L_Nv,0:J L_J,0:J^T, in one workgroup (wg_gemm_diag_border).
+// tile C_NvJ -= L_Nv,0:J L_J,0:J^T, in one workgroup (wg_gemm_diag_border,
+// balanced plan).
 template <bool VEC>
 __device__ __forceinline__ void dev_gemm_diag_border(const Lay& lay, double* base, int J,
                                                      bool border, double* lds) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int wr = wave >> 1, wc = wave & 1;
   const int prows = lay.rows(J);
   const int qrows = border ? lay.q : 0;
   const int nbr = border ? lay.TB / 16 : 0;
   const int kmax = min(J * T, lay.n);
+  if (prows <= 0 || kmax <= 0) return;
   d4 acc[4][4];
   zero_acc<double>(acc);
-  wg_gemm_diag_border<VEC>(acc, lds, base + lay.tile_off(J, 0), prows,
-                           base + lay.tile_off(lay.Nv, 0), lay.TB, qrows, nbr, kmax);
-  if (wr == 0 && wc == 1) {
-    if (nbr == 0) return;
-    sub_store_border<double>(base + lay.tile_off(lay.Nv, J), lay.TB, acc, nbr, qrows, prows, lane);
-    return;
-  }
-  const int war = prows - 64 * wr, wbr = prows - 64 * wc;
-  if (wc > wr || nblk(war) == 0 || nblk(wbr) == 0) return;
-  double* C = base + lay.tile_off(J, J) + 64 * wr + 64 * wc * T;
-  store64<double, true>(C, T, C, T, acc, war, wbr, lane);
+  wg_gemm_diag_border<VEC, double, true>(acc, lds, base + lay.tile_off(J, 0), prows,
+                                         base + lay.tile_off(lay.Nv, 0), lay.TB, qrows, nbr, kmax);
+  double* C = base + lay.tile_off(J, J);
+  sub_store_diag_bal(C, T, C, T, base + lay.tile_off(lay.Nv, J), lay.TB, acc, wave, prows, qrows,
+                     nbr, lane);
 }
 
 // Diagonal tile J: factor and invert, register-blocked.
