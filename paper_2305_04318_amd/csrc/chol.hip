@@ -271,7 +271,7 @@ hipError_t launch_col_update_mx_plain(const Lay& lay, float* m32, double* dscrat
 //   the FP64 scratch tile, L is not kept, W is written in FP32 to slot J of
 //   the omega's inverse table (the back substitution needs every W_J).
 template <int MODE>
-__global__ __launch_bounds__(256) void k_potrf(Lay lay, double* __restrict__ mats,
+__global__ __launch_bounds__(256, 2) void k_potrf(Lay lay, double* __restrict__ mats,
                                                double* __restrict__ Wbuf, float* __restrict__ W32,
                                                double* __restrict__ logdet,
                                                int32_t* __restrict__ info, int J) {
@@ -296,7 +296,7 @@ hipError_t launch_potrf(const Lay& lay, double* mats, double* W, double* logdet,
 
 // Plain FP32 matrix: the FP64 tile from dscratch[k], L_JJ rounded into the
 // matrix, W_J to the omega's single FP32 slot W32[k].
-__global__ __launch_bounds__(256) void k_potrf_mx_plain(Lay lay, float* __restrict__ m32,
+__global__ __launch_bounds__(256, 2) void k_potrf_mx_plain(Lay lay, float* __restrict__ m32,
                                                         double* __restrict__ dscratch,
                                                         float* __restrict__ W32,
                                                         double* __restrict__ logdet,

@@ -1431,7 +1431,7 @@ __device__ __forceinline__ void dev_potrf(const Lay& lay, double* C, int64_t ld,
 // dev_potrf (the first non-positive pivot sets *info_k; the workgroup then
 // returns uniformly).  smem: at least POTRF_BLK_SMEM_DOUBLES.
 constexpr int PB_LS = 65;  // LDS column stride of a 64 x 64 block
-constexpr int POTRF_BLK_SMEM_DOUBLES = 2 * 64 * PB_LS + 4 * 64 + 8;
+constexpr int POTRF_BLK_SMEM_DOUBLES = 2 * 64 * PB_LS + 64 + 8;
 
 // LDS hand-off between the lanes of one wave: its LDS operations execute in
 // order, so only the compiler has to be kept from moving or forwarding
@@ -1456,44 +1456,79 @@ __device__ __forceinline__ double rsqrt_nr(double d) {
 // identity).  On return a holds W = L^-1 (lower, garbage above the diagonal)
 // and Lout receives L through put_l(r, c, v) for every valid r >= c; sl gets
 // the sum of log L_jj over valid j.  Returns the first failing column + 1
-// (0: success).
+// (0: success).  colbuf and rowbuf hold two 64-double buffers each, dinv 64.
+//
+// Both sweeps look one step ahead, so that a step's latency chain (LDS
+// round trip, reciprocal square root) runs under the previous step's bulk
+// arithmetic: step j first updates column j + 1 (8 of the lane's 64 FMAs),
+// publishes it to the other buffer and reads the next pivot from its owner
+// lane, and only then runs its other 56 FMAs.  The inverse does the same
+// with row m + 1 of W, which step m completes and scales before its bulk
+// update (L's columns do not change during the inverse, so column m + 1 is
+// published at the start of step m).
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffLL), src);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 template <typename PutL>
 __device__ __forceinline__ int wave64_chol_inv(double (&a)[8][8], int nvb, double* colbuf,
                                                double* rowbuf, double* dinv, double& sl,
                                                PutL put_l) {
   const int lane = threadIdx.x & 63, bi = lane >> 3, bj = lane & 7;
   const bool low = bi >= bj;
+  // ---- factor, right-looking: column j unscaled in colbuf[j & 1]
+  if (bj == 0) {
+#pragma unroll
+    for (int rr = 0; rr < 8; ++rr) colbuf[8 * bi + rr] = a[rr][0];
+  }
+  wave_lds_sync();
+  double d = lane_bcast(a[0][0], 0);  // the pivot, from its owner lane
   for (int jb = 0; jb < 8; ++jb) {
 #pragma unroll
     for (int jj = 0; jj < 8; ++jj) {
       const int j = 8 * jb + jj;
-      if (bj == jb) {
+      const double* cb = colbuf + 64 * (jj & 1);
+      double cr[8], cc8[8];
 #pragma unroll
-        for (int rr = 0; rr < 8; ++rr) colbuf[8 * bi + rr] = a[rr][jj];
-      }
-      wave_lds_sync();
-      const double d = colbuf[j];  // the same value in every lane
+      for (int rr = 0; rr < 8; ++rr) cr[rr] = cb[8 * bi + rr];
+#pragma unroll
+      for (int c8 = 0; c8 < 8; ++c8) cc8[c8] = cb[8 * bj + c8];
       if (!(d > 0.0)) return j + 1;
       const double rs = rsqrt_nr(d);  // 1 / L_jj
       if (lane == 0) dinv[j] = rs;
+      const int cn = (jj + 1) & 7;  // lane column of column j + 1
+      const int jbn = jj == 7 ? jb + 1 : jb;
+      const bool more = j + 1 < 64;
       if (low && bj >= jb) {
         const double invd = rs * rs;
-        double cr[8], cc8[8];
 #pragma unroll
-        for (int rr = 0; rr < 8; ++rr) cr[rr] = colbuf[8 * bi + rr] * invd;
+        for (int rr = 0; rr < 8; ++rr) cr[rr] *= invd;
 #pragma unroll
-        for (int c8 = 0; c8 < 8; ++c8) cc8[c8] = (bj > jb || c8 > jj) ? colbuf[8 * bj + c8] : 0.0;
+        for (int c8 = 0; c8 < 8; ++c8) cc8[c8] = (bj > jb || c8 > jj) ? cc8[c8] : 0.0;
+        // column j + 1 first, then its publication
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr) a[rr][cn] = fma(-cr[rr], cc8[cn], a[rr][cn]);
+        if (more && bj == jbn) {
+          double* nb = colbuf + 64 * ((jj + 1) & 1);
+#pragma unroll
+          for (int rr = 0; rr < 8; ++rr) nb[8 * bi + rr] = a[rr][cn];
+        }
 #pragma unroll
         for (int rr = 0; rr < 8; ++rr)
 #pragma unroll
-          for (int c8 = 0; c8 < 8; ++c8) a[rr][c8] = fma(-cr[rr], cc8[c8], a[rr][c8]);
+          for (int c8 = 0; c8 < 8; ++c8)
+            if (c8 != cn) a[rr][c8] = fma(-cr[rr], cc8[c8], a[rr][c8]);
         if (bj == jb) {
 #pragma unroll
           for (int rr = 0; rr < 8; ++rr)
             if (bi > jb || rr >= jj) a[rr][jj] *= rs;
         }
       }
-      wave_lds_sync();  // this step's reads before the next step's writes
+      if (more) d = lane_bcast(a[cn][cn], 9 * jbn);
+      wave_lds_sync();  // keeps this step's LDS accesses before the next step's
     }
   }
   // L is final (dinv holds 1 / L_jj): hand it out, log L_jj
@@ -1512,40 +1547,61 @@ __device__ __forceinline__ int wave64_chol_inv(double (&a)[8][8], int nvb, doubl
     for (int rr = 0; rr < 8; ++rr)
       if (8 * bi + rr < nvb) sl += log(a[rr][rr]);
   }
+  // ---- inverse, row by row: L's column m in colbuf[m & 1], W's final row m
+  // (columns below m) in rowbuf[m & 1]; row 0 has no such columns
+  if (low && bj == 0) {
+#pragma unroll
+    for (int rr = 0; rr < 8; ++rr) colbuf[8 * bi + rr] = a[rr][0];
+  }
   wave_lds_sync();
-  // inverse, row by row (as dev_potrf's second phase)
   for (int mb = 0; mb < 8; ++mb) {
 #pragma unroll
     for (int mm = 0; mm < 8; ++mm) {
       const int m = 8 * mb + mm;
-      if (low && bj == mb) {
+      const int rn = (mm + 1) & 7;  // lane row of row m + 1
+      const int mbn = mm == 7 ? mb + 1 : mb;
+      const bool more = m + 1 < 64;
+      const int p = mm & 1;
+      double lr[8], wv[8];
 #pragma unroll
-        for (int rr = 0; rr < 8; ++rr) colbuf[8 * bi + rr] = a[rr][mm];
-      }
-      if (low && bi == mb) {
-        const double dm = dinv[m];
+      for (int rr = 0; rr < 8; ++rr) lr[rr] = colbuf[64 * p + 8 * bi + rr];
 #pragma unroll
-        for (int c8 = 0; c8 < 8; ++c8) {
-          if (bj < mb || c8 < mm) a[mm][c8] *= dm;
-          rowbuf[8 * bj + c8] = a[mm][c8];
-        }
-      }
-      wave_lds_sync();
+      for (int c8 = 0; c8 < 8; ++c8) wv[c8] = rowbuf[64 * p + 8 * bj + c8];
       const double wmm = dinv[m];
+      const double wn = more ? dinv[m + 1] : 0.0;
+      // L's column m + 1, unchanged since the factorisation
+      if (more && low && bj == mbn) {
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr) colbuf[64 * (1 - p) + 8 * bi + rr] = a[rr][rn];
+      }
       if (low && bi >= mb && bj <= mb) {
-        double lr[8], wv[8];
 #pragma unroll
-        for (int rr = 0; rr < 8; ++rr) lr[rr] = (bi > mb || rr > mm) ? colbuf[8 * bi + rr] : 0.0;
+        for (int rr = 0; rr < 8; ++rr) lr[rr] = (bi > mb || rr > mm) ? lr[rr] : 0.0;
 #pragma unroll
-        for (int c8 = 0; c8 < 8; ++c8) wv[c8] = (bj < mb || c8 < mm) ? rowbuf[8 * bj + c8] : 0.0;
+        for (int c8 = 0; c8 < 8; ++c8) wv[c8] = (bj < mb || c8 < mm) ? wv[c8] : 0.0;
+        // row m + 1 first: its update by row m, W_{m+1,m}, its scaling and
+        // publication
 #pragma unroll
-        for (int rr = 0; rr < 8; ++rr)
+        for (int c8 = 0; c8 < 8; ++c8) a[rn][c8] = fma(-lr[rn], wv[c8], a[rn][c8]);
+        if (bj == mb && (bi > mb || rn > mm)) a[rn][mm] = -lr[rn] * wmm;
+        if (more && bi == mbn) {
+          double* nb = rowbuf + 64 * (1 - p);
+#pragma unroll
+          for (int c8 = 0; c8 < 8; ++c8) {
+            if (bj < mbn || c8 < rn) a[rn][c8] *= wn;
+            nb[8 * bj + c8] = a[rn][c8];
+          }
+        }
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr) {
+          if (rr == rn) continue;
 #pragma unroll
           for (int c8 = 0; c8 < 8; ++c8) a[rr][c8] = fma(-lr[rr], wv[c8], a[rr][c8]);
+        }
         if (bj == mb) {
 #pragma unroll
           for (int rr = 0; rr < 8; ++rr)
-            if (bi > mb || rr > mm) a[rr][mm] = -lr[rr] * wmm;
+            if (rr != rn && (bi > mb || rr > mm)) a[rr][mm] = -lr[rr] * wmm;
           if (bi == mb) a[mm][mm] = wmm;
         }
       }
@@ -1562,10 +1618,12 @@ __device__ __forceinline__ void dev_potrf_blk(const Lay& lay, double* C, int64_t
                                               int64_t ld32 = 0) {
   double* P = smem;                  // W11, then X^T = (L21 W11)^T
   double* Q = smem + 64 * PB_LS;     // L21, then A22 - L21 L21^T, then W22
-  double* colbuf = smem + 2 * 64 * PB_LS;
-  double* rowbuf = colbuf + 64;
-  double* dinv = rowbuf + 64;
-  double* red = dinv + 64;
+  // the one-wave sweeps' buffers live in Q, which holds nothing then (the
+  // first sweep precedes L21; the second starts by loading A22' from it)
+  double* colbuf = Q;        // two buffers
+  double* rowbuf = Q + 128;  // two buffers
+  double* dinv = Q + 256;
+  double* red = smem + 2 * 64 * PB_LS;
   volatile int* flag = reinterpret_cast<volatile int*>(red + 64);
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
