@@ -40,7 +40,8 @@ __global__ void k_cheb_nodes(const MaternParams* __restrict__ mp, double* __rest
   const double sj = cos(M_PI * (j + 0.5) / NC);
   // node j of piece `sub` of binade W_E_LO + bin, in the mantissa of w
   const double w = ldexp(1.0 + (sub + 0.5 + 0.5 * sj) / PB, W_E_LO + bin);
-  nodes[idx] = exp(g_direct(P, w));
+  // rho underflows beyond w_hi (rho_eval returns 0 there)
+  nodes[idx] = w < P.w_hi ? exp(g_direct(P, w)) : 0.0;
 }
 
 __global__ void k_cheb_coeffs(const double* __restrict__ nodes, double* __restrict__ tables, int K) {
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(256) void k_matern(Lay lay, double* __restrict__ ma
                                                 const MaternParams* __restrict__ mp,
                                                 const double* __restrict__ tables, int ntiles,
                                                 int G) {
-  __shared__ double smem[TABLE + 2 * T];
+  __shared__ __attribute__((aligned(16))) double smem[TABLE + 2 * T];
   const int wg = xcd_remap(blockIdx.x, G);
   const int k = wg / ntiles;
   const int t = wg % ntiles;

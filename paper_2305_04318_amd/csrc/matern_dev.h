@@ -46,31 +46,45 @@ static __device__ double g_direct(const MaternParams& P, double w) {
   return P.log_norm + P.kappa * log(x) + (log_scaled_kv_quad(P.kappa, x) - x);
 }
 
-// rho for one element given d^2 (the squared anisotropic distance) and the
-// omega's table (TABLE doubles: per piece, the power-basis coefficients of the
-// Chebyshev interpolant of rho itself in the local variable s).  The piece
-// comes from the binary exponent and mantissa of w = 8 kappa d^2 (no
-// logarithm), the value from a Horner sum clamped to [0, 1] (no exp).
-__device__ __forceinline__ double rho_eval(const MaternParams& P, const double* tab, double d2) {
-  const double w = P.k8 * d2;
-  if (w == 0.0) return 1.0;
-  if (w >= P.w_hi) return 0.0;
-  if (w < 0x1p-20) return fmin(exp(g_direct(P, w)), 1.0);  // 2^W_E_LO
-  int e;
-  const double m = frexp(w, &e);            // w = m 2^e, m in [0.5, 1)
-  const double t = (2.0 * m - 1.0) * PB;    // position in the binade, [0, PB)
-  int j = (int)t;
-  j = j < 0 ? 0 : (j >= PB ? PB - 1 : j);
-  int piece = (e - 1 - W_E_LO) * PB + j;
-  // in range for every finite w in [2^W_E_LO, w_hi); the clamp keeps the
-  // table read in bounds for any input (a NaN coordinate included)
-  piece = piece < 0 ? 0 : (piece >= NPIECE ? NPIECE - 1 : piece);
-  const double s = 2.0 * (t - (double)j) - 1.0;
-  const double* a = tab + piece * NC;  // power-basis coefficients in s
+// rho for one element given w = 8 kappa d^2 (d the anisotropic distance) and
+// the omega's table (TABLE doubles, 16-byte aligned: per piece, the
+// power-basis coefficients of the Chebyshev interpolant of rho itself in the
+// local variable s).  For w >= 2^W_E_LO, a normal double, the piece is the
+// binary exponent and the top two mantissa bits of w (PB = 4 pieces per
+// binade) and s the remaining mantissa bits, read off its bit pattern (no
+// logarithm); the value is a Horner sum clamped to [0, 1] (no exp).
+__device__ __forceinline__ double rho_eval(const MaternParams& P, const double* tab, double w) {
+  static_assert(PB == 4 && NC % 2 == 0, "two mantissa bits per piece; coefficient pairs");
+  if (w < 0x1p-20) {  // 2^W_E_LO; w = 0: coincident locations
+    if (w == 0.0) return 1.0;
+    return fmin(exp(g_direct(P, w)), 1.0);
+  }
+  const long long u = __double_as_longlong(w);
+  const int hi = (int)(u >> 32);
+  // exponent and top two mantissa bits, relative to 2^W_E_LO; the clamp
+  // keeps the table read in bounds for any input (a NaN or infinite w
+  // included, which the final test maps to 0)
+  int piece = (hi >> 18) - ((1023 + W_E_LO) << 2);
+  piece = max(0, min(piece, NPIECE - 1));
+  // the other 50 mantissa bits under exponent 0: v = 1 + f / 4 with f the
+  // position in the piece, in [0, 1); s = 2 f - 1 = 8 v - 9, exact
+  const double v = __longlong_as_double((long long)(((unsigned long long)((hi & 0x3FFFF) | 0x3FF00000) << 32) |
+                                                    (unsigned long long)(u & 0xffffffffLL)));
+  const double s = fma(8.0, v, -9.0);
+  typedef double pair __attribute__((ext_vector_type(2)));
+  const pair* a2 = reinterpret_cast<const pair*>(tab + piece * NC);
+  double a[NC];
+#pragma unroll
+  for (int q = 0; q < NC / 2; ++q) {
+    const pair t = a2[q];
+    a[2 * q] = t.x;
+    a[2 * q + 1] = t.y;
+  }
   double r = a[NC - 1];
 #pragma unroll
   for (int mm = NC - 2; mm >= 0; --mm) r = fma(r, s, a[mm]);
-  return fmin(fmax(r, 0.0), 1.0);
+  r = fmin(fmax(r, 0.0), 1.0);
+  return w < P.w_hi ? r : 0.0;
 }
 
 // ---- covariance tiles -----------------------------------------------------
@@ -92,6 +106,11 @@ __device__ __forceinline__ void matern_tile(const MaternParams& P, const double*
   if (gi >= n) return;
   const double xi = locs[2 * gi], yi = locs[2 * gi + 1];
   const int cmax = min(T, n - J * T);
+  // w = 8 kappa d^2 = |M (dx, dy)|^2: rotation by phi_A, the two range
+  // scales and sqrt(8 kappa) in one 2 x 2 map
+  const double sk = sqrt(P.k8);
+  const double m11 = sk * P.inv_phix * P.cosA, m12 = -sk * P.inv_phix * P.sinA;
+  const double m21 = sk * P.inv_phiy * P.sinA, m22 = sk * P.inv_phiy * P.cosA;
   for (int c = hh; c < cmax; c += 2) {
     const int gj = J * T + c;
     if ((MODE == 1 || MODE == 3) && gj > gi) continue;
@@ -100,10 +119,9 @@ __device__ __forceinline__ void matern_tile(const MaternParams& P, const double*
       v = 1.0 + P.nugget;
     } else {
       const double dx = xi - cx[c], dy = yi - cy[c];
-      const double u1 = P.cosA * dx - P.sinA * dy;
-      const double u2 = P.sinA * dx + P.cosA * dy;
-      const double a = u1 * P.inv_phix, b = u2 * P.inv_phiy;
-      v = rho_eval(P, tab, a * a + b * b);
+      const double u1 = fma(m12, dy, m11 * dx);
+      const double u2 = fma(m22, dy, m21 * dx);
+      v = rho_eval(P, tab, fma(u1, u1, u2 * u2));
     }
     if (MODE != 3) C[(int64_t)c * ldc + r] = v;
     if (MODE == 2 || MODE == 3) C32[(int64_t)c * ldc + r] = (float)v;
