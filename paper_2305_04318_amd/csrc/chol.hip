@@ -349,7 +349,7 @@ __global__ __launch_bounds__(256, 2) void k_col_update(Lay lay, double* __restri
 
 hipError_t launch_col_update(const Lay& lay, double* mats, const int32_t* info, int J, int K,
                              hipStream_t s) {
-  if (J <= 0 || J >= lay.Nv) return hipErrorInvalidValue;
+  if (lay.kind != 0 || J <= 0 || J >= lay.Nv) return hipErrorInvalidValue;
   const bool has_border = lay.kind == 0 && lay.q > 0;
   const bool border = has_border && lay.TB <= 32;
   // off-diagonal tile rows J+1 .. Nv-1, and the bordered row unless the

@@ -669,7 +669,8 @@ __device__ __forceinline__ int nblk(int rows) { return rows <= 0 ? 0 : min(4, (r
 // nrb valid block rows, block (i, j) in acc[i >> 1][2 (i & 1) + j] -- 2 nrb
 // blocks on every wave, where the quadrant plan runs 16 blocks on the waves
 // of the first wave row whatever the valid rows (a compute unit's waves of
-// one index share a SIMD, so those 16 set the tile's time).
+// one index share a SIMD, so those 16 set the tile's time).  With TRI the
+// wave's block columns are w and 7 - w, which need 9 k blocks together.
 template <int KC, int NST>
 constexpr int dma_lds_bytes() { return NST * 2 * KC * LROW * 8; }
 
@@ -711,21 +712,24 @@ __device__ __forceinline__ void wg_gemm_nt_dma(d4 (&acc)[4][4], double* lds,
     else vmcnt_barrier<CPW>();
     if (c + NST - 1 < nchunks) request(c + NST - 1, stage == 0 ? NST - 1 : stage - 1);
     if constexpr (SPLIT) {
+      // the wave's two output block columns (TRI: w and 7 - w, 9 nonzero
+      // k blocks between them; each runs while its k blocks last)
+      const int g0 = TRI ? wave : 2 * wave, g1 = TRI ? 7 - wave : 2 * wave + 1;
+      const bool on0 = !TRI || 16 * (g0 + 1) > c * KC, on1 = !TRI || 16 * (g1 + 1) > c * KC;
       const double* sa = lds + stage * STG + lr;
-      const double* sb = lds + stage * STG + KC * LROW + 32 * wave + lr;
+      const double* sb = lds + stage * STG + KC * LROW + lr;
 #pragma unroll
       for (int s4 = 0; s4 < KC / 4; ++s4) {
         const int kk = 4 * s4 + lk;
-        double a[8], b[2];
+        double a[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) a[i] = sa[kk * LROW + 16 * i];
+        const double b0 = sb[kk * LROW + 16 * g0], b1 = sb[kk * LROW + 16 * g1];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) b[j] = sb[kk * LROW + 16 * j];
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j)
-            if (i < nrb) acc[i >> 1][2 * (i & 1) + j] = MF<double>::op(b[j], a[i], acc[i >> 1][2 * (i & 1) + j]);
+        for (int i = 0; i < 8; ++i) {
+          if (i < nrb && on0) acc[i >> 1][2 * (i & 1)] = MF<double>::op(b0, a[i], acc[i >> 1][2 * (i & 1)]);
+          if (i < nrb && on1) acc[i >> 1][2 * (i & 1) + 1] = MF<double>::op(b1, a[i], acc[i >> 1][2 * (i & 1) + 1]);
+        }
       }
       if (++stage == NST) stage = 0;
       continue;
@@ -860,10 +864,29 @@ __device__ __forceinline__ void dev_trsm_dma(const Lay& lay, double* base, const
   double* Ct = base + lay.tile_off(I, J);
   d4 acc[4][4];
   zero_acc<double>(acc);
+  const int lr = lane & 15, lg = lane >> 4;
+  if (arows < T) {
+    // the last tile row: column-split plan, block columns w and 7 - w
+    wg_gemm_nt_dma<true, KC, NST, true>(acc, lds, Ct, W, T, true, (arows + 15) >> 4);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int r = 16 * i + lr;
+      if (r >= arows) continue;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int cb = 16 * (h ? 7 - wave : wave);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int c = cb + MF<double>::col(lg, e);
+          if (c < brows) Ct[(int64_t)c * T + r] = acc[i >> 1][2 * (i & 1) + h][e];
+        }
+      }
+    }
+    return;
+  }
   // the core's barriers order every read of C_IJ before the overwrite
   wg_gemm_nt_dma<true, KC, NST>(acc, lds, Ct, W, T, act);
   if (!act) return;
-  const int lr = lane & 15, lg = lane >> 4;
   double* Cw = Ct + 64 * wr;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -1151,6 +1174,78 @@ __device__ __forceinline__ void wg_gemm_diag_border(d4 (&acc)[4][4], TS* lds,
   }
 }
 
+// The balanced plan of wg_gemm_diag_border on direct-to-LDS loads, for the
+// packed layout: P = L_J,0:J is a whole-tile panel (leading dimension T) and
+// the bordered rows' panel Q (nbr <= 2 block rows, leading dimension
+// TB = 16 nbr) is contiguous, so a chunk of KC = 16 of its columns is TB / 8
+// pieces of 1 KB.  Per chunk: 16 P columns (four per wave) and the Q pieces
+// (waves 0 .. TB / 8 - 1), two stages published as in wg_gemm_nt_dma.  kmax is
+// a multiple of 16 (J T).
+constexpr int DIAG_DMA_KC = 16;
+constexpr int DIAG_DMA_STG = DIAG_DMA_KC * LROW + DIAG_DMA_KC * 32;  // doubles per stage
+static_assert(2 * DIAG_DMA_STG * 8 <= GEMM_LDS_BYTES, "the diagonal core shares the GEMM LDS");
+
+__device__ __forceinline__ void wg_gemm_diag_dma(d4 (&acc)[4][4], double* lds,
+                                                 const double* __restrict__ P, int prows,
+                                                 const double* __restrict__ Q, int nbr, int kmax) {
+  constexpr int KC = DIAG_DMA_KC, STG = DIAG_DMA_STG, CPW = KC / 4;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nchunks = __builtin_amdgcn_readfirstlane(kmax) / KC;
+  if (nchunks <= 0) return;
+  nbr = __builtin_amdgcn_readfirstlane(nbr);
+  const int tb = 16 * nbr, qpieces = 2 * nbr;  // KC tb doubles = qpieces KB
+  auto request = [&](int c, int stage) {
+    double* st = lds + stage * STG;
+#pragma unroll
+    for (int h = 0; h < CPW; ++h) {
+      const int col = CPW * wave + h;
+      __builtin_amdgcn_global_load_lds(
+          reinterpret_cast<const void*>(P + (int64_t)(c * KC + col) * T + 2 * lane),
+          (lds_void*)(st + col * LROW), 16, 0, 0);
+    }
+    if (wave < qpieces)
+      __builtin_amdgcn_global_load_lds(
+          reinterpret_cast<const void*>(Q + (int64_t)c * KC * tb + 128 * wave + 2 * lane),
+          (lds_void*)(st + KC * LROW + 128 * wave), 16, 0, 0);
+  };
+  request(0, 0);
+  const int lr = lane & 15, lk = lane >> 4;
+  const int c0 = wave, c1 = 7 - wave;
+  const int nrb = __builtin_amdgcn_readfirstlane((min(prows, T) + 15) >> 4);
+  for (int c = 0; c < nchunks; ++c) {
+    const int stage = c & 1;
+    vmcnt_barrier<0>();  // chunk c in LDS; chunk c - 1's stage free
+    if (c + 1 < nchunks) request(c + 1, stage ^ 1);
+    const double* sp = lds + stage * STG + lr;
+    const double* sq = lds + stage * STG + KC * LROW + lr;
+#pragma unroll
+    for (int s4 = 0; s4 < KC / 4; ++s4) {
+      const int kk = 4 * s4 + lk;
+      double a[8], q[2];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) a[i] = sp[kk * LROW + 16 * i];
+      const double b0 = sp[kk * LROW + 16 * c0], b1 = sp[kk * LROW + 16 * c1];
+#pragma unroll
+      for (int ib = 0; ib < 2; ++ib) q[ib] = sq[kk * tb + 16 * ib];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (4 * i + j >= c0 && 4 * i + j < nrb)
+            acc[i][j] = MF<double>::op(b0, a[4 * i + j], acc[i][j]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (4 + j >= c1 && 4 + j < nrb) acc[2][j] = MF<double>::op(b1, a[4 + j], acc[2][j]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if ((j & 1) < nbr && (j < 2 ? c0 : c1) < nrb)
+          acc[3][j] = MF<double>::op(j < 2 ? b0 : b1, q[j & 1], acc[3][j]);
+    }
+  }
+  __syncthreads();  // the last stage is read before the caller reuses LDS
+}
+
 // C -= acc for the balanced plan of wg_gemm_diag_border (wave w): C the
 // diagonal tile (leading dimension ldc, prows valid rows and columns), Cb the
 // bordered row's tile (leading dimension ldb, qrows valid rows, nbr block
@@ -1217,8 +1312,9 @@ __device__ __forceinline__ void sub_store_diag_bal(const TI* Cin, int64_t ldin, 
 }
 
 // C_JJ -= L_J,0:J L_J,0:J^T and, when `border` (TB <= 32), the bordered row's
-// tile C_NvJ -= L_Nv,0:J L_J,0:J^T, in one workgroup (wg_gemm_diag_border,
-// balanced plan).
+// tile C_NvJ -= L_Nv,0:J L_J,0:J^T, in one workgroup (balanced plan; VEC:
+// direct-to-LDS loads, wg_gemm_diag_dma; else wg_gemm_diag_border).  Packed
+// layout, 0 < J < Nv.
 template <bool VEC>
 __device__ __forceinline__ void dev_gemm_diag_border(const Lay& lay, double* base, int J,
                                                      bool border, double* lds) {
@@ -1231,8 +1327,13 @@ __device__ __forceinline__ void dev_gemm_diag_border(const Lay& lay, double* bas
   if (prows <= 0 || kmax <= 0) return;
   d4 acc[4][4];
   zero_acc<double>(acc);
-  wg_gemm_diag_border<VEC, double, true>(acc, lds, base + lay.tile_off(J, 0), prows,
-                                         base + lay.tile_off(lay.Nv, 0), lay.TB, qrows, nbr, kmax);
+  if constexpr (VEC)  // packed layout, J < Nv: kmax = J T
+    wg_gemm_diag_dma(acc, lds, base + lay.tile_off(J, 0), prows, base + lay.tile_off(lay.Nv, 0),
+                     nbr, kmax);
+  else
+    wg_gemm_diag_border<VEC, double, true>(acc, lds, base + lay.tile_off(J, 0), prows,
+                                           base + lay.tile_off(lay.Nv, 0), lay.TB, qrows, nbr,
+                                           kmax);
   double* C = base + lay.tile_off(J, J);
   sub_store_diag_bal(C, T, C, T, base + lay.tile_off(lay.Nv, J), lay.TB, acc, wave, prows, qrows,
                      nbr, lane);
