@@ -122,6 +122,39 @@ __device__ __forceinline__ Lay unit_lay(const BDataset& d, int Nv, int q, int TB
   return lay;
 }
 
+// The task bodies as calls of their own: inlined into one switch they share
+// one register allocation, and the largest (the factorisation) makes the
+// others spill inside their k-loops.
+__device__ __noinline__ void task_gemm(const Lay& lay, double* base, int I, int J, double* smem) {
+  // the step kernels' bodies: direct-to-LDS loads (no staging registers),
+  // the balanced plans; the bordered row's tiles (I = Nv, its own block at
+  // J = Nv included) keep the register-staged core (their panel has TB rows)
+  if (I < lay.Nv && I == J) dev_gemm_diag_border<true>(lay, base, J, false, smem);
+  else if (I < lay.Nv) dev_gemm_col_dma(lay, base, J, I, smem);
+  else dev_gemm_col<true, 1>(lay, base, J, I, smem);
+}
+
+__device__ __noinline__ void task_trsm(const Lay& lay, double* base, const double* W, int I, int J,
+                                       double* smem) {
+  if (I < lay.Nv) {
+    dev_trsm_dma<TRSM_KC, TRSM_NST>(lay, base, W, J, I, smem);
+    return;
+  }
+  switch (lay.TB) {  // the bordered row's tile
+    case 16: dev_trsm_border<1>(lay, base, W, J); break;
+    case 32: dev_trsm_border<2>(lay, base, W, J); break;
+    case 48: dev_trsm_border<3>(lay, base, W, J); break;
+    case 64: dev_trsm_border<4>(lay, base, W, J); break;
+    default: dev_trsm<double, true, 1, 1>(lay, base, W, J, I, smem); break;
+  }
+}
+
+__device__ __noinline__ void task_potrf(const Lay& lay, double* base, double* W, double* logdet_k,
+                                        int32_t* info_k, int J, double* smem) {
+  dev_potrf<0>(lay, base + lay.tile_off(J, J), lay.tile_ld(J), W, nullptr, logdet_k, info_k, J,
+               smem);
+}
+
 __global__ __launch_bounds__(256, 2) void k_batch_persistent(BatchArgs a) {
   __shared__ __attribute__((aligned(16))) char smem_raw[GEMM_LDS_BYTES];
   static_assert((TABLE + 2 * T) * 8 <= GEMM_LDS_BYTES, "covariance task staging");
@@ -165,15 +198,13 @@ __global__ __launch_bounds__(256, 2) void k_batch_persistent(BatchArgs a) {
                            base + lay.tile_off(tk.I, tk.J), lay.tile_ld(tk.I), nullptr, smem);
         break;
       case TK_GEMM:
-        if (!failed) dev_gemm_col<true, 1>(lay, base, tk.J, tk.I, smem);
+        if (!failed) task_gemm(lay, base, tk.I, tk.J, smem);
         break;
       case TK_POTRF:
-        if (!failed)
-          dev_potrf<0>(lay, base + lay.tile_off(tk.J, tk.J), lay.tile_ld(tk.J), W, nullptr,
-                       a.logdet + tk.unit, a.info + tk.unit, tk.J, smem);
+        if (!failed) task_potrf(lay, base, W, a.logdet + tk.unit, a.info + tk.unit, tk.J, smem);
         break;
       case TK_TRSM:
-        if (!failed) dev_trsm<double, true, 1, 1>(lay, base, W, tk.J, tk.I, smem);
+        if (!failed) task_trsm(lay, base, W, tk.I, tk.J, smem);
         break;
       default: {  // TK_FINAL
         const int64_t rec = (int64_t)u.om * a.M;

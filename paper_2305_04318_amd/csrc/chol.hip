@@ -470,7 +470,6 @@ __global__ __launch_bounds__(256, 2) void k_trsm(Lay lay, TS* __restrict__ mats,
 // (49.5 KB of LDS) and no staging registers, so three workgroups share a CU
 // (each tile is only 128 columns deep; the extra workgroups hide the load
 // latency); the bordered row's tile (tile row Nv) on dev_trsm_border.
-constexpr int TRSM_KC = 8, TRSM_NST = 3;
 __global__ __launch_bounds__(256, 3) void k_trsm_dma(Lay lay, double* __restrict__ mats,
                                                      const double* __restrict__ Wbuf,
                                                      const int32_t* __restrict__ info, int J,

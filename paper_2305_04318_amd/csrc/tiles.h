@@ -850,6 +850,10 @@ __device__ __forceinline__ void dev_gemm_col_dma(const Lay& lay, double* base, i
   }
 }
 
+// Chunks of 8 columns in three stages for the FP64 panel solve (49.5 KB of
+// LDS, so three workgroups share a CU).
+constexpr int TRSM_KC = 8, TRSM_NST = 3;
+
 // L_IJ = C_IJ W^T (FP64, TRI column map) on the direct-to-LDS core: tile
 // (I, J) with I < Nv of the packed layout.
 template <int KC, int NST>
