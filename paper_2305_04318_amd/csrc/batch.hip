@@ -156,7 +156,8 @@ __device__ __noinline__ void task_potrf(const Lay& lay, double* base, double* W,
 }
 
 __global__ __launch_bounds__(256, 2) void k_batch_persistent(BatchArgs a) {
-  __shared__ __attribute__((aligned(16))) char smem_raw[GEMM_LDS_BYTES];
+  __shared__ __attribute__((aligned(16)))
+  char smem_raw[UPD_DMA_LDS_BYTES > GEMM_LDS_BYTES ? UPD_DMA_LDS_BYTES : GEMM_LDS_BYTES];
   static_assert((TABLE + 2 * T) * 8 <= GEMM_LDS_BYTES, "covariance task staging");
   static_assert(POTRF_SMEM_DOUBLES * 8 <= GEMM_LDS_BYTES, "factorisation task staging");
   static_assert(FIN_SMEM_DOUBLES * 8 <= GEMM_LDS_BYTES, "finalize task staging");

@@ -335,7 +335,8 @@ template <bool VEC>
 __global__ __launch_bounds__(256, 2) void k_col_update(Lay lay, double* __restrict__ mats,
                                                        const int32_t* __restrict__ info, int J,
                                                        int border, int nOff, int G) {
-  __shared__ __attribute__((aligned(16))) char lds_raw[GEMM_LDS_BYTES];
+  __shared__ __attribute__((aligned(16)))
+  char lds_raw[UPD_DMA_LDS_BYTES > GEMM_LDS_BYTES ? UPD_DMA_LDS_BYTES : GEMM_LDS_BYTES];
   double* lds = reinterpret_cast<double*>(lds_raw);
   const int wg = xcd_remap(blockIdx.x, G);
   const int k = wg / (nOff + 1), r = wg % (nOff + 1);

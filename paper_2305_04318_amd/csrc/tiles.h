@@ -671,15 +671,23 @@ __device__ __forceinline__ int nblk(int rows) { return rows <= 0 ? 0 : min(4, (r
 // of the first wave row whatever the valid rows (a compute unit's waves of
 // one index share a SIMD, so those 16 set the tile's time).  With TRI the
 // wave's block columns are w and 7 - w, which need 9 k blocks together.
-template <int KC, int NST>
-constexpr int dma_lds_bytes() { return NST * 2 * KC * LROW * 8; }
+// LR: LDS stride per k column.  The update uses LROW_UPD = 144 (1152 B, 128 B
+// mod 256): the four 16-lane groups of a fragment read (k columns kk .. kk + 3)
+// then fall on banks 0-31, 32-63, 0-31, 32-63, two conflict-free passes; with
+// LROW = 132 (an 8-bank shift per column) groups 0 and 1 overlap.  The panel
+// solve keeps LROW, whose smaller stages let three workgroups share a CU.
+constexpr int LROW_UPD = 144;
+constexpr int UPD_DMA_LDS_BYTES = 2 * 2 * 16 * LROW_UPD * 8;
 
-template <bool TRI, int KC = 16, int NST = 2, bool SPLIT = false>
+template <int KC, int NST, int LR = LROW>
+constexpr int dma_lds_bytes() { return NST * 2 * KC * LR * 8; }
+
+template <bool TRI, int KC = 16, int NST = 2, bool SPLIT = false, int LR = LROW>
 __device__ __forceinline__ void wg_gemm_nt_dma(d4 (&acc)[4][4], double* lds,
                                                const double* __restrict__ A,
                                                const double* __restrict__ B, int kmax,
                                                bool do_mfma, int nrb = 8) {
-  constexpr int STG = 2 * KC * LROW, CPW = 2 * KC / 4;  // columns per wave and chunk
+  constexpr int STG = 2 * KC * LR, CPW = 2 * KC / 4;  // columns per wave and chunk
   static_assert(NST == 2 || NST == 3, "two or three stages");
   static_assert(KC % 8 == 0 && CPW <= 15, "whole k-steps; vmcnt holds one chunk");
   const int lane = threadIdx.x & 63;
@@ -697,7 +705,7 @@ __device__ __forceinline__ void wg_gemm_nt_dma(d4 (&acc)[4][4], double* lds,
       const bool isb = col >= KC;
       const double* src = (isb ? B : A) + (int64_t)(c * KC + col - (isb ? KC : 0)) * T + 2 * lane;
       __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src),
-                                       (lds_void*)(lds + stage * STG + col * LROW),
+                                       (lds_void*)(lds + stage * STG + col * LR),
                                        16, 0, 0);
     }
   };
@@ -717,14 +725,14 @@ __device__ __forceinline__ void wg_gemm_nt_dma(d4 (&acc)[4][4], double* lds,
       const int g0 = TRI ? wave : 2 * wave, g1 = TRI ? 7 - wave : 2 * wave + 1;
       const bool on0 = !TRI || 16 * (g0 + 1) > c * KC, on1 = !TRI || 16 * (g1 + 1) > c * KC;
       const double* sa = lds + stage * STG + lr;
-      const double* sb = lds + stage * STG + KC * LROW + lr;
+      const double* sb = lds + stage * STG + KC * LR + lr;
 #pragma unroll
       for (int s4 = 0; s4 < KC / 4; ++s4) {
         const int kk = 4 * s4 + lk;
         double a[8];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) a[i] = sa[kk * LROW + 16 * i];
-        const double b0 = sb[kk * LROW + 16 * g0], b1 = sb[kk * LROW + 16 * g1];
+        for (int i = 0; i < 8; ++i) a[i] = sa[kk * LR + 16 * i];
+        const double b0 = sb[kk * LR + 16 * g0], b1 = sb[kk * LR + 16 * g1];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
           if (i < nrb && on0) acc[i >> 1][2 * (i & 1)] = MF<double>::op(b0, a[i], acc[i >> 1][2 * (i & 1)]);
@@ -737,15 +745,15 @@ __device__ __forceinline__ void wg_gemm_nt_dma(d4 (&acc)[4][4], double* lds,
     const int jlo = TRI ? tri_lo(wc, c * KC) : 0;
     if (do_mfma && jlo < 4) {
       const double* sa = lds + stage * STG + 64 * wr + lr;
-      const double* sb = lds + stage * STG + KC * LROW + (TRI ? 0 : 64 * wc) + lr;
+      const double* sb = lds + stage * STG + KC * LR + (TRI ? 0 : 64 * wc) + lr;
 #pragma unroll
       for (int s4 = 0; s4 < KC / 4; ++s4) {
         const int kk = 4 * s4 + lk;
         double a[4], b[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          a[i] = sa[kk * LROW + 16 * i];
-          b[i] = sb[kk * LROW + 16 * (TRI ? tri_blk(wc, i) : i)];
+          a[i] = sa[kk * LR + 16 * i];
+          b[i] = sb[kk * LR + 16 * (TRI ? tri_blk(wc, i) : i)];
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i)
@@ -835,15 +843,16 @@ __device__ __forceinline__ void dev_gemm_col_dma(const Lay& lay, double* base, i
   if (arows < T) {
     // the last tile row: column-split plan
     const int nrb = (arows + 15) >> 4;
-    wg_gemm_nt_dma<false, 16, 2, true>(acc, lds, base + lay.tile_off(I, 0),
-                                       base + lay.tile_off(J, 0), kmax, true, nrb);
+    wg_gemm_nt_dma<false, 16, 2, true, LROW_UPD>(acc, lds, base + lay.tile_off(I, 0),
+                                                 base + lay.tile_off(J, 0), kmax, true, nrb);
     double* C = base + lay.tile_off(I, J);
     sub_store_split(C, T, C, T, acc, wave, arows, brows, lane);
     return;
   }
   const int war = arows - 64 * wr, wbr = brows - 64 * wc;
   const bool act = war > 0 && wbr > 0;
-  wg_gemm_nt_dma<false>(acc, lds, base + lay.tile_off(I, 0), base + lay.tile_off(J, 0), kmax, act);
+  wg_gemm_nt_dma<false, 16, 2, false, LROW_UPD>(acc, lds, base + lay.tile_off(I, 0),
+                                                base + lay.tile_off(J, 0), kmax, act);
   if (act) {
     double* C = base + lay.tile_off(I, J) + 64 * wr + 64 * wc * T;
     store64<double, true, double, double>(C, T, C, T, acc, war, wbr, lane);
@@ -1186,8 +1195,8 @@ __device__ __forceinline__ void wg_gemm_diag_border(d4 (&acc)[4][4], TS* lds,
 // (waves 0 .. TB / 8 - 1), two stages published as in wg_gemm_nt_dma.  kmax is
 // a multiple of 16 (J T).
 constexpr int DIAG_DMA_KC = 16;
-constexpr int DIAG_DMA_STG = DIAG_DMA_KC * LROW + DIAG_DMA_KC * 32;  // doubles per stage
-static_assert(2 * DIAG_DMA_STG * 8 <= GEMM_LDS_BYTES, "the diagonal core shares the GEMM LDS");
+constexpr int DIAG_DMA_STG = DIAG_DMA_KC * LROW_UPD + DIAG_DMA_KC * 32;  // doubles per stage
+static_assert(2 * DIAG_DMA_STG * 8 <= UPD_DMA_LDS_BYTES, "the diagonal core shares the update's LDS");
 
 __device__ __forceinline__ void wg_gemm_diag_dma(d4 (&acc)[4][4], double* lds,
                                                  const double* __restrict__ P, int prows,
@@ -1206,12 +1215,12 @@ __device__ __forceinline__ void wg_gemm_diag_dma(d4 (&acc)[4][4], double* lds,
       const int col = CPW * wave + h;
       __builtin_amdgcn_global_load_lds(
           reinterpret_cast<const void*>(P + (int64_t)(c * KC + col) * T + 2 * lane),
-          (lds_void*)(st + col * LROW), 16, 0, 0);
+          (lds_void*)(st + col * LROW_UPD), 16, 0, 0);
     }
     if (wave < qpieces)
       __builtin_amdgcn_global_load_lds(
           reinterpret_cast<const void*>(Q + (int64_t)c * KC * tb + 128 * wave + 2 * lane),
-          (lds_void*)(st + KC * LROW + 128 * wave), 16, 0, 0);
+          (lds_void*)(st + KC * LROW_UPD + 128 * wave), 16, 0, 0);
   };
   request(0, 0);
   const int lr = lane & 15, lk = lane >> 4;
@@ -1222,14 +1231,14 @@ __device__ __forceinline__ void wg_gemm_diag_dma(d4 (&acc)[4][4], double* lds,
     vmcnt_barrier<0>();  // chunk c in LDS; chunk c - 1's stage free
     if (c + 1 < nchunks) request(c + 1, stage ^ 1);
     const double* sp = lds + stage * STG + lr;
-    const double* sq = lds + stage * STG + KC * LROW + lr;
+    const double* sq = lds + stage * STG + KC * LROW_UPD + lr;
 #pragma unroll
     for (int s4 = 0; s4 < KC / 4; ++s4) {
       const int kk = 4 * s4 + lk;
       double a[8], q[2];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) a[i] = sp[kk * LROW + 16 * i];
-      const double b0 = sp[kk * LROW + 16 * c0], b1 = sp[kk * LROW + 16 * c1];
+      for (int i = 0; i < 8; ++i) a[i] = sp[kk * LROW_UPD + 16 * i];
+      const double b0 = sp[kk * LROW_UPD + 16 * c0], b1 = sp[kk * LROW_UPD + 16 * c1];
 #pragma unroll
       for (int ib = 0; ib < 2; ++ib) q[ib] = sq[kk * tb + 16 * ib];
 #pragma unroll
