@@ -17,8 +17,9 @@
 //
 // Two forms share these kernels:
 //   FP64  : every tile in FP64, FP64 MFMA.
-//   mixed : the factor is stored in FP32 and off-diagonal updates and panel
-//           solves use FP32 MFMA; each diagonal tile is updated with FP64
+//   mixed : the factor is stored in FP32 and off-diagonal updates use FP32
+//           MFMA; panel solves (k_trsm_mx_dma) widen the FP32 tiles to FP64
+//           MFMA and round L once; each diagonal tile is updated with FP64
 //           accumulation from the original FP64 V and factored in FP64, and
 //           the log-determinant is accumulated in FP64.
 //
@@ -77,7 +78,7 @@ __device__ __forceinline__ void dev_col_mx(const Lay& lay, float* __restrict__ m
     if (arows <= 0 || brows <= 0) return;  // a tile past an uneven unit's order (uniform)
     if (arows < T) {
       // the last tile row: column-split plan
-      wg_gemm_nt_f32x64_dma<FLUSH, false, true>(acc, lds, base + lay.tile_off(I, 0),
+      wg_gemm_nt_f32x64_dma<FLUSH, true>(acc, lds, base + lay.tile_off(I, 0),
                                                 base + lay.tile_off(J, 0), kmax, true,
                                                 (arows + 15) >> 4);
       const double* Cin = m64 ? m64 + (int64_t)k * m64stride + lay.tile_off(I, J) : nullptr;
@@ -453,17 +454,13 @@ __global__ __launch_bounds__(256, 2) void k_trsm(Lay lay, TS* __restrict__ mats,
                                                  const TS* __restrict__ Wbuf,
                                                  const int32_t* __restrict__ info, int J, int I0,
                                                  int nI, int G, int64_t wstride) {
-  // the FP32 form: whole packed tiles on the direct-to-LDS core
-  constexpr bool DMA32 = sizeof(TS) == 4 && VEC;
-  constexpr int LDS = DMA32 && F32_DMA_LDS_BYTES > GEMM_LDS_BYTES ? F32_DMA_LDS_BYTES : GEMM_LDS_BYTES;
-  __shared__ __attribute__((aligned(16))) char lds_raw[LDS];
+  __shared__ __attribute__((aligned(16))) char lds_raw[GEMM_LDS_BYTES];
   const int wg = xcd_remap(blockIdx.x, G);
   const int k = wg / nI;
   const int I = I0 + wg % nI;
   if (info[k] != 0) return;  // uniform for the workgroup
-  dev_trsm<TS, VEC, MX_FLUSH, 2, DMA32>(lay_of(lay, k), mats + (int64_t)k * lay.mstride,
-                                        Wbuf + (int64_t)k * wstride, J, I,
-                                        reinterpret_cast<TS*>(lds_raw));
+  dev_trsm<TS, VEC, MX_FLUSH, 2>(lay_of(lay, k), mats + (int64_t)k * lay.mstride,
+                                 Wbuf + (int64_t)k * wstride, J, I, reinterpret_cast<TS*>(lds_raw));
 }
 
 // FP64 panel solve of the packed layout (tile rows J + 1 .. J + nI): whole
@@ -496,6 +493,36 @@ __global__ __launch_bounds__(256, 3) void k_trsm_dma(Lay lay, double* __restrict
   }
 }
 
+// Mixed-form panel solve of the packed layout (tile rows J + 1 .. J + nI):
+// whole tiles in FP64 MFMA on FP32 panels loaded straight into LDS (chunks of
+// 16 columns in three stages, 51 KB, three workgroups per CU), the bordered
+// row's tile on dev_trsm_border<., float>.  W from slot J of the omega's
+// table (wstride floats per omega).
+__global__ __launch_bounds__(256, 3) void k_trsm_mx_dma(Lay lay, float* __restrict__ m32,
+                                                        const float* __restrict__ Wbuf,
+                                                        const int32_t* __restrict__ info, int J,
+                                                        int nI, int G, int64_t wstride) {
+  __shared__ __attribute__((aligned(16))) char lds_raw[f32dma_lds_bytes<TRSM_MX_KC, TRSM_MX_NST>()];
+  const int wg = xcd_remap(blockIdx.x, G);
+  const int k = wg / nI;
+  const int I = J + 1 + wg % nI;
+  if (info[k] != 0) return;  // uniform for the workgroup
+  const Lay L = lay_of(lay, k);
+  float* base = m32 + (int64_t)k * lay.mstride;
+  const float* W = Wbuf + (int64_t)k * wstride;
+  if (I < lay.Nv) {
+    dev_trsm_mx_dma(L, base, W, J, I, reinterpret_cast<float*>(lds_raw));
+    return;
+  }
+  if (lay.q <= 0) return;  // no bordered row: nothing below the last tile row
+  switch (lay.TB) {
+    case 16: dev_trsm_border<1, float>(L, base, W, J); break;
+    case 32: dev_trsm_border<2, float>(L, base, W, J); break;
+    case 48: dev_trsm_border<3, float>(L, base, W, J); break;
+    default: dev_trsm_border<4, float>(L, base, W, J); break;
+  }
+}
+
 hipError_t launch_trsm(const Lay& lay, double* mats, const double* W, const int32_t* info, int J,
                        int nI, int K, hipStream_t s) {
   const int64_t ws = (int64_t)T * T;
@@ -520,10 +547,15 @@ hipError_t launch_trsm(const Lay& lay, double* mats, const double* W, const int3
 
 hipError_t launch_trsm_mx(const Lay& lay, float* m32, const float* W32, const int32_t* info, int J,
                           int nI, int K, hipStream_t s) {
+  if (nI <= 0) return hipSuccess;
   const int G = K * nI;
   const int64_t ws = (int64_t)lay.Nv * T * T;
-  hipLaunchKernelGGL((k_trsm<float, true>), dim3(G), dim3(256), 0, s, lay, m32,
-                     W32 + (int64_t)J * T * T, info, J, J + 1, nI, G, ws);
+  if (lay.kind == 0 && (lay.q == 0 || lay.TB <= 64))
+    hipLaunchKernelGGL(k_trsm_mx_dma, dim3(G), dim3(256), 0, s, lay, m32,
+                       W32 + (int64_t)J * T * T, info, J, nI, G, ws);
+  else
+    hipLaunchKernelGGL((k_trsm<float, true>), dim3(G), dim3(256), 0, s, lay, m32,
+                       W32 + (int64_t)J * T * T, info, J, J + 1, nI, G, ws);
   return hipGetLastError();
 }
 

@@ -384,6 +384,18 @@ __device__ __forceinline__ void vmcnt_barrier() {
   asm volatile("s_waitcnt vmcnt(%0)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
 }
 
+// vmcnt_barrier leaving the requests of `ahead` later chunks (P loads per
+// wave each, ahead <= MAXA, uniform) in flight.
+template <int P, int MAXA>
+__device__ __forceinline__ void vmcnt_barrier_ahead(int ahead) {
+  if constexpr (MAXA <= 0) {
+    vmcnt_barrier<0>();
+  } else {
+    if (ahead >= MAXA) vmcnt_barrier<P * MAXA>();
+    else vmcnt_barrier_ahead<P, MAXA - 1>(ahead);
+  }
+}
+
 // FP32 form with direct-to-LDS loads (the fold pipeline of wg_gemm_nt_f32x64,
 // two stages as in wg_gemm_nt_dma).  One instruction carries two 128-float
 // columns (lanes 0-31 and 32-63, 512 B each), so the columns of a pair are
@@ -391,14 +403,14 @@ __device__ __forceinline__ void vmcnt_barrier() {
 // holds row r at r ^ 32 (the lanes' source rows are swizzled, in 16-byte
 // pieces), and with F32_PS = 16 mod 64 the 64 lanes of a fragment read (four
 // columns, sixteen rows) touch 64 different banks.  Whole 128-row panels of
-// leading dimension T; kmax a multiple of 32.  HALF as in wg_gemm_nt_f32x64.
+// leading dimension T; kmax a multiple of 32.
 // SPLIT: the column-split plan of wg_gemm_nt_dma (ni then counts the valid
 // block rows): the fold pipeline runs over row pairs, slot row i holding
 // block rows 2 i and 2 i + 1 against the wave's block columns 2 w, 2 w + 1.
 constexpr int F32_PS = 272;
 constexpr int F32_DMA_LDS_BYTES = 2 * 2 * 16 * F32_PS * 4;  // stages x panels x pairs
 
-template <int FLUSH, bool HALF = false, bool SPLIT = false>
+template <int FLUSH, bool SPLIT = false>
 __device__ __forceinline__ void wg_gemm_nt_f32x64_dma(d4 (&acc)[4][4], float* lds,
                                                       const float* __restrict__ A,
                                                       const float* __restrict__ B, int kmax,
@@ -407,7 +419,6 @@ __device__ __forceinline__ void wg_gemm_nt_f32x64_dma(d4 (&acc)[4][4], float* ld
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wr = wave >> 1, wc = wave & 1;
-  static_assert(!(SPLIT && HALF), "one plan");
   const int nchunks = __builtin_amdgcn_readfirstlane(kmax) / KC;
   if (nchunks <= 0) return;
   ni = __builtin_amdgcn_readfirstlane(ni);
@@ -442,7 +453,7 @@ __device__ __forceinline__ void wg_gemm_nt_f32x64_dma(d4 (&acc)[4][4], float* ld
     const int stage = c & 1;
     vmcnt_barrier<0>();  // chunk c in LDS; chunk c - 1's stage free
     if (c + 1 < nchunks) request(c + 1, stage ^ 1);
-    if (do_mfma && (!HALF || wc == 1 || c * KC < 64)) {
+    if (do_mfma) {
       const float* sa = lds + stage * STG + colbase;
       const float* sb = sa + NPAIR * F32_PS;
       // rolled: only one group's fragments and partial sums are live at a time
@@ -530,6 +541,86 @@ __device__ __forceinline__ void wg_gemm_nt_f32x64_dma(d4 (&acc)[4][4], float* ld
 #pragma unroll
       for (int e = 0; e < 4; ++e) acc[3][j][e] += (double)pp[j][e];
   }
+}
+
+// acc += C[0:128, 0:128] W[0:128, 0:128]^T in FP64 MFMA from FP32 panels
+// staged as in wg_gemm_nt_f32x64_dma (chunks of KC columns, column pairs
+// F32_PS floats apart, the odd column's rows swizzled by 32), each fragment
+// widened to FP64 on its LDS read: the mixed form's panel solve of a whole
+// packed tile, with exact products and FP64 sums (no FP32 partials to fold).
+// TRI column map of the FP64 panel solve: the blocks that still need a
+// k-step from k0 on are j >= tri_lo(wc, k0).  NST stages as in
+// wg_gemm_nt_dma.  Both panels have leading dimension T and 128 rows.
+template <int KC, int NST>
+constexpr int f32dma_lds_bytes() { return NST * 2 * (KC / 2) * F32_PS * 4; }
+
+template <int KC, int NST>
+__device__ __forceinline__ void wg_gemm_nt_f32dma_f64(d4 (&acc)[4][4], float* lds,
+                                                      const float* __restrict__ A,
+                                                      const float* __restrict__ B, int kmax,
+                                                      bool do_mfma) {
+  constexpr int NPAIR = KC / 2, STG = 2 * NPAIR * F32_PS, PPW = 2 * NPAIR / 4;
+  static_assert(NST >= 2 && NST <= 6, "two to six stages");
+  static_assert((KC == 8 || KC % 16 == 0) && (NST - 2) * PPW <= 15,
+                "no k block split across chunks; vmcnt holds the chunks in flight");
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wr = wave >> 1, wc = wave & 1;
+  const int nchunks = __builtin_amdgcn_readfirstlane(kmax) / KC;
+  if (nchunks <= 0) return;
+  do_mfma = __builtin_amdgcn_readfirstlane((int)do_mfma) != 0;
+  const int half = lane >> 5;                        // even / odd column of a pair
+  const int srow = (4 * (lane & 31)) ^ (32 * half);  // source row of the lane's 16 bytes
+  // wave w moves pairs PPW w .. PPW w + PPW - 1 of the chunk's 2 NPAIR (A, then B)
+  auto request = [&](int c, int stage) {
+#pragma unroll
+    for (int h = 0; h < PPW; ++h) {
+      const int p = PPW * wave + h;
+      const bool isb = p >= NPAIR;
+      const int q = p - (isb ? NPAIR : 0);
+      const float* src = (isb ? B : A) + (int64_t)(c * KC + 2 * q + half) * T + srow;
+      __builtin_amdgcn_global_load_lds(
+          reinterpret_cast<const void*>(src),
+          (lds_void*)(lds + stage * STG + (isb ? NPAIR * F32_PS : 0) + q * F32_PS), 16, 0, 0);
+    }
+  };
+#pragma unroll
+  for (int p = 0; p < NST - 1; ++p)
+    if (p < nchunks) request(p, p);
+  const int lr = lane & 15, lk = lane >> 4;
+  // column 4 s + lk of a chunk: pair 2 s + (lk >> 1), half lk & 1
+  const int swz = (lk & 1) ? 32 : 0;
+  const int colbase = (lk >> 1) * F32_PS + (lk & 1) * 128;
+  int stage = 0;
+  for (int c = 0; c < nchunks; ++c) {
+    // chunk c in LDS (the requests of the chunks after it may stay in
+    // flight); chunk c - 1's stage free
+    vmcnt_barrier_ahead<PPW, NST - 2>(min(NST - 2, nchunks - 1 - c));
+    if (c + NST - 1 < nchunks) request(c + NST - 1, stage == 0 ? NST - 1 : stage - 1);
+    // no chunk straddles a 16-column k block: every k of the chunk has the
+    // same block columns
+    const int jlo = tri_lo(wc, c * KC);
+    if (do_mfma && jlo < 4) {
+      const float* sa = lds + stage * STG + colbase;
+      const float* sb = sa + NPAIR * F32_PS;
+#pragma unroll
+      for (int s4 = 0; s4 < KC / 4; ++s4) {
+        double a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          a[i] = (double)sa[2 * s4 * F32_PS + ((64 * wr + 16 * i + lr) ^ swz)];
+          b[i] = (double)sb[2 * s4 * F32_PS + ((16 * tri_blk(wc, i) + lr) ^ swz)];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (j >= jlo) acc[i][j] = MF<double>::op(b[j], a[i], acc[i][j]);
+      }
+    }
+    if (++stage == NST) stage = 0;
+  }
+  __syncthreads();  // the last stage is read before the caller reuses LDS
 }
 
 template <typename TC>
@@ -917,21 +1008,56 @@ __device__ __forceinline__ void dev_trsm_dma(const Lay& lay, double* base, const
   }
 }
 
+// Mixed-form panel solve of a whole packed tile (I < Nv), FP32 storage:
+// wg_gemm_nt_f32dma_f64 with the TRI column map, L rounded to FP32 once.
+constexpr int TRSM_MX_KC = 8, TRSM_MX_NST = 3;
+
+__device__ __forceinline__ void dev_trsm_mx_dma(const Lay& lay, float* base, const float* W,
+                                                int J, int I, float* lds) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int war = lay.rows(I) - 64 * wr, brows = lay.rows(J);
+  const bool act = war > 0 && 16 * tri_blk(wc, 0) < brows;
+  float* Ct = base + lay.tile_off(I, J);
+  d4 acc[4][4];
+  zero_acc<double>(acc);
+  // the core's final barrier orders every read of C_IJ before the overwrite
+  wg_gemm_nt_f32dma_f64<TRSM_MX_KC, TRSM_MX_NST>(acc, lds, Ct, W, T, act);
+  if (!act) return;
+  const int lr = lane & 15, lg = lane >> 4;
+  float* Cw = Ct + 64 * wr;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = 16 * i + lr;
+    if (r >= war) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int cb = 16 * tri_blk(wc, j);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = cb + MF<double>::col(lg, e);
+        if (c < brows) Cw[(int64_t)c * T + r] = (float)acc[i][j][e];
+      }
+    }
+  }
+}
+
 // L_NvJ = C_NvJ W^T for the bordered row's tile (q valid rows of TB = 16 NBR,
 // leading dimension TB) without LDS: wave w computes the output block
 // columns w and 7 - w (w + 1 and 8 - w nonzero k-blocks of W^T: the same
 // count for every wave) over all NBR block rows, with fragments loaded
 // straight from global memory (16 lanes read 16 consecutive rows of one
-// column), four k-steps per batch of loads.  One barrier separates the last
-// read of C from the first write of L (the waves read columns that others
-// write).
-template <int NBR>
-__device__ __forceinline__ void dev_trsm_border(const Lay& lay, double* base, const double* W,
-                                                int J) {
+// column), four k-steps per batch of loads; columns at or beyond brows (the
+// last block column's padding, which need not hold finite values in C or W)
+// read as zero.  One barrier separates the last read of C from the first
+// write of L (the waves read columns that others write).  TS float: the mixed form's FP32 storage, widened on the load and
+// rounded once on the store (the MFMA is FP64).
+template <int NBR, typename TS = double>
+__device__ __forceinline__ void dev_trsm_border(const Lay& lay, TS* base, const TS* W, int J) {
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lr = lane & 15, lk = lane >> 4;
-  double* C = base + lay.tile_off(lay.Nv, J);
+  TS* C = base + lay.tile_off(lay.Nv, J);
   const int64_t ld = lay.TB;
   const int q = lay.q, brows = lay.rows(J);
   const int g0 = w, g1 = 7 - w;         // g1 > g0: the longer k range
@@ -945,9 +1071,10 @@ __device__ __forceinline__ void dev_trsm_border(const Lay& lay, double* base, co
     for (int u = 0; u < 4; ++u) {
       const int kk = 4 * (s0 + u) + lk;
 #pragma unroll
-      for (int ib = 0; ib < NBR; ++ib) a[u][ib] = C[(int64_t)kk * ld + 16 * ib + lr];
-      b[u][0] = W[(int64_t)kk * T + 16 * g0 + lr];
-      b[u][1] = W[(int64_t)kk * T + 16 * g1 + lr];
+      for (int ib = 0; ib < NBR; ++ib)
+        a[u][ib] = kk < brows ? (double)C[(int64_t)kk * ld + 16 * ib + lr] : 0.0;
+      b[u][0] = kk < brows ? (double)W[(int64_t)kk * T + 16 * g0 + lr] : 0.0;
+      b[u][1] = kk < brows ? (double)W[(int64_t)kk * T + 16 * g1 + lr] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -970,7 +1097,7 @@ __device__ __forceinline__ void dev_trsm_border(const Lay& lay, double* base, co
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int c = cb + MF<double>::col(lk, e);
-        if (c < brows) C[(int64_t)c * ld + r] = acc[ib][h][e];
+        if (c < brows) C[(int64_t)c * ld + r] = (TS)acc[ib][h][e];
       }
     }
   }
@@ -979,10 +1106,9 @@ __device__ __forceinline__ void dev_trsm_border(const Lay& lay, double* base, co
 // Panel solve of tile (I, J), I > J: L_IJ = C_IJ W^T with W = L_JJ^-1 (ld T).
 // The FP64 two-set pipeline (step kernels) uses the TRI column map; the FP32
 // form skips the chunks its first wave column does not need (HALF); the
-// persistent batch kernel's one-set pipeline keeps the plain halves.
-// DMA32: the FP32 form of whole packed tiles (I < Nv) takes the direct-to-LDS
-// core (lds of at least F32_DMA_LDS_BYTES).
-template <typename TS, bool VEC, int FLUSH, int DEPTH = 2, bool DMA32 = false>
+// persistent batch kernel's one-set pipeline keeps the plain halves.  The
+// mixed form's whole packed tiles take dev_trsm_mx_dma instead.
+template <typename TS, bool VEC, int FLUSH, int DEPTH = 2>
 __device__ __forceinline__ void dev_trsm(const Lay& lay, TS* base, const TS* W, int J, int I, TS* lds) {
   constexpr bool TRI = sizeof(TS) == 8 && DEPTH > 1;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -998,8 +1124,6 @@ __device__ __forceinline__ void dev_trsm(const Lay& lay, TS* base, const TS* W, 
   // the core's final barrier orders every read of C_IJ before the overwrite
   if constexpr (sizeof(TS) == 8) {
     wg_gemm_nt<TS, TS, VEC, 4, DEPTH, TRI>(acc, lds, Ct, ldc, arows, W, T, brows, brows, act, ni);
-  } else if (DMA32 && lay.kind == 0 && I < lay.Nv) {
-    wg_gemm_nt_f32x64_dma<FLUSH, true>(acc, lds, Ct, W, T, act, ni);
   } else {
     wg_gemm_nt_f32x64<FLUSH, true>(acc, lds, Ct, ldc, arows, W, T, brows, brows, act, ni);
   }

@@ -139,3 +139,21 @@ def test_mixed_tall_border_matches_oracle(plprof_lib, n, p, K, M, seed):
     assert dll.max() <= TOL_LL
     assert np.abs(got["loglik_reml"] - ref["loglik_reml"]).max() <= TOL_LL
     np.testing.assert_allclose(got["beta"], refb, rtol=0, atol=1e-3 * max(1.0, np.abs(refb).max()))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_workspace_contents_do_not_leak_into_results(plprof_lib, precision):
+    """The padding of the last block column (rows past n) is never read as
+    data: a workspace filled with all-ones bytes (NaN in FP32 and FP64) gives
+    the same records, bit for bit, as one filled with zeros."""
+    pl = plprof_lib
+    pr = synth.small_problem(300, p=2, K=3, M=2, seed=77, aniso=True)
+    size = pl.workspace_size(300, 2, 3, 2, precision, 0)
+    print(f"workspace fill: {precision}, n = 300, {size} bytes", flush=True)
+    recs = []
+    for fill in (0, 255):
+        work = torch.full((size,), fill, dtype=torch.uint8, device="cuda")
+        recs.append(_run(pl, pr, precision=precision, work=work))
+    for key in ("loglik", "loglik_reml", "logdet_v", "info", "beta"):
+        np.testing.assert_array_equal(recs[0][key], recs[1][key], err_msg=key)
+    assert np.all(np.isfinite(recs[0]["loglik"]))
