@@ -58,7 +58,8 @@ __global__ void k_cheb_coeffs(const double* __restrict__ nodes, double* __restri
 
 // Chebyshev coefficients c_0 .. c_{NC-1} of one piece (c_0 already halved)
 // -> power-basis coefficients a_j of sum_m c_m T_m(s), in place, through the
-// integer coefficients of T_m (T_{m+1} = 2 s T_m - T_{m-1}).
+// integer coefficients of T_m (T_{m+1} = 2 s T_m - T_{m-1}); stored as
+// a_j 8^j, the coefficients in s / 8 (exact: a power of two).
 __global__ void k_cheb_mono(double* __restrict__ tables, int K) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)K * NPIECE) return;
@@ -87,7 +88,7 @@ __global__ void k_cheb_mono(double* __restrict__ tables, int K) {
     }
   }
 #pragma unroll
-  for (int j = 0; j < NC; ++j) c[j] = a[j];
+  for (int j = 0; j < NC; ++j) c[j] = ldexp(a[j], 3 * j);
 }
 
 hipError_t launch_cheb_tables(const MaternParams* mp, double* nodes, double* tables, int K,

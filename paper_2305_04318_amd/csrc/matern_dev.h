@@ -49,11 +49,13 @@ static __device__ double g_direct(const MaternParams& P, double w) {
 // rho for one element given w = 8 kappa d^2 (d the anisotropic distance) and
 // the omega's table (TABLE doubles, 16-byte aligned: per piece, the
 // power-basis coefficients of the Chebyshev interpolant of rho itself in the
-// local variable s).  For w >= 2^W_E_LO, a normal double, the piece is the
-// binary exponent and the top two mantissa bits of w (PB = 4 pieces per
-// binade) and s the remaining mantissa bits, read off its bit pattern (no
-// logarithm); the value is a Horner sum clamped to [0, 1] (no exp).
-__device__ __forceinline__ double rho_eval(const MaternParams& P, const double* tab, double w) {
+// local variable s, the coefficient of s^m scaled by 8^-m).  For w >= 2^W_E_LO,
+// a normal double, the piece is the binary exponent and the top two mantissa
+// bits of w (PB = 4 pieces per binade) and s the remaining mantissa bits,
+// read off its bit pattern (no logarithm); the value is a Horner sum in s / 8
+// clamped to [0, 1] (no exp).  w_hi: the omega's underflow point (P.w_hi).
+__device__ __forceinline__ double rho_eval(const MaternParams& P, const double* tab, double w,
+                                           double w_hi) {
   static_assert(PB == 4 && NC % 2 == 0, "two mantissa bits per piece; coefficient pairs");
   if (w < 0x1p-20) {  // 2^W_E_LO; w = 0: coincident locations
     if (w == 0.0) return 1.0;
@@ -66,13 +68,18 @@ __device__ __forceinline__ double rho_eval(const MaternParams& P, const double* 
   // included, which the final test maps to 0)
   int piece = (hi >> 18) - ((1023 + W_E_LO) << 2);
   piece = max(0, min(piece, NPIECE - 1));
+  // the piece's byte offset, opaque to the compiler: otherwise it folds the
+  // bias above into five separate address constants instead of one base
+  // address with the five reads' immediate offsets
+  int off = piece * (NC * 8);
+  asm volatile("" : "+v"(off));
   // the other 50 mantissa bits under exponent 0: v = 1 + f / 4 with f the
-  // position in the piece, in [0, 1); s = 2 f - 1 = 8 v - 9, exact
+  // position in the piece, in [0, 1); s / 8 = v - 9 / 8 in [-1/8, 1/8), exact
   const double v = __longlong_as_double((long long)(((unsigned long long)((hi & 0x3FFFF) | 0x3FF00000) << 32) |
                                                     (unsigned long long)(u & 0xffffffffLL)));
-  const double s = fma(8.0, v, -9.0);
+  const double s8 = v - 1.125;
   typedef double pair __attribute__((ext_vector_type(2)));
-  const pair* a2 = reinterpret_cast<const pair*>(tab + piece * NC);
+  const pair* a2 = reinterpret_cast<const pair*>(reinterpret_cast<const char*>(tab) + off);
   double a[NC];
 #pragma unroll
   for (int q = 0; q < NC / 2; ++q) {
@@ -82,9 +89,9 @@ __device__ __forceinline__ double rho_eval(const MaternParams& P, const double* 
   }
   double r = a[NC - 1];
 #pragma unroll
-  for (int mm = NC - 2; mm >= 0; --mm) r = fma(r, s, a[mm]);
+  for (int mm = NC - 2; mm >= 0; --mm) r = fma(r, s8, a[mm]);
   r = fmin(fmax(r, 0.0), 1.0);
-  return w < P.w_hi ? r : 0.0;
+  return w < w_hi ? r : 0.0;
 }
 
 // ---- covariance tiles -----------------------------------------------------
@@ -111,17 +118,19 @@ __device__ __forceinline__ void matern_tile(const MaternParams& P, const double*
   const double sk = sqrt(P.k8);
   const double m11 = sk * P.inv_phix * P.cosA, m12 = -sk * P.inv_phix * P.sinA;
   const double m21 = sk * P.inv_phiy * P.sinA, m22 = sk * P.inv_phiy * P.cosA;
+  // read once: the stores below may alias P as far as the compiler knows
+  const double w_hi = P.w_hi, vdiag = 1.0 + P.nugget;
   for (int c = hh; c < cmax; c += 2) {
     const int gj = J * T + c;
     if ((MODE == 1 || MODE == 3) && gj > gi) continue;
     double v;
     if (gi == gj) {
-      v = 1.0 + P.nugget;
+      v = vdiag;
     } else {
       const double dx = xi - cx[c], dy = yi - cy[c];
       const double u1 = fma(m12, dy, m11 * dx);
       const double u2 = fma(m22, dy, m21 * dx);
-      v = rho_eval(P, tab, fma(u1, u1, u2 * u2));
+      v = rho_eval(P, tab, fma(u1, u1, u2 * u2), w_hi);
     }
     if (MODE != 3) C[(int64_t)c * ldc + r] = v;
     if (MODE == 2 || MODE == 3) C32[(int64_t)c * ldc + r] = (float)v;

@@ -84,12 +84,16 @@ constexpr int GEMM_LDS_BYTES = 2 * 2 * 16 * LROW * 8;
 
 // TRI (the panel solve C W^T, W lower triangular): output block column g
 // (16 columns) needs only k < 16 (g + 1).  Wave column wc owns the block
-// columns tri_blk(wc, 0..3) = {0, 1, 6, 7} or {2, 3, 4, 5}, 18 nonzero
+// columns tri_blk(wc, 0..3) = {0, 3, 4, 7} or {1, 2, 5, 6}, 18 nonzero
 // 16 x 16 x 16 products each, instead of the halves {0..3} and {4..7} (10
-// and 26).  tri_blk grows with j, so the blocks that still need the k from k0
-// on are j >= tri_lo(wc, k0): one scalar branch per MFMA.  Blocks at or
-// beyond brows multiply the zero rows of B and are not stored.
-__device__ __forceinline__ int tri_blk(int wc, int j) { return wc ? j + 2 : (j < 2 ? j : j + 4); }
+// and 26); per k block m the two columns have 4/4, 3/4, 3/3, 3/2, 2/2, 1/2,
+// 1/1, 1/0 blocks still running, so a chunk's barrier waits for at most one
+// block more on either side.  tri_blk grows with j, so the blocks that still
+// need the k from k0 on are j >= tri_lo(wc, k0): one scalar branch per MFMA.
+// Blocks at or beyond brows multiply the zero rows of B and are not stored.
+__device__ __forceinline__ int tri_blk(int wc, int j) {
+  return wc ? (j < 2 ? j + 1 : j + 3) : (j < 2 ? 3 * j : 3 * j - 2);
+}
 
 __device__ __forceinline__ int tri_lo(int wc, int k0) {
   int jlo = 4;
