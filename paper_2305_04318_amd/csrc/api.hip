@@ -191,8 +191,8 @@ hipError_t plk::run_pass(const PassArgs& a, const PassBufs& b, int kk, hipStream
   if (e != hipSuccess) return e;
   e = timed(PL_KC_MATERN, 0.0, s, [&] {
     return a.mixed ? launch_matern_mixed(lay, b.m64, v_stride64(lay), b.m32, a.locs, a.mp,
-                                         a.tables, kk, s)
-                   : launch_matern_packed(lay, b.mats, a.locs, a.mp, a.tables, kk, s);
+                                         a.tables, kk, s, a.flag_ws)
+                   : launch_matern_packed(lay, b.mats, a.locs, a.mp, a.tables, kk, s, a.flag_ws);
   });
   if (e != hipSuccess) return e;
   if (!a.mixed) {
@@ -520,6 +520,7 @@ int pl_profile_loglik(const double* locs, const double* y, const double* X, int6
     const int kk = (int)std::min<int64_t>(kc, K - c0);
     pa.mp = mp + c0;
     pa.tables = tables + c0 * TABLE;
+    pa.flag_ws = reinterpret_cast<uint8_t*>(nodes + c0 * TABLE);
     pa.out = out + c0 * M;
     pa.beta = beta_hat ? beta_hat + c0 * M * p : nullptr;
     pa.xvx = xvx_inv ? xvx_inv + c0 * p * p : nullptr;

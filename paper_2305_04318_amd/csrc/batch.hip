@@ -733,6 +733,7 @@ hipError_t capture_bucketed(pl_batch* b, char* w, pl_result* out, double* beta_h
     pa.lay.units = ui + ps.u0;
     pa.mp = mp + ps.u0;
     pa.tables = tables + (int64_t)ps.u0 * TABLE;
+    pa.flag_ws = reinterpret_cast<uint8_t*>(w + b->off_nodes) + (size_t)ps.u0 * TABLE * sizeof(double);
     pa.info_out = info + ps.u0;
     const PassBufs pb = carve_pass(w + b->off_lanes + (size_t)ps.lane * b->region, pa.lay,
                                    b->mixed, ps.cnt);

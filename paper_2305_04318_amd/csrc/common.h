@@ -114,9 +114,12 @@ hipError_t stage_h2d(void* dst, const void* src, size_t bytes, hipStream_t s);
 // ---- launch wrappers (defined in the .hip files) --------------------------
 hipError_t launch_cheb_tables(const MaternParams* mp, double* nodes, double* tables,
                               int K, hipStream_t s);
+// flag_ws: scratch of at least 4 bytes per tile per omega (the pass's table
+// nodes, dead once the tables are built), or null; with it the elements that
+// need the quadrature go to a second, short launch (see matern.hip)
 hipError_t launch_matern_packed(const Lay& lay, double* mats, const double* locs,
                                 const MaternParams* mp, const double* tables, int K,
-                                hipStream_t s);
+                                hipStream_t s, uint8_t* flag_ws = nullptr);
 hipError_t launch_matern_colmajor(double* V, int64_t ld, int n, const double* locs,
                                   const MaternParams* mp, const double* tables, int K,
                                   hipStream_t s);
@@ -153,7 +156,7 @@ hipError_t launch_finalize(const Lay& lay, const double* mats, const double* sre
 // mixed form
 hipError_t launch_matern_mixed(const Lay& lay, double* m64, int64_t stride64, float* m32,
                                const double* locs, const MaternParams* mp, const double* tables,
-                               int K, hipStream_t s);
+                               int K, hipStream_t s, uint8_t* flag_ws = nullptr);
 hipError_t launch_border_init_f32(const Lay& lay, float* mats, const double* rhs, int K,
                                   hipStream_t s);
 constexpr int MX_FLUSH = 4;  // default FP32 MFMA k-steps per FP64 fold of the mixed update
@@ -205,6 +208,7 @@ struct PassArgs {
   const double* rhs;             // its Box-Cox right-hand sides (n x TB)
   const MaternParams* mp;        // this pass's omega constants and tables
   const double* tables;
+  uint8_t* flag_ws;              // the pass's table nodes, reused by the covariance build, or null
   const double* jac;
   const int32_t* yflags;
   const double* lam;             // device, M values

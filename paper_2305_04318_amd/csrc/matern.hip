@@ -103,48 +103,112 @@ hipError_t launch_cheb_tables(const MaternParams* mp, double* nodes, double* tab
   return hipGetLastError();
 }
 
-template <int MODE>
+// Lower tile t of the packed order (row-major over I, then J <= I).
+__device__ __forceinline__ void tile_of(int t, int& I, int& J) {
+  I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while (I * (I + 1) / 2 > t) --I;
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  J = t - I * (I + 1) / 2;
+}
+
+// SPLIT: flags holds 4 bytes per tile (one per wave; see matern_tile).
+template <int MODE, bool SPLIT = false>
 __global__ __launch_bounds__(256) void k_matern(Lay lay, double* __restrict__ mats,
                                                 int64_t stride64, float* __restrict__ m32,
                                                 int64_t stride32,
                                                 const double* __restrict__ locs,
                                                 const MaternParams* __restrict__ mp,
                                                 const double* __restrict__ tables, int ntiles,
-                                                int G) {
+                                                int G, uint8_t* __restrict__ flags) {
   __shared__ __attribute__((aligned(16))) double smem[TABLE + 2 * T];
   const int wg = xcd_remap(blockIdx.x, G);
   const int k = wg / ntiles;
   const int t = wg % ntiles;
-  int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-  while (I * (I + 1) / 2 > t) --I;
-  while ((I + 1) * (I + 2) / 2 <= t) ++I;
-  const int J = t - I * (I + 1) / 2;
+  int I, J;
+  tile_of(t, I, J);
   const int64_t off = lay.tile_off(I, J);
   double* C = (MODE != 3) ? mats + (int64_t)k * stride64 + off : nullptr;
   float* C32 = (MODE == 2 || MODE == 3) ? m32 + (int64_t)k * stride32 + off : nullptr;
   // an uneven batch: the unit's own order and locations
   const double* lk = lay.units ? lay.units[k].locs : locs;
-  dev_matern_tile<MODE>(lay_of(lay, k), mp[k], tables + (int64_t)k * TABLE, lk, I, J, C,
-                        lay.tile_ld(I), C32, smem);
+  dev_matern_tile<MODE, SPLIT>(lay_of(lay, k), mp[k], tables + (int64_t)k * TABLE, lk, I, J, C,
+                               lay.tile_ld(I), C32, smem,
+                               SPLIT ? flags + ((int64_t)k * ntiles + t) * 4 : nullptr);
+}
+
+// After k_matern<MODE, true>: one workgroup per omega walks its tiles' flags
+// (staged through LDS 256 at a time) and computes, in the flagged tiles, the
+// elements left to the quadrature (pairs within about 1e-3 of the range:
+// a few tiles per omega at most in practice).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_matern_quad(Lay lay, double* __restrict__ mats,
+                                                     int64_t stride64, float* __restrict__ m32,
+                                                     int64_t stride32,
+                                                     const double* __restrict__ locs,
+                                                     const MaternParams* __restrict__ mp,
+                                                     const uint8_t* __restrict__ flags,
+                                                     int ntiles) {
+  __shared__ uint32_t fl[256];
+  const int k = blockIdx.x;
+  const Lay L = lay_of(lay, k);
+  const double* lk = lay.units ? lay.units[k].locs : locs;
+  const uint32_t* f = reinterpret_cast<const uint32_t*>(flags) + (int64_t)k * ntiles;
+  for (int t0 = 0; t0 < ntiles; t0 += 256) {
+    __syncthreads();  // the previous block of flags is read
+    fl[threadIdx.x] = t0 + (int)threadIdx.x < ntiles ? f[t0 + threadIdx.x] : 0u;
+    __syncthreads();
+    const int nb = min(256, ntiles - t0);
+    for (int i = 0; i < nb; ++i) {
+      if (fl[i] == 0u) continue;  // uniform: every lane reads the same word
+      int I, J;
+      tile_of(t0 + i, I, J);
+      const int64_t off = lay.tile_off(I, J);
+      double* C = mats + (int64_t)k * stride64 + off;
+      float* C32 = MODE == 2 ? m32 + (int64_t)k * stride32 + off : nullptr;
+      matern_tile_quad<MODE>(mp[k], lk, L.n, I, J, C, lay.tile_ld(I), C32);
+    }
+  }
+}
+
+// The split build needs 4 bytes per tile per omega of flag_ws (the table
+// nodes' TABLE doubles per omega); without it, or past that, the one-launch
+// form with the quadrature inline.
+static bool split_ok(int ntiles, const uint8_t* flag_ws) {
+  return flag_ws != nullptr && (reinterpret_cast<uintptr_t>(flag_ws) & 3) == 0 &&
+         (int64_t)ntiles * 4 <= (int64_t)TABLE * (int64_t)sizeof(double);
 }
 
 hipError_t launch_matern_packed(const Lay& lay, double* mats, const double* locs,
                                 const MaternParams* mp, const double* tables, int K,
-                                hipStream_t s) {
+                                hipStream_t s, uint8_t* flag_ws) {
   const int ntiles = lay.Nv * (lay.Nv + 1) / 2;
   const int G = K * ntiles;
-  hipLaunchKernelGGL(k_matern<0>, dim3(G), dim3(256), 0, s, lay, mats, lay.mstride, (float*)nullptr,
-                     (int64_t)0, locs, mp, tables, ntiles, G);
+  if (split_ok(ntiles, flag_ws)) {
+    hipLaunchKernelGGL((k_matern<0, true>), dim3(G), dim3(256), 0, s, lay, mats, lay.mstride,
+                       (float*)nullptr, (int64_t)0, locs, mp, tables, ntiles, G, flag_ws);
+    hipLaunchKernelGGL(k_matern_quad<0>, dim3(K), dim3(256), 0, s, lay, mats, lay.mstride,
+                       (float*)nullptr, (int64_t)0, locs, mp, flag_ws, ntiles);
+  } else {
+    hipLaunchKernelGGL((k_matern<0, false>), dim3(G), dim3(256), 0, s, lay, mats, lay.mstride,
+                       (float*)nullptr, (int64_t)0, locs, mp, tables, ntiles, G, (uint8_t*)nullptr);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_matern_mixed(const Lay& lay, double* m64, int64_t stride64, float* m32,
                                const double* locs, const MaternParams* mp, const double* tables,
-                               int K, hipStream_t s) {
+                               int K, hipStream_t s, uint8_t* flag_ws) {
   const int ntiles = lay.Nv * (lay.Nv + 1) / 2;
   const int G = K * ntiles;
-  hipLaunchKernelGGL(k_matern<2>, dim3(G), dim3(256), 0, s, lay, m64, stride64, m32, lay.mstride,
-                     locs, mp, tables, ntiles, G);
+  if (split_ok(ntiles, flag_ws)) {
+    hipLaunchKernelGGL((k_matern<2, true>), dim3(G), dim3(256), 0, s, lay, m64, stride64, m32,
+                       lay.mstride, locs, mp, tables, ntiles, G, flag_ws);
+    hipLaunchKernelGGL(k_matern_quad<2>, dim3(K), dim3(256), 0, s, lay, m64, stride64, m32,
+                       lay.mstride, locs, mp, flag_ws, ntiles);
+  } else {
+    hipLaunchKernelGGL((k_matern<2, false>), dim3(G), dim3(256), 0, s, lay, m64, stride64, m32,
+                       lay.mstride, locs, mp, tables, ntiles, G, (uint8_t*)nullptr);
+  }
   return hipGetLastError();
 }
 
@@ -159,8 +223,8 @@ hipError_t launch_matern_colmajor(double* V, int64_t ld, int n, const double* lo
   lay.mstride = ld * (int64_t)n;
   const int ntiles = lay.Nv * (lay.Nv + 1) / 2;
   const int G = K * ntiles;
-  hipLaunchKernelGGL(k_matern<1>, dim3(G), dim3(256), 0, s, lay, V, lay.mstride, (float*)nullptr,
-                     (int64_t)0, locs, mp, tables, ntiles, G);
+  hipLaunchKernelGGL((k_matern<1, false>), dim3(G), dim3(256), 0, s, lay, V, lay.mstride,
+                     (float*)nullptr, (int64_t)0, locs, mp, tables, ntiles, G, (uint8_t*)nullptr);
   return hipGetLastError();
 }
 
@@ -176,8 +240,8 @@ hipError_t launch_matern_colmajor_f32(float* V, int64_t ld, int n, const double*
   lay.mstride = ld * (int64_t)n;
   const int ntiles = lay.Nv * (lay.Nv + 1) / 2;
   const int G = K * ntiles;
-  hipLaunchKernelGGL(k_matern<3>, dim3(G), dim3(256), 0, s, lay, (double*)nullptr, (int64_t)0, V,
-                     lay.mstride, locs, mp, tables, ntiles, G);
+  hipLaunchKernelGGL((k_matern<3, false>), dim3(G), dim3(256), 0, s, lay, (double*)nullptr,
+                     (int64_t)0, V, lay.mstride, locs, mp, tables, ntiles, G, (uint8_t*)nullptr);
   return hipGetLastError();
 }
 

@@ -54,13 +54,17 @@ static __device__ double g_direct(const MaternParams& P, double w) {
 // bits of w (PB = 4 pieces per binade) and s the remaining mantissa bits,
 // read off its bit pattern (no logarithm); the value is a Horner sum in s / 8
 // clamped to [0, 1] (no exp).  w_hi: the omega's underflow point (P.w_hi).
-__device__ __forceinline__ double rho_eval(const MaternParams& P, const double* tab, double w,
-                                           double w_hi) {
+// rho_table covers w >= 2^W_E_LO (RHO_W_LO), rho_small the rest.
+constexpr double RHO_W_LO = 0x1p-20;
+
+// rho for 0 <= w < 2^W_E_LO: 1 at w = 0 (coincident locations), else the
+// quadrature directly.
+__device__ __forceinline__ double rho_small(const MaternParams& P, double w) {
+  return w == 0.0 ? 1.0 : fmin(exp(g_direct(P, w)), 1.0);
+}
+
+__device__ __forceinline__ double rho_table(const double* tab, double w, double w_hi) {
   static_assert(PB == 4 && NC % 2 == 0, "two mantissa bits per piece; coefficient pairs");
-  if (w < 0x1p-20) {  // 2^W_E_LO; w = 0: coincident locations
-    if (w == 0.0) return 1.0;
-    return fmin(exp(g_direct(P, w)), 1.0);
-  }
   const long long u = __double_as_longlong(w);
   const int hi = (int)(u >> 32);
   // exponent and top two mantissa bits, relative to 2^W_E_LO; the clamp
@@ -94,6 +98,14 @@ __device__ __forceinline__ double rho_eval(const MaternParams& P, const double* 
   return w < w_hi ? r : 0.0;
 }
 
+// Whether w takes the quadrature (NaN does not: the table path maps it to 0).
+__device__ __forceinline__ bool rho_needs_quad(double w) { return w < RHO_W_LO && w != 0.0; }
+
+__device__ __forceinline__ double rho_eval(const MaternParams& P, const double* tab, double w,
+                                           double w_hi) {
+  return w < RHO_W_LO ? rho_small(P, w) : rho_table(tab, w, w_hi);
+}
+
 // ---- covariance tiles -----------------------------------------------------
 // One workgroup per (omega, lower tile (I,J)).  Column coordinates and the
 // omega's table are staged in LDS; thread (r, h) owns row r of the tile and
@@ -102,36 +114,91 @@ __device__ __forceinline__ double rho_eval(const MaternParams& P, const double* 
 // MODE 0: packed FP64 tiles (full diagonal tiles); MODE 1: column-major,
 // lower triangle only; MODE 2: packed FP64 tiles plus an FP32 copy; MODE 3:
 // column-major, lower triangle only, FP32 only (C32; C is not written).
-template <int MODE>
+// SPLIT: the elements that need the quadrature (rho_needs_quad) are stored as
+// 0 and left to matern_tile_quad; each wave writes flags[wave] = whether it
+// left any.  The quadrature's call holds more than twice the registers of
+// the table path, so keeping it out of this loop doubles the resident waves.
+
+// w = 8 kappa d^2 = |M (dx, dy)|^2: rotation by phi_A, the two range scales
+// and sqrt(8 kappa) in one 2 x 2 map (m11, m12, m21, m22)
+struct WMap {
+  double m11, m12, m21, m22;
+  __device__ __forceinline__ explicit WMap(const MaternParams& P) {
+    const double sk = sqrt(P.k8);
+    m11 = sk * P.inv_phix * P.cosA;
+    m12 = -sk * P.inv_phix * P.sinA;
+    m21 = sk * P.inv_phiy * P.sinA;
+    m22 = sk * P.inv_phiy * P.cosA;
+  }
+  __device__ __forceinline__ double w(double xi, double yi, double xj, double yj) const {
+    const double dx = xi - xj, dy = yi - yj;
+    const double u1 = fma(m12, dy, m11 * dx);
+    const double u2 = fma(m22, dy, m21 * dx);
+    return fma(u1, u1, u2 * u2);
+  }
+};
+
+template <int MODE, bool SPLIT = false>
 __device__ __forceinline__ void matern_tile(const MaternParams& P, const double* tab,
                                             const double* __restrict__ locs, int n, int I, int J,
                                             double* C, int64_t ldc, float* C32, const double* cx,
-                                            const double* cy) {
+                                            const double* cy, uint8_t* flags = nullptr) {
+  const int r = threadIdx.x & (T - 1);
+  const int hh = threadIdx.x >> 7;
+  const int gi = I * T + r;
+  bool quad = false;  // SPLIT: an element of this lane left to the quadrature launch
+  if (gi < n) {
+    const double xi = locs[2 * gi], yi = locs[2 * gi + 1];
+    const int cmax = min(T, n - J * T);
+    const WMap M(P);
+    // read once: the stores below may alias P as far as the compiler knows
+    const double w_hi = P.w_hi, vdiag = 1.0 + P.nugget;
+    for (int c = hh; c < cmax; c += 2) {
+      const int gj = J * T + c;
+      if ((MODE == 1 || MODE == 3) && gj > gi) continue;
+      double v;
+      if (gi == gj) {
+        v = vdiag;
+      } else {
+        const double w = M.w(xi, yi, cx[c], cy[c]);
+        if constexpr (SPLIT) {
+          const bool q = rho_needs_quad(w);
+          quad |= q;
+          v = q ? 0.0 : (w == 0.0 ? 1.0 : rho_table(tab, w, w_hi));
+        } else {
+          v = rho_eval(P, tab, w, w_hi);
+        }
+      }
+      if (MODE != 3) C[(int64_t)c * ldc + r] = v;
+      if (MODE == 2 || MODE == 3) C32[(int64_t)c * ldc + r] = (float)v;
+    }
+  }
+  if constexpr (SPLIT) {
+    const bool any = __any(quad);
+    if ((threadIdx.x & 63) == 0) flags[threadIdx.x >> 6] = any ? 1 : 0;
+  }
+}
+
+// The elements of tile (I, J) that matern_tile<MODE, true> left to the
+// quadrature: the same w, bit for bit (same map, same coordinates), then
+// rho_small.  Coordinates straight from global memory (few tiles get here).
+template <int MODE>
+__device__ __forceinline__ void matern_tile_quad(const MaternParams& P,
+                                                 const double* __restrict__ locs, int n, int I,
+                                                 int J, double* C, int64_t ldc, float* C32) {
   const int r = threadIdx.x & (T - 1);
   const int hh = threadIdx.x >> 7;
   const int gi = I * T + r;
   if (gi >= n) return;
   const double xi = locs[2 * gi], yi = locs[2 * gi + 1];
   const int cmax = min(T, n - J * T);
-  // w = 8 kappa d^2 = |M (dx, dy)|^2: rotation by phi_A, the two range
-  // scales and sqrt(8 kappa) in one 2 x 2 map
-  const double sk = sqrt(P.k8);
-  const double m11 = sk * P.inv_phix * P.cosA, m12 = -sk * P.inv_phix * P.sinA;
-  const double m21 = sk * P.inv_phiy * P.sinA, m22 = sk * P.inv_phiy * P.cosA;
-  // read once: the stores below may alias P as far as the compiler knows
-  const double w_hi = P.w_hi, vdiag = 1.0 + P.nugget;
+  const WMap M(P);
   for (int c = hh; c < cmax; c += 2) {
     const int gj = J * T + c;
-    if ((MODE == 1 || MODE == 3) && gj > gi) continue;
-    double v;
-    if (gi == gj) {
-      v = vdiag;
-    } else {
-      const double dx = xi - cx[c], dy = yi - cy[c];
-      const double u1 = fma(m12, dy, m11 * dx);
-      const double u2 = fma(m22, dy, m21 * dx);
-      v = rho_eval(P, tab, fma(u1, u1, u2 * u2), w_hi);
-    }
+    if (gj == gi || ((MODE == 1 || MODE == 3) && gj > gi)) continue;
+    const double w = M.w(xi, yi, locs[2 * gj], locs[2 * gj + 1]);
+    if (!rho_needs_quad(w)) continue;
+    const double v = rho_small(P, w);
     if (MODE != 3) C[(int64_t)c * ldc + r] = v;
     if (MODE == 2 || MODE == 3) C32[(int64_t)c * ldc + r] = (float)v;
   }
@@ -140,11 +207,12 @@ __device__ __forceinline__ void matern_tile(const MaternParams& P, const double*
 // One T x T tile (I, J) of V for one omega: the omega's table and the tile's
 // column coordinates are staged in smem (TABLE + 2T doubles).  C points at the
 // tile (leading dimension ldc); MODE 2 also writes C32, MODE 3 only C32.
-template <int MODE>
+template <int MODE, bool SPLIT = false>
 __device__ __forceinline__ void dev_matern_tile(const Lay& lay, const MaternParams& P,
                                                 const double* __restrict__ tab_g,
                                                 const double* __restrict__ locs, int I, int J,
-                                                double* C, int64_t ldc, float* C32, double* smem) {
+                                                double* C, int64_t ldc, float* C32, double* smem,
+                                                uint8_t* flags = nullptr) {
   double* tab = smem;
   double* cx = smem + TABLE;
   double* cy = cx + T;
@@ -155,7 +223,7 @@ __device__ __forceinline__ void dev_matern_tile(const Lay& lay, const MaternPara
     cy[i] = gj < lay.n ? locs[2 * gj + 1] : 0.0;
   }
   __syncthreads();
-  matern_tile<MODE>(P, tab, locs, lay.n, I, J, C, ldc, C32, cx, cy);
+  matern_tile<MODE, SPLIT>(P, tab, locs, lay.n, I, J, C, ldc, C32, cx, cy, flags);
 }
 
 }  // namespace plk

@@ -4,6 +4,7 @@ Tolerances: covariance elements 1e-12 absolute (rho <= 1; the oracle's own
 Bessel route is good to ~1e-13); log|V| and l_p within
 1e-8 * max(|l_p|, n) (the FP64 criterion for this path); beta-hat within
 1e-7 relative to max(1, |beta|)."""
+import dataclasses
 import math
 
 import numpy as np
@@ -158,3 +159,27 @@ def test_bad_y_flags_every_record(plprof_lib):
     torch.cuda.synchronize()
     assert np.all(got["info"].cpu().numpy() == pl.PL_INFO_BAD_Y)
     assert np.all(np.isnan(got["loglik"].cpu().numpy()))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_profile_close_pairs_take_the_quadrature(plprof_lib, precision):
+    """Pairs closer than the tables' lower end (w < 2^-20), spread over
+    several tiles of the packed build, one exact duplicate among them: their
+    elements come from the build's quadrature launch (or are 1), and the
+    records match the oracle."""
+    pl = plprof_lib
+    pr = synth.small_problem(300, p=2, K=3, M=2, seed=21, aniso=True)
+    rng = np.random.default_rng(21)
+    idx = rng.permutation(300)[:24]
+    locs = pr.locs.copy()
+    locs[idx[12:]] = locs[idx[:12]] + rng.uniform(-1e-6, 1e-6, (12, 2))
+    locs[idx[23]] = locs[idx[11]]
+    pr = dataclasses.replace(pr, locs=locs)
+    print(f"close pairs: {precision}, n = 300, 12 pairs", flush=True)
+    got = _gpu(pl, pr, precision=precision)
+    ref, refb = oracle.profile_loglik(pr.locs, pr.y, pr.X, pr.omega, pr.lam, return_beta=True)
+    if precision == "fp64":
+        _check(got, ref, refb, pr.n)
+    else:
+        assert np.all((got["info"] & ~pl.PL_INFO_FALLBACK) == 0)
+        assert np.max(np.abs(got["loglik"] - ref["loglik"])) <= 1e-2
